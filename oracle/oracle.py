@@ -232,6 +232,9 @@ def _pow2ceil(x: int) -> int:
 def rule_p(h: Sequence[int], S: int, rmax: int, T: int = 24) -> List[int]:
     """Rule P: a pattern from a past histogram h (our reading; the paper gives no rule).
 
+    0. If the budget holds rmax sub-bins for every value (256 * rmax <= S), every
+       value gets rmax: the pattern exists to share a limited sub-histogram
+       (Sec. III.A), and with room for all there is nothing to share.
     1. N = sum h.  N = 0 -> every r = 1.
     2. For t = 0..T' (T' = min(T, 64 - bitlen(N)), so h * 2**t stays below 2**64):
        r_t[b] = min(rmax, pow2ceil(max(1, ceil(h[b] * 2**t / N)))).
@@ -246,7 +249,9 @@ def rule_p(h: Sequence[int], S: int, rmax: int, T: int = 24) -> List[int]:
     if S < 256 or rmax < 1 or rmax & (rmax - 1):
         raise ValueError("need S >= 256 and rmax a power of two")
     N = sum(h)
-    if N == 0:
+    if 256 * rmax <= S:
+        r = [rmax] * 256
+    elif N == 0:
         r = [1] * 256
     else:
         tmax = min(T, 64 - N.bit_length())

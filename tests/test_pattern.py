@@ -86,7 +86,7 @@ def test_validity_rejects():
 # ---------------------------------------------------------------- rule P closed forms
 
 @pytest.mark.parametrize("v", [0, 1, 127, 200, 255])
-@pytest.mark.parametrize("S,rmax", [(960, 8), (8192, 32), (4096, 16)])
+@pytest.mark.parametrize("S,rmax", [(960, 8), (4096, 32), (2048, 64), (300, 16)])
 def test_rule_p_one_hot(v, S, rmax):
     h = [0] * 256
     h[v] = 12345
@@ -105,9 +105,21 @@ def test_rule_p_flat_gives_two():
     assert bases(w) == [2 * b for b in range(256)]
 
 
-def test_rule_p_flat_large_budget():
-    w = O.rule_p([7] * 256, 8192, 32)
-    assert rs(w) == [32] * 256
+@pytest.mark.parametrize("S,rmax", [(8192, 32), (16384, 64), (4096, 16), (256, 1), (9000, 32)])
+def test_rule_p_saturated_budget(S, rmax):
+    # 256 * rmax <= S: every value gets rmax whatever the histogram, laid out in value order
+    for h in ([7] * 256, [0] * 256, [0] * 255 + [99]):
+        w = O.rule_p(h, S, rmax)
+        assert rs(w) == [rmax] * 256
+        assert bases(w) == [rmax * b for b in range(256)]
+
+
+def test_rule_p_just_below_saturation():
+    # S = 256 * 32 - 1: the empty values keep one sub-bin, the rest reach rmax
+    h = [5] * 200 + [0] * 56
+    w = O.rule_p(h, 8191, 32)
+    r = rs(w)
+    assert r[:200] == [32] * 200 and r[200:] == [1] * 56
 
 
 def test_rule_p_two_spike():
