@@ -1,0 +1,308 @@
+/*
+ * histmi -- exact 256-bin histograms of packed 8-bit pixel streams on MI355X (gfx950).
+ *
+ * C ABI of libhistmi.so.  The operations follow Koppaka et al., "Fast Histograms
+ * using Adaptive CUDA Streams" (2010):
+ *   - the histogram itself: 256 counts of byte values 0..255, exact (Sec. I, Sec. III.A);
+ *   - AHist: each value's atomics spread over r sub-bins of an on-chip sub-histogram,
+ *     assigned to the lanes of a wavefront cyclically, indexed by a binning pattern
+ *     (Sec. III.A, Figure 1, discussion of Table 2);
+ *   - the per-wavefront sub-histogram kernel the paper compares against (NVHist, Sec. I,
+ *     Table 2), here one 256-bin table per 64-lane wavefront;
+ *   - streams with an Accumulator and a moving-window (MW) histogram, the pattern
+ *     recomputed from past histograms, and a kernel switch on the degeneracy of the
+ *     last MW histogram (Sec. III.B, Sec. III.C);
+ *   - many slices batched into one asynchronous call returning many histograms
+ *     (Sec. III.B).
+ *
+ * Conventions for every entry point:
+ *   - Pointers named d_* are device memory of the current HIP device; h_* are host memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work is
+ *     enqueued asynchronously on it unless the description says "synchronous".
+ *   - The caller owns every input and output buffer.  The library owns opaque handles,
+ *     their device state and its internal scratch.
+ *   - Calls return a status and never abort or throw.  Argument errors are returned
+ *     synchronously and enqueue nothing.  Errors of the HIP runtime map to HIST_EDEVICE.
+ *   - A handle is used by one host thread at a time, except hist_server_submit/poll,
+ *     which are thread-safe.
+ *   - Counts never depend on the mode or the binning pattern: every mode and every valid
+ *     pattern give the identical histogram.
+ */
+#ifndef HISTMI_H
+#define HISTMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HIST_OK = 0,
+    HIST_EINVAL = -1,     /* bad argument: NULL buffer with n > 0, bad mode, invalid pattern, ... */
+    HIST_ENOMEM = -2,     /* device or host allocation failed */
+    HIST_EOVERFLOW = -3,  /* a count could exceed its 32-bit output (n >= 2^32 for hist_u8) */
+    HIST_EBUSY = -4,      /* server queue full */
+    HIST_EDEVICE = -5,    /* the HIP runtime reported an error */
+    HIST_ENOTSUP = -6,    /* not supported on this device (e.g. not gfx950) */
+    HIST_ETIMEDOUT = -7,  /* a wait ran out of time */
+    HIST_ECANCELED = -8   /* request canceled (server shut down before it ran) */
+} hist_status_t;
+
+typedef enum {
+    /* hist_u8 / hist_u8_u64 / hist_batch: the kernel the library measured fastest for a
+     * call with no history (lane-cyclic sub-bins, HIST_AUTO_FLAT_R per value).
+     * Streams and the server: the paper's switch (Sec. III.C) -- AHist with the pattern
+     * derived from the moving window when the window is degenerate, else per-wavefront. */
+    HIST_MODE_AUTO = 0,
+    HIST_MODE_AHIST = 1,     /* sub-bins indexed by the binning pattern */
+    HIST_MODE_WAVEHIST = 2   /* one 256-bin table per wavefront (NVHist style) */
+} hist_mode_t;
+
+typedef enum {
+    HIST_PAT_IDENTITY = 0,   /* r = 1 for every value, base = value (S = 256) */
+    HIST_PAT_PAPER960 = 1,   /* reconstruction of Figure 1: runs of 32 values, r = 1,2,4,8,8,4,2,1 (S = 960) */
+    HIST_PAT_FLAT = 2        /* r = rmax for every value, in value order (S = 256 * rmax) */
+} hist_pattern_kind_t;
+
+#define HIST_BINS 256
+#define HIST_S_MAX 16384u        /* largest sub-histogram (sub-bins) a pattern may use */
+#define HIST_RMAX_MAX 64u        /* most sub-bins per value: one per lane of a wavefront */
+#define HIST_AUTO_FLAT_R 32u     /* sub-bins per value used by HIST_MODE_AUTO for history-free calls */
+
+/*
+ * Binning pattern (Sec. III.A: 256 entries that index a value's bins in the shared
+ * sub-histogram; Figure 1).  word[v]: bits [0,16) = base sub-bin of value v,
+ * bits [16,24) = log2 r(v), bits [24,32) = 0.  Lane L of a wavefront adds value v into
+ * sub-bin base(v) + (L mod r(v)) (cyclic allotment of sub-bins to lanes, discussion of
+ * Table 2).  Valid iff rmax is a power of two in [1, HIST_RMAX_MAX], every r(v) is a
+ * power of two <= rmax, total_S <= HIST_S_MAX, every range [base, base + r) lies inside
+ * [0, total_S), and the 256 ranges are pairwise disjoint.  1032 bytes; may live in host
+ * or device memory as each call states.
+ */
+typedef struct {
+    uint32_t word[256];
+    uint32_t total_S;
+    uint32_t rmax;
+} hist_pattern_t;
+
+const char *hist_strerror(hist_status_t e);
+
+/* Device facts the library sees (synchronous).  arch: e.g. "gfx950". */
+typedef struct {
+    int device;
+    int cu_count;
+    int clock_khz;
+    size_t lds_per_cu;
+    size_t hbm_bytes;
+    char arch[32];
+} hist_device_info_t;
+hist_status_t hist_device_info(hist_device_info_t *info);
+
+/*
+ * hist_u8 -- out[b] = #{ i < n : in[i] == b } for b = 0..255 (Sec. III.A; exact, Sec. I).
+ *   d_in:   n bytes of device memory, any alignment (n = 0: d_in may be NULL).
+ *   d_out:  device uint32[256], OVERWRITTEN (n = 0 gives zeros).
+ *   mode:   HIST_MODE_AUTO / AHIST / WAVEHIST.
+ *   h_pat:  HOST hist_pattern_t used by HIST_MODE_AHIST (NULL = HIST_PAT_IDENTITY); it is
+ *           checked on the host and copied into the launch, so it may be freed on return.
+ *           Ignored by the other modes.
+ * Errors: HIST_EINVAL (NULL d_in with n > 0, NULL d_out, bad mode, invalid pattern),
+ *         HIST_EOVERFLOW (n >= 2^32: use hist_u8_u64), HIST_EDEVICE.
+ */
+hist_status_t hist_u8(const void *d_in, size_t n_bytes, uint32_t *d_out, hist_mode_t mode,
+                      const hist_pattern_t *h_pat, void *stream);
+
+/* hist_u8_u64 -- as hist_u8 but ACCUMULATES into device uint64[256] d_acc; any n. */
+hist_status_t hist_u8_u64(const void *d_in, size_t n_bytes, uint64_t *d_acc, hist_mode_t mode,
+                          const hist_pattern_t *h_pat, void *stream);
+
+/* hist_pattern_init -- fill a HOST pattern of the given kind (synchronous).
+ *   IDENTITY ignores S/rmax (S = 256, rmax = 1); PAPER960 ignores them (S = 960, rmax = 8);
+ *   FLAT needs rmax a power of two <= HIST_RMAX_MAX (S = 256 * rmax; the S argument is ignored). */
+hist_status_t hist_pattern_init(hist_pattern_t *h_pat, hist_pattern_kind_t kind, uint32_t S, uint32_t rmax);
+
+/* hist_pattern_validate -- HIST_OK iff the HOST pattern is valid (see hist_pattern_t). */
+hist_status_t hist_pattern_validate(const hist_pattern_t *h_pat);
+
+/*
+ * hist_pattern_update -- recompute the pattern from a past histogram (Sec. III.B: the
+ * indices are recomputed from the past stream's histograms).  The paper gives no rule;
+ * this is rule P: with N = sum h, if 256*rmax <= S every value gets rmax; else if N = 0
+ * every value gets 1; else r_t(v) = min(rmax, pow2ceil(max(1, ceil(h(v) 2^t / N)))) for the
+ * largest t in [0, min(24, 64 - bitlen(N))] with sum_v r_t(v) <= S, laid out by
+ * (r descending, value ascending) with bases as running sums.
+ *   d_hist: device uint64[256];  d_pat: device hist_pattern_t, overwritten.
+ *   Needs 256 <= S <= HIST_S_MAX and rmax a power of two <= HIST_RMAX_MAX, else HIST_EINVAL.
+ */
+hist_status_t hist_pattern_update(const uint64_t *d_hist, uint32_t S, uint32_t rmax, hist_pattern_t *d_pat,
+                                  void *stream);
+
+/* ---------------------------------------------------------------- streams (Sec. III.B, III.C) */
+
+typedef struct hist_stream hist_stream_t;
+
+typedef struct {
+    uint32_t W;          /* moving window length in chunks, >= 1 (Table 4 uses 32, 128, 256) */
+    uint32_t theta_pct;  /* critical degeneracy in percent, 0..100 (Sec. III.C: 40-50) */
+    uint32_t S;          /* sub-histogram budget for rule P, 256..HIST_S_MAX */
+    uint32_t rmax;       /* most sub-bins per value, power of two <= HIST_RMAX_MAX */
+    uint32_t lag;        /* chunk k runs with the decision made after chunk k-1-lag (0 = sequential) */
+    uint32_t trace_cap;  /* chunks whose (mode, pattern) are recorded for hist_stream_read */
+} hist_stream_config_t;
+
+/*
+ * Stream semantics.  Chunk k gets histogram h_k.  After chunk k the device updates
+ *   Acc += h_k (uint64, the Accumulator), MW = h_{k-W+1} + ... + h_k (the moving window),
+ *   D_k = (AHIST if 100 * max_v MW(v) > theta * sum_v MW(v) else WAVEHIST, rule P(MW)).
+ * Chunk k runs with D_{k-1-lag}; chunks with k-1-lag < 0 run WAVEHIST with the identity
+ * pattern.  A forced mode in push replaces the decided kernel but not the pattern.  All
+ * state lives on the device; no host round trip happens between chunks.
+ */
+hist_status_t hist_stream_create(hist_stream_t **st, const hist_stream_config_t *cfg);
+
+/* One chunk.  d_out_k: device uint32[256] overwritten with h_k, or NULL. */
+hist_status_t hist_stream_push(hist_stream_t *st, const void *d_chunk, size_t n, hist_mode_t mode,
+                               uint32_t *d_out_k, void *stream);
+
+/* Many chunks in one persistent launch (same semantics as `count` pushes).
+ * h_ptrs/h_sizes: HOST arrays of device pointers and sizes (< 2^32 each).
+ * d_out: device uint32[count][256] (row k overwritten with h_k), or NULL. */
+hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs, const uint64_t *h_sizes,
+                                    uint32_t count, hist_mode_t mode, uint32_t *d_out, void *stream);
+
+typedef struct {
+    uint64_t chunks;       /* chunks pushed so far */
+    uint64_t acc[256];     /* Accumulator */
+    uint64_t mw[256];      /* moving window after the last chunk */
+    uint32_t next_mode;    /* decided kernel after the last chunk (HIST_MODE_AHIST / WAVEHIST) */
+    hist_pattern_t next_pattern;  /* rule P of the current moving window */
+} hist_stream_snapshot_t;
+
+/* Synchronous: waits for `stream`, then copies the state.  h_mode_trace (uint8[trace_len])
+ * and h_pattern_trace (uint32[trace_len][256]) may be NULL; entry k holds the mode / pattern
+ * words chunk k ran with (k < trace_cap). */
+hist_status_t hist_stream_read(hist_stream_t *st, hist_stream_snapshot_t *snap, uint8_t *h_mode_trace,
+                               uint32_t *h_pattern_trace, uint32_t trace_len, void *stream);
+
+/* Synchronous; waits for the device before freeing. */
+hist_status_t hist_stream_destroy(hist_stream_t *st);
+
+/* ---------------------------------------------------------------- batches (Sec. III.B) */
+
+/*
+ * hist_batch -- n histograms in one persistent launch.
+ *   h_ptrs, h_sizes: HOST arrays of n device pointers (any alignment) and sizes (< 2^32).
+ *   d_out: device uint32[n][256]; row j OVERWRITTEN with the histogram of buffer j.
+ *   mode, h_pat: as for hist_u8, one choice for all n buffers.
+ */
+hist_status_t hist_batch(const void *const *h_ptrs, const uint64_t *h_sizes, uint32_t n, uint32_t *d_out,
+                         hist_mode_t mode, const hist_pattern_t *h_pat, void *stream);
+
+/* A batch captured once into a HIP graph (descriptors uploaded at create time); each launch
+ * recomputes all n histograms from the current contents of the same buffers. */
+typedef struct hist_batch_graph hist_batch_graph_t;
+hist_status_t hist_batch_graph_create(hist_batch_graph_t **g, const void *const *h_ptrs, const uint64_t *h_sizes,
+                                      uint32_t n, uint32_t *d_out, hist_mode_t mode, const hist_pattern_t *h_pat);
+hist_status_t hist_batch_graph_launch(hist_batch_graph_t *g, void *stream);
+hist_status_t hist_batch_graph_destroy(hist_batch_graph_t *g);
+
+/* ---------------------------------------------------------------- served requests */
+
+/*
+ * A continuous-batching server of histogram requests.  Requests carry a stream id; each
+ * stream id has device-resident state: a uint64 running histogram and the kernel decision
+ * (mode and binning pattern) recomputed from its latest finished request with the paper's
+ * switch (Sec. III.C) and rule P (the pattern from past histograms, Sec. III.B).  A scheduler
+ * thread admits queued requests in arrival order while the admitted bytes stay within the
+ * HBM budget and the admitted requests within max_slots, packs them into micro-batches (one
+ * persistent launch each, as hist_batch; the paper batches small slices into one asynchronous
+ * call, Sec. III.B) and spreads the micro-batches over n_hip_streams HIP streams, so work
+ * admitted while other batches run overlaps with them on the device.
+ *
+ * Each request's histogram is exact and does not depend on what else is in flight; a
+ * stream's running histogram is the order-free sum of its finished requests.  A stream's
+ * decision follows its latest finished request (a window of one request), so which kernel a
+ * request runs with depends on timing -- only speed does.
+ */
+typedef struct hist_server hist_server_t;
+
+typedef struct {
+    uint64_t hbm_budget_bytes;  /* bytes of admitted, unfinished requests, at most (> 0) */
+    uint32_t max_slots;         /* admitted, unfinished requests, at most (>= 1) */
+    uint32_t n_stream_ids;      /* stream ids 0..n-1 (1..65536) */
+    uint32_t n_hip_streams;     /* HIP streams the micro-batches are spread over (1..16) */
+    uint32_t max_batch;         /* requests per micro-batch, at most (>= 1) */
+    uint32_t mode;              /* hist_mode_t: AUTO = per-stream decision; AHIST / WAVEHIST forced */
+    uint32_t theta_pct;         /* critical degeneracy, percent */
+    uint32_t S;                 /* sub-histogram budget for rule P (256..HIST_S_MAX) */
+    uint32_t rmax;              /* most sub-bins per value (power of two <= HIST_RMAX_MAX) */
+} hist_server_config_t;
+
+typedef struct {
+    int32_t status;             /* HIST_OK finished; HIST_EBUSY queued or running; HIST_ECANCELED; HIST_EDEVICE */
+    uint32_t stream_id;
+    uint64_t bytes;
+    uint64_t t_submit_ns;       /* CLOCK_MONOTONIC: submit returned the ticket */
+    uint64_t t_admit_ns;        /* admitted into a micro-batch (0 if not yet) */
+    uint64_t t_done_ns;         /* the host saw the micro-batch finish (0 if not yet) */
+} hist_server_result_t;
+
+typedef struct {
+    uint64_t submitted, completed, canceled, batches, bytes_done;
+    uint64_t max_inflight_bytes, max_inflight_requests, max_concurrent_batches;
+} hist_server_stats_t;
+
+/* Synchronous.  Starts the scheduler thread on the current device. */
+hist_status_t hist_server_create(hist_server_t **sv, const hist_server_config_t *cfg);
+
+/* Thread-safe, non-blocking.  d_buf: n device bytes (any alignment) that stay unchanged until
+ * the request finishes; d_out: device uint32[256] overwritten with the histogram (or NULL).
+ * Errors: HIST_EINVAL (bad id, NULL buffer with n > 0, n above the HBM budget),
+ * HIST_EOVERFLOW (n >= 2^32), HIST_EBUSY (queue of not-yet-admitted requests full),
+ * HIST_ECANCELED (server shutting down). */
+hist_status_t hist_server_submit(hist_server_t *sv, uint32_t stream_id, const void *d_buf, size_t n, uint32_t *d_out,
+                                 uint64_t *ticket);
+
+/* Thread-safe, non-blocking: fills r (r->status HIST_EBUSY while the request is not done). */
+hist_status_t hist_server_poll(hist_server_t *sv, uint64_t ticket, hist_server_result_t *r);
+
+/* Blocks until the request is done or timeout_ns passes (< 0: no limit); HIST_ETIMEDOUT then. */
+hist_status_t hist_server_wait(hist_server_t *sv, uint64_t ticket, int64_t timeout_ns, hist_server_result_t *r);
+
+/* Blocks until every submitted request is done (or timeout_ns passes: HIST_ETIMEDOUT). */
+hist_status_t hist_server_drain(hist_server_t *sv, int64_t timeout_ns);
+
+/* Synchronous copy of a stream's running uint64[256] histogram (complete after a drain). */
+hist_status_t hist_server_stream_acc(hist_server_t *sv, uint32_t stream_id, uint64_t *h_acc);
+
+hist_status_t hist_server_stats(hist_server_t *sv, hist_server_stats_t *st);
+
+/* Cancels requests not yet admitted (HIST_ECANCELED), waits for admitted ones, frees everything. */
+hist_status_t hist_server_destroy(hist_server_t *sv);
+
+/* ---------------------------------------------------------------- diagnostics and tuning */
+
+typedef struct {
+    uint64_t invalid_patterns;   /* device-side checks of stream patterns that failed (chunk ran per-wavefront) */
+    uint64_t wait_timeouts;      /* bounded in-kernel waits that gave up (stream state may be stale) */
+} hist_diag_t;
+/* Synchronous read of the current device's counters. */
+hist_status_t hist_diag_read(hist_diag_t *d);
+
+/* Launch shape of one kernel family.  Zero fields keep the built-in default. */
+typedef struct {
+    uint32_t blocks_per_cu;   /* persistent workgroups per compute unit */
+    uint32_t tile_kib;        /* batch/stream tile size in KiB (multiple of 16) */
+    uint32_t merge_copies;    /* partial-histogram copies a segment spreads its merge over (power of 2) */
+} hist_tune_t;
+/* family: 0 = per-wavefront, 1 = lane-cyclic uniform sub-bins, 2 = pattern lookup. */
+hist_status_t hist_tune_set(uint32_t family, const hist_tune_t *t);
+hist_status_t hist_tune_get(uint32_t family, hist_tune_t *t);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HISTMI_H */

@@ -1,0 +1,400 @@
+"""ctypes binding of libhistmi.so (argument marshalling only; every count is made by the HIP kernels).
+
+Device buffers are passed as torch tensors (their data_ptr) or raw integer addresses;
+streams as torch.cuda.Stream or a raw hipStream_t integer.  The library must have been
+built (``python paper_1011_0235_amd/build.py`` or ``__graft_entry__.build()``); loading
+fails loudly otherwise.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhistmi.so")
+
+OK, EINVAL, ENOMEM, EOVERFLOW, EBUSY, EDEVICE, ENOTSUP, ETIMEDOUT, ECANCELED = 0, -1, -2, -3, -4, -5, -6, -7, -8
+MODE_AUTO, MODE_AHIST, MODE_WAVEHIST = 0, 1, 2
+PAT_IDENTITY, PAT_PAPER960, PAT_FLAT = 0, 1, 2
+S_MAX = 16384
+RMAX_MAX = 64
+AUTO_FLAT_R = 32
+
+c_u32p = ctypes.POINTER(ctypes.c_uint32)
+c_u64p = ctypes.POINTER(ctypes.c_uint64)
+c_u8p = ctypes.POINTER(ctypes.c_uint8)
+
+
+class HistError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__("%s: %s (%d)" % (what, strerror(status), status))
+
+
+class Pattern(ctypes.Structure):
+    _fields_ = [("word", ctypes.c_uint32 * 256), ("total_S", ctypes.c_uint32), ("rmax", ctypes.c_uint32)]
+
+    @classmethod
+    def from_words(cls, words: Sequence[int], S: int, rmax: int) -> "Pattern":
+        p = cls()
+        for i, w in enumerate(words):
+            p.word[i] = int(w)
+        p.total_S = int(S)
+        p.rmax = int(rmax)
+        return p
+
+    def words(self):
+        return [int(x) for x in self.word]
+
+
+class DeviceInfo(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("cu_count", ctypes.c_int), ("clock_khz", ctypes.c_int),
+                ("lds_per_cu", ctypes.c_size_t), ("hbm_bytes", ctypes.c_size_t), ("arch", ctypes.c_char * 32)]
+
+
+class StreamConfig(ctypes.Structure):
+    _fields_ = [("W", ctypes.c_uint32), ("theta_pct", ctypes.c_uint32), ("S", ctypes.c_uint32),
+                ("rmax", ctypes.c_uint32), ("lag", ctypes.c_uint32), ("trace_cap", ctypes.c_uint32)]
+
+
+class StreamSnapshot(ctypes.Structure):
+    _fields_ = [("chunks", ctypes.c_uint64), ("acc", ctypes.c_uint64 * 256), ("mw", ctypes.c_uint64 * 256),
+                ("next_mode", ctypes.c_uint32), ("next_pattern", Pattern)]
+
+
+class Diag(ctypes.Structure):
+    _fields_ = [("invalid_patterns", ctypes.c_uint64), ("wait_timeouts", ctypes.c_uint64)]
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [("blocks_per_cu", ctypes.c_uint32), ("tile_kib", ctypes.c_uint32), ("merge_copies", ctypes.c_uint32)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_uint32),
+                ("n_stream_ids", ctypes.c_uint32), ("n_hip_streams", ctypes.c_uint32),
+                ("max_batch", ctypes.c_uint32), ("mode", ctypes.c_uint32), ("theta_pct", ctypes.c_uint32),
+                ("S", ctypes.c_uint32), ("rmax", ctypes.c_uint32)]
+
+
+class ServerResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("stream_id", ctypes.c_uint32), ("bytes", ctypes.c_uint64),
+                ("t_submit_ns", ctypes.c_uint64), ("t_admit_ns", ctypes.c_uint64), ("t_done_ns", ctypes.c_uint64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("canceled", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("bytes_done", ctypes.c_uint64), ("max_inflight_bytes", ctypes.c_uint64),
+                ("max_inflight_requests", ctypes.c_uint64), ("max_concurrent_batches", ctypes.c_uint64)]
+
+
+# (name, restype, argtypes) of every symbol include/histmi.h declares
+_VP = ctypes.c_void_p
+_SIGS = [
+    ("hist_strerror", ctypes.c_char_p, [ctypes.c_int]),
+    ("hist_device_info", ctypes.c_int, [ctypes.POINTER(DeviceInfo)]),
+    ("hist_u8", ctypes.c_int, [_VP, ctypes.c_size_t, _VP, ctypes.c_int, ctypes.POINTER(Pattern), _VP]),
+    ("hist_u8_u64", ctypes.c_int, [_VP, ctypes.c_size_t, _VP, ctypes.c_int, ctypes.POINTER(Pattern), _VP]),
+    ("hist_pattern_init", ctypes.c_int, [ctypes.POINTER(Pattern), ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32]),
+    ("hist_pattern_validate", ctypes.c_int, [ctypes.POINTER(Pattern)]),
+    ("hist_pattern_update", ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.c_uint32, _VP, _VP]),
+    ("hist_stream_create", ctypes.c_int, [ctypes.POINTER(_VP), ctypes.POINTER(StreamConfig)]),
+    ("hist_stream_push", ctypes.c_int, [_VP, _VP, ctypes.c_size_t, ctypes.c_int, _VP, _VP]),
+    ("hist_stream_push_many", ctypes.c_int, [_VP, ctypes.POINTER(_VP), c_u64p, ctypes.c_uint32, ctypes.c_int, _VP, _VP]),
+    ("hist_stream_read", ctypes.c_int, [_VP, ctypes.POINTER(StreamSnapshot), c_u8p, c_u32p, ctypes.c_uint32, _VP]),
+    ("hist_stream_destroy", ctypes.c_int, [_VP]),
+    ("hist_batch", ctypes.c_int, [ctypes.POINTER(_VP), c_u64p, ctypes.c_uint32, _VP, ctypes.c_int,
+                                  ctypes.POINTER(Pattern), _VP]),
+    ("hist_batch_graph_create", ctypes.c_int, [ctypes.POINTER(_VP), ctypes.POINTER(_VP), c_u64p, ctypes.c_uint32, _VP,
+                                               ctypes.c_int, ctypes.POINTER(Pattern)]),
+    ("hist_batch_graph_launch", ctypes.c_int, [_VP, _VP]),
+    ("hist_batch_graph_destroy", ctypes.c_int, [_VP]),
+    ("hist_diag_read", ctypes.c_int, [ctypes.POINTER(Diag)]),
+    ("hist_tune_set", ctypes.c_int, [ctypes.c_uint32, ctypes.POINTER(Tune)]),
+    ("hist_tune_get", ctypes.c_int, [ctypes.c_uint32, ctypes.POINTER(Tune)]),
+    ("hist_server_create", ctypes.c_int, [ctypes.POINTER(_VP), ctypes.POINTER(ServerConfig)]),
+    ("hist_server_submit", ctypes.c_int, [_VP, ctypes.c_uint32, _VP, ctypes.c_size_t, _VP, c_u64p]),
+    ("hist_server_poll", ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.POINTER(ServerResult)]),
+    ("hist_server_wait", ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.c_int64, ctypes.POINTER(ServerResult)]),
+    ("hist_server_drain", ctypes.c_int, [_VP, ctypes.c_int64]),
+    ("hist_server_stream_acc", ctypes.c_int, [_VP, ctypes.c_uint32, c_u64p]),
+    ("hist_server_stats", ctypes.c_int, [_VP, ctypes.POINTER(ServerStats)]),
+    ("hist_server_destroy", ctypes.c_int, [_VP]),
+]
+
+_lib = None
+
+
+def declared_symbols():
+    return [name for name, _, _ in _SIGS]
+
+
+def load(path: Optional[str] = None):
+    """Load libhistmi.so (once).  Raises if it is missing: there is no fallback path."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError("libhistmi.so is not built (%s); run python paper_1011_0235_amd/build.py" % p)
+    lib = ctypes.CDLL(p)
+    for name, res, args in _SIGS:
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def strerror(status: int) -> str:
+    if _lib is None:
+        return "status %d" % status
+    return _lib.hist_strerror(int(status)).decode()
+
+
+def _check(status: int, what: str):
+    if status != OK:
+        raise HistError(status, what)
+
+
+def _ptr(x) -> int:
+    if x is None:
+        return 0
+    if isinstance(x, int):
+        return x
+    return int(x.data_ptr())
+
+
+def _stream(s) -> int:
+    if s is None:
+        try:
+            import torch
+            return int(torch.cuda.current_stream().cuda_stream)
+        except Exception:
+            return 0
+    if isinstance(s, int):
+        return s
+    return int(s.cuda_stream)
+
+
+def _nbytes(x) -> int:
+    return int(x.numel() * x.element_size())
+
+
+# ---------------------------------------------------------------- patterns (host)
+
+def pattern_init(kind: int, S: int = 0, rmax: int = 0) -> Pattern:
+    p = Pattern()
+    _check(load().hist_pattern_init(ctypes.byref(p), int(kind), int(S), int(rmax)), "hist_pattern_init")
+    return p
+
+
+def pattern_validate(p: Pattern) -> int:
+    return load().hist_pattern_validate(ctypes.byref(p))
+
+
+def pattern_update(d_hist, S: int, rmax: int, d_pat, stream=None):
+    """Rule P on the device: d_hist uint64[256] (int64 tensor) -> d_pat (int32 tensor of 258 words)."""
+    _check(load().hist_pattern_update(_ptr(d_hist), int(S), int(rmax), _ptr(d_pat), _stream(stream)),
+           "hist_pattern_update")
+
+
+# ---------------------------------------------------------------- single histograms
+
+def hist_u8(d_in, d_out, mode: int = MODE_AUTO, pattern: Optional[Pattern] = None, stream=None, n: Optional[int] = None):
+    """d_out (int32/uint32 tensor of 256, device) <- histogram of the bytes of d_in."""
+    nb = _nbytes(d_in) if n is None else int(n)
+    st = load().hist_u8(_ptr(d_in), nb, _ptr(d_out), int(mode), ctypes.byref(pattern) if pattern is not None else None,
+                        _stream(stream))
+    _check(st, "hist_u8")
+
+
+def hist_u8_u64(d_in, d_acc, mode: int = MODE_AUTO, pattern: Optional[Pattern] = None, stream=None,
+                n: Optional[int] = None):
+    nb = _nbytes(d_in) if n is None else int(n)
+    st = load().hist_u8_u64(_ptr(d_in), nb, _ptr(d_acc), int(mode),
+                            ctypes.byref(pattern) if pattern is not None else None, _stream(stream))
+    _check(st, "hist_u8_u64")
+
+
+def _ptr_arrays(bufs) -> Tuple[ctypes.Array, np.ndarray]:
+    ptrs = (ctypes.c_void_p * len(bufs))()
+    sizes = np.zeros(len(bufs), dtype=np.uint64)
+    for i, b in enumerate(bufs):
+        if isinstance(b, tuple):
+            ptrs[i] = int(b[0])
+            sizes[i] = int(b[1])
+        else:
+            ptrs[i] = _ptr(b)
+            sizes[i] = _nbytes(b)
+    return ptrs, sizes
+
+
+def hist_batch(bufs, d_out, mode: int = MODE_AUTO, pattern: Optional[Pattern] = None, stream=None):
+    """bufs: list of device tensors or (address, nbytes) pairs; d_out: int32 [n, 256] device tensor."""
+    ptrs, sizes = _ptr_arrays(bufs)
+    st = load().hist_batch(ptrs, sizes.ctypes.data_as(c_u64p), len(bufs), _ptr(d_out), int(mode),
+                           ctypes.byref(pattern) if pattern is not None else None, _stream(stream))
+    _check(st, "hist_batch")
+
+
+class BatchGraph:
+    """A batch captured once into a HIP graph; launch() recomputes every histogram."""
+
+    def __init__(self, bufs, d_out, mode: int = MODE_AUTO, pattern: Optional[Pattern] = None):
+        ptrs, sizes = _ptr_arrays(bufs)
+        self._h = ctypes.c_void_p()
+        st = load().hist_batch_graph_create(ctypes.byref(self._h), ptrs, sizes.ctypes.data_as(c_u64p), len(bufs),
+                                            _ptr(d_out), int(mode),
+                                            ctypes.byref(pattern) if pattern is not None else None)
+        _check(st, "hist_batch_graph_create")
+
+    def launch(self, stream=None):
+        _check(load().hist_batch_graph_launch(self._h, _stream(stream)), "hist_batch_graph_launch")
+
+    def close(self):
+        if self._h:
+            load().hist_batch_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- streams
+
+class Stream:
+    """A device-resident histogram stream (Accumulator, moving window, adaptive kernel switch)."""
+
+    def __init__(self, W: int = 1, theta_pct: int = 45, S: int = 960, rmax: int = 8, lag: int = 0,
+                 trace_cap: int = 1024):
+        cfg = StreamConfig(W, theta_pct, S, rmax, lag, trace_cap)
+        self.cfg = cfg
+        self._h = ctypes.c_void_p()
+        _check(load().hist_stream_create(ctypes.byref(self._h), ctypes.byref(cfg)), "hist_stream_create")
+
+    def push(self, d_chunk, mode: int = MODE_AUTO, d_out=None, stream=None, n: Optional[int] = None):
+        nb = _nbytes(d_chunk) if n is None else int(n)
+        _check(load().hist_stream_push(self._h, _ptr(d_chunk), nb, int(mode), _ptr(d_out), _stream(stream)),
+               "hist_stream_push")
+
+    def push_many(self, chunks, mode: int = MODE_AUTO, d_out=None, stream=None):
+        ptrs, sizes = _ptr_arrays(chunks)
+        _check(load().hist_stream_push_many(self._h, ptrs, sizes.ctypes.data_as(c_u64p), len(chunks), int(mode),
+                                            _ptr(d_out), _stream(stream)), "hist_stream_push_many")
+
+    def read(self, trace_len: int = 0, stream=None):
+        snap = StreamSnapshot()
+        modes = np.zeros(max(trace_len, 1), dtype=np.uint8)
+        pats = np.zeros((max(trace_len, 1), 256), dtype=np.uint32)
+        _check(load().hist_stream_read(self._h, ctypes.byref(snap), modes.ctypes.data_as(c_u8p),
+                                       pats.ctypes.data_as(c_u32p), int(trace_len), _stream(stream)),
+               "hist_stream_read")
+        return snap, modes[:trace_len], pats[:trace_len]
+
+    def close(self):
+        if self._h:
+            load().hist_stream_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- diagnostics / tuning / device
+
+def diag() -> Diag:
+    d = Diag()
+    _check(load().hist_diag_read(ctypes.byref(d)), "hist_diag_read")
+    return d
+
+
+def tune_get(family: int) -> Tune:
+    t = Tune()
+    _check(load().hist_tune_get(int(family), ctypes.byref(t)), "hist_tune_get")
+    return t
+
+
+def tune_set(family: int, blocks_per_cu: int = 0, tile_kib: int = 0, merge_copies: int = 0):
+    t = Tune(blocks_per_cu, tile_kib, merge_copies)
+    _check(load().hist_tune_set(int(family), ctypes.byref(t)), "hist_tune_set")
+
+
+def device_info() -> DeviceInfo:
+    d = DeviceInfo()
+    _check(load().hist_device_info(ctypes.byref(d)), "hist_device_info")
+    return d
+
+
+# ---------------------------------------------------------------- server
+
+class Server:
+    """Continuous-batching request server (see hist_server_* in include/histmi.h)."""
+
+    def __init__(self, hbm_budget_bytes: int = 1 << 30, max_slots: int = 256, n_stream_ids: int = 64,
+                 n_hip_streams: int = 4, max_batch: int = 64, mode: int = MODE_AUTO, theta_pct: int = 45,
+                 S: int = 8192, rmax: int = 32):
+        cfg = ServerConfig(int(hbm_budget_bytes), max_slots, n_stream_ids, n_hip_streams, max_batch, mode, theta_pct,
+                           S, rmax)
+        self.cfg = cfg
+        self._h = ctypes.c_void_p()
+        _check(load().hist_server_create(ctypes.byref(self._h), ctypes.byref(cfg)), "hist_server_create")
+
+    def submit(self, stream_id: int, d_buf, d_out=None, n: Optional[int] = None) -> int:
+        nb = _nbytes(d_buf) if (n is None and not isinstance(d_buf, int)) else int(n)
+        t = ctypes.c_uint64()
+        _check(load().hist_server_submit(self._h, int(stream_id), _ptr(d_buf), nb, _ptr(d_out), ctypes.byref(t)),
+               "hist_server_submit")
+        return int(t.value)
+
+    def try_submit(self, stream_id: int, d_buf, d_out=None, n: Optional[int] = None):
+        """(status, ticket) without raising."""
+        nb = _nbytes(d_buf) if (n is None and not isinstance(d_buf, int)) else int(n)
+        t = ctypes.c_uint64()
+        st = load().hist_server_submit(self._h, int(stream_id), _ptr(d_buf), nb, _ptr(d_out), ctypes.byref(t))
+        return st, int(t.value)
+
+    def poll(self, ticket: int) -> ServerResult:
+        r = ServerResult()
+        _check(load().hist_server_poll(self._h, int(ticket), ctypes.byref(r)), "hist_server_poll")
+        return r
+
+    def wait(self, ticket: int, timeout_ns: int = -1) -> ServerResult:
+        r = ServerResult()
+        _check(load().hist_server_wait(self._h, int(ticket), int(timeout_ns), ctypes.byref(r)), "hist_server_wait")
+        return r
+
+    def drain(self, timeout_ns: int = -1):
+        _check(load().hist_server_drain(self._h, int(timeout_ns)), "hist_server_drain")
+
+    def stream_acc(self, stream_id: int) -> np.ndarray:
+        out = np.zeros(256, dtype=np.uint64)
+        _check(load().hist_server_stream_acc(self._h, int(stream_id), out.ctypes.data_as(c_u64p)),
+               "hist_server_stream_acc")
+        return out
+
+    def stats(self) -> ServerStats:
+        s = ServerStats()
+        _check(load().hist_server_stats(self._h, ctypes.byref(s)), "hist_server_stats")
+        return s
+
+    def close(self):
+        if self._h:
+            load().hist_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,742 @@
+// C ABI of libhistmi: argument checks, launch planning, library-owned scratch, streams,
+// batches and batch graphs.  Every histogram is computed by the HIP kernels in kernels.hip.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "histmi.h"
+#include "histmi_dev.h"
+#include "runtime.h"
+
+namespace histmi {
+namespace rt {
+
+// Defaults from the gfx950 probes: the lane-cyclic table streams best with 2 workgroups of
+// 4 wavefronts per CU and 4 loads in flight per lane.
+Tune g_tune[kFamilies] = {{4, 256, 4}, {2, 256, 4}, {2, 256, 4}};
+uint32_t g_single_copies = 64;   // partial copies for a launch with one large segment
+
+static std::mutex g_mu;
+static std::unordered_map<int, DevCtx *> g_dev;
+
+hist_status_t get_dev(DevCtx **out) {
+  int dev = 0;
+  TRY_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_dev.find(dev);
+  if (it != g_dev.end()) {
+    *out = it->second;
+    return HIST_OK;
+  }
+  hipDeviceProp_t pr;
+  TRY_HIP(hipGetDeviceProperties(&pr, dev));
+  if (std::strncmp(pr.gcnArchName, "gfx950", 6) != 0) return HIST_ENOTSUP;
+  DevCtx *d = new DevCtx();
+  d->dev = dev;
+  d->cus = pr.multiProcessorCount;
+  d->lds_cu = pr.maxSharedMemoryPerMultiProcessor ? pr.maxSharedMemoryPerMultiProcessor : pr.sharedMemPerBlock;
+  if (hipMalloc(&d->diag, 64 * sizeof(uint32_t)) != hipSuccess) {
+    delete d;
+    return HIST_ENOMEM;
+  }
+  if (hipMemset(d->diag, 0, 64 * sizeof(uint32_t)) != hipSuccess) {
+    (void)hipFree(d->diag);
+    delete d;
+    return HIST_EDEVICE;
+  }
+  // allow dynamic LDS up to the CU's size; launches that need less work either way
+  if (set_kernel_attrs((uint32_t)(d->lds_cu - kStaticLdsReserve)) != hipSuccess) (void)hipGetLastError();
+  g_dev[dev] = d;
+  *out = d;
+  return HIST_OK;
+}
+
+// Grow-only device buffer; the old one is released after `s` drains.  New memory is zeroed on `s`.
+template <typename T>
+static hist_status_t ensure(T **p, size_t *cap, size_t need, hipStream_t s, bool zero) {
+  if (need <= *cap && *p) return HIST_OK;
+  const size_t ncap = std::max<size_t>(need, *cap * 2);
+  if (*p) {
+    TRY_HIP(hipStreamSynchronize(s));
+    TRY_HIP(hipFree(*p));
+    *p = nullptr;
+    *cap = 0;
+  }
+  if (hipMalloc(reinterpret_cast<void **>(p), ncap * sizeof(T)) != hipSuccess) return HIST_ENOMEM;
+  if (zero) TRY_HIP(hipMemsetAsync(*p, 0, ncap * sizeof(T), s));
+  *cap = ncap;
+  return HIST_OK;
+}
+
+hist_status_t alloc_scratch(Scratch *sc, size_t nseg, uint32_t copies, size_t desc_bytes, hipStream_t s) {
+  TRY(ensure(&sc->ctr, &sc->ctr_cap, 64, s, true));
+  TRY(ensure(&sc->seg_done, &sc->seg_cap, std::max<size_t>(nseg, 1), s, true));
+  TRY(ensure(&sc->partial, &sc->partial_cap, std::max<size_t>(nseg, 1) * copies * 256, s, true));
+  if (desc_bytes) TRY(ensure(&sc->desc, &sc->desc_cap, desc_bytes, s, false));
+  return HIST_OK;
+}
+
+void free_scratch(Scratch *sc) {
+  if (sc->ctr) (void)hipFree(sc->ctr);
+  if (sc->seg_done) (void)hipFree(sc->seg_done);
+  if (sc->partial) (void)hipFree(sc->partial);
+  if (sc->desc) (void)hipFree(sc->desc);
+  for (int k = 0; k < 2; ++k) {
+    if (sc->stage[k]) (void)hipHostFree(sc->stage[k]);
+    if (sc->ev[k]) (void)hipEventDestroy(sc->ev[k]);
+  }
+  *sc = Scratch();
+}
+
+hist_status_t get_scratch(DevCtx *d, hipStream_t s, size_t nseg, uint32_t copies, size_t desc_bytes,
+                          Scratch **out) {
+  Scratch *sc;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = d->scratch.find(s);
+    if (it == d->scratch.end()) {
+      sc = new Scratch();
+      d->scratch[s] = sc;
+    } else {
+      sc = it->second;
+    }
+  }
+  TRY(alloc_scratch(sc, nseg, copies, desc_bytes, s));
+  *out = sc;
+  return HIST_OK;
+}
+
+// Copy `bytes` of host data to sc->desc asynchronously through pinned staging (two buffers,
+// each reused only after its previous copy has finished).
+hist_status_t upload_desc(Scratch *sc, const void *host, size_t bytes, hipStream_t s) {
+  const int k = sc->turn;
+  sc->turn ^= 1;
+  if (sc->ev[k]) TRY_HIP(hipEventSynchronize(sc->ev[k]));
+  else TRY_HIP(hipEventCreateWithFlags(&sc->ev[k], hipEventDisableTiming));
+  if (sc->stage_cap[k] < bytes) {
+    if (sc->stage[k]) TRY_HIP(hipHostFree(sc->stage[k]));
+    sc->stage[k] = nullptr;
+    sc->stage_cap[k] = 0;
+    const size_t cap = std::max<size_t>(bytes, 1 << 16);
+    if (hipHostMalloc(reinterpret_cast<void **>(&sc->stage[k]), cap, hipHostMallocDefault) != hipSuccess)
+      return HIST_ENOMEM;
+    sc->stage_cap[k] = cap;
+  }
+  std::memcpy(sc->stage[k], host, bytes);
+  TRY_HIP(hipMemcpyAsync(sc->desc, sc->stage[k], bytes, hipMemcpyHostToDevice, s));
+  TRY_HIP(hipEventRecord(sc->ev[k], s));
+  return HIST_OK;
+}
+
+bool pattern_ok(const hist_pattern_t *p) {
+  const uint32_t S = p->total_S, rmax = p->rmax;
+  if (!is_pow2(rmax) || rmax > HIST_RMAX_MAX || S < 1 || S > HIST_S_MAX) return false;
+  std::vector<uint8_t> used(S, 0);
+  for (int v = 0; v < 256; ++v) {
+    const uint32_t w = p->word[v];
+    if (w >> 24) return false;
+    const uint32_t lg = (w >> 16) & 0xFF, base = w & 0xFFFF;
+    if (lg > 6 || (1u << lg) > rmax) return false;
+    const uint32_t r = 1u << lg;
+    if (base + r > S) return false;
+    for (uint32_t i = base; i < base + r; ++i) {
+      if (used[i]) return false;
+      used[i] = 1;
+    }
+  }
+  return true;
+}
+
+void init_params(Params *P) {
+  std::memset(P, 0, sizeof(*P));
+  P->seg0.chunk = -1;
+}
+
+// LDS layout: counting table of `table_words` at word 0, then the lookup table.
+static void set_lds(Params *P, uint32_t table_words, bool lookup, uint32_t rr_lg) {
+  P->table_words = (std::max<uint32_t>(table_words, kWaves * 256) + 3u) & ~3u;
+  P->look_off = P->table_words;
+  P->look_rr_lg = rr_lg;
+  P->look_words = lookup ? (256u << rr_lg) : 0u;
+}
+
+hist_status_t select_kind(hist_mode_t mode, const hist_pattern_t *h_pat, Params *P) {
+  uint32_t table = kWaves * 256;
+  bool lookup = false;
+  uint32_t rr_lg = 5;
+  if (mode == HIST_MODE_WAVEHIST) {
+    P->kind = KIND_WAVE;
+  } else if (mode == HIST_MODE_AUTO) {
+    P->kind = KIND_UNIFORM;
+    P->uni_lg = log2u(HIST_AUTO_FLAT_R);
+    table = 256u << P->uni_lg;
+  } else if (mode == HIST_MODE_AHIST) {
+    if (!h_pat) {
+      P->kind = KIND_UNIFORM;   // identity pattern: r = 1, base = value
+      P->uni_lg = 0;
+      table = 256;
+    } else {
+      if (!pattern_ok(h_pat)) return HIST_EINVAL;
+      const uint32_t lg0 = (h_pat->word[0] >> 16) & 0xFF;
+      bool uni = true;
+      for (uint32_t v = 0; v < 256 && uni; ++v) uni = (h_pat->word[v] == ((v << lg0) | (lg0 << 16)));
+      if (uni) {
+        P->kind = KIND_UNIFORM;
+        P->uni_lg = lg0;
+        table = 256u << lg0;
+      } else {
+        P->kind = KIND_LOOKUP;
+        P->pat_S = h_pat->total_S;
+        for (int v = 0; v < 256; ++v) P->pat_words[v] = h_pat->word[v];
+        rr_lg = h_pat->rmax > 32 ? 6 : 5;
+        table = h_pat->total_S;
+        lookup = true;
+      }
+    }
+  } else {
+    return HIST_EINVAL;
+  }
+  set_lds(P, table, lookup, rr_lg);
+  return HIST_OK;
+}
+
+void stream_layout(uint32_t S, uint32_t rmax, hist_mode_t mode, Params *P) {
+  const bool saturated = 256u * rmax <= S;   // rule P then always gives the uniform pattern
+  P->forced = mode == HIST_MODE_AUTO ? 0u : (uint32_t)mode;
+  P->pat_S = S;
+  P->kind = KIND_WAVE;
+  set_lds(P, std::max<uint32_t>(S, 256u * rmax), !saturated, rmax > 32 ? 6 : 5);
+}
+
+uint32_t lds_bytes(const Params &P) { return (P.table_words + P.look_words) * 4u; }
+
+// Workgroups per CU: the family's tuned value, capped by what fits.
+uint32_t blocks_per_cu(uint32_t family, uint32_t lds) {
+  int occ = 1;
+  if (occupancy(lds, &occ) != hipSuccess || occ < 1) occ = 1;
+  return std::max<uint32_t>(1, std::min<uint32_t>(g_tune[family].bpc, (uint32_t)occ));
+}
+
+hist_status_t run_single(DevCtx *d, Params &P, hipStream_t s) {
+  const uint64_t n = P.seg0.size;
+  const uint32_t lds = lds_bytes(P);
+  const uint32_t fam = P.st ? (uint32_t)KIND_UNIFORM : P.kind;
+  const uint32_t G = (uint32_t)d->cus * blocks_per_cu(fam, lds);
+  const uint64_t tile = std::max<uint64_t>(16384, ceil_div(ceil_div(n, G), 16384) * 16384);
+  const uint32_t ntiles = (uint32_t)std::max<uint64_t>(1, ceil_div(n, tile));
+  const uint32_t copies = std::min<uint32_t>(g_single_copies, pow2ceil32(ntiles));
+  Scratch *sc;
+  TRY(get_scratch(d, s, 1, copies, 0, &sc));
+  P.seg0.tile0 = 0;
+  P.seg0.ntiles = ntiles;
+  P.nseg = 1;
+  P.ntiles = ntiles;
+  P.tile_bytes = tile;
+  P.dynamic = 0;
+  P.clog2 = log2u(copies);
+  P.ctr = sc->ctr;
+  P.seg_done = sc->seg_done;
+  P.partial = sc->partial;
+  P.diag = d->diag;
+  const LaunchShape sh{ntiles, lds, 4};
+  return dev_err(launch_hist(P, sh, s));
+}
+
+hist_status_t plan_multi(std::vector<SegDesc> &segs, uint64_t tile, uint32_t max_grid, bool balanced, MultiPlan *mp) {
+  const uint32_t n = (uint32_t)segs.size();
+  uint64_t nt = 0;
+  for (uint32_t j = 0; j < n; ++j) {
+    if (segs[j].size > kMaxSegBytes) return HIST_EOVERFLOW;
+    if (segs[j].size && !segs[j].ptr) return HIST_EINVAL;
+    segs[j].tile0 = (uint32_t)nt;
+    segs[j].ntiles = (uint32_t)std::max<uint64_t>(1, ceil_div(segs[j].size, tile));
+    nt += segs[j].ntiles;
+    if (nt >= 0x7FFFFFFFull) return HIST_EOVERFLOW;
+  }
+  const uint32_t ntiles = (uint32_t)nt;
+  const uint32_t G = std::max<uint32_t>(1, std::min<uint32_t>(max_grid, ntiles));
+  mp->nseg = n;
+  mp->ntiles = ntiles;
+  mp->grid = G;
+  mp->tile = tile;
+  mp->seg_bytes = ((size_t)n * sizeof(SegDesc) + 15) & ~(size_t)15;
+  mp->blob.assign(mp->seg_bytes + ((size_t)ntiles + G + 1) * 4, 0);
+  std::memcpy(mp->blob.data(), segs.data(), (size_t)n * sizeof(SegDesc));
+  uint32_t *map = reinterpret_cast<uint32_t *>(mp->blob.data() + mp->seg_bytes);
+  uint32_t *bounds = map + ntiles;
+  std::vector<uint64_t> wcum((size_t)ntiles + 1, 0);
+  uint32_t ti = 0;
+  for (uint32_t j = 0; j < n; ++j) {
+    for (uint32_t k = 0; k < segs[j].ntiles; ++k, ++ti) {
+      map[ti] = j;
+      const uint64_t off = (uint64_t)k * tile;
+      const uint64_t bytes = off < segs[j].size ? std::min<uint64_t>(tile, segs[j].size - off) : 0;
+      wcum[ti + 1] = wcum[ti] + bytes + 8192;   // a tile also costs its staging and merge
+    }
+  }
+  if (balanced) {
+    // contiguous tile ranges of about equal cost, one per workgroup
+    const uint64_t total = wcum[ntiles];
+    uint32_t k = 0;
+    for (uint32_t g = 0; g <= G; ++g) {
+      const uint64_t target = (g == G) ? total : (total * g) / G;
+      while (k < ntiles && wcum[k] < target) ++k;
+      bounds[g] = (g == G) ? ntiles : k;
+    }
+  }
+  return HIST_OK;
+}
+
+hist_status_t run_multi(DevCtx *d, Params &P, const MultiPlan &mp, uint32_t copies, hipStream_t s, Scratch *own,
+                        bool dynamic, bool upload) {
+  Scratch *sc = own;
+  if (!sc) TRY(get_scratch(d, s, mp.nseg, copies, mp.blob.size(), &sc));
+  else TRY(alloc_scratch(sc, mp.nseg, copies, mp.blob.size(), s));
+  if (upload) TRY(upload_desc(sc, mp.blob.data(), mp.blob.size(), s));
+  P.segs = reinterpret_cast<const SegDesc *>(sc->desc);
+  P.tile_seg = reinterpret_cast<const uint32_t *>(sc->desc + mp.seg_bytes);
+  P.nseg = mp.nseg;
+  P.ntiles = mp.ntiles;
+  P.tile_bytes = mp.tile;
+  P.dynamic = dynamic ? 1u : 0u;
+  P.clog2 = log2u(copies);
+  P.ctr = sc->ctr;
+  P.seg_done = sc->seg_done;
+  P.partial = sc->partial;
+  P.diag = d->diag;
+  const LaunchShape sh{mp.grid, lds_bytes(P), 4};
+  return dev_err(launch_hist(P, sh, s));
+}
+
+hist_status_t stream_state_alloc(uint32_t count, uint32_t W, uint32_t theta, uint32_t S, uint32_t rmax, uint32_t lag,
+                                 uint32_t nslot, uint32_t trace_cap, StreamAlloc *sa) {
+  const size_t tc = std::max<uint32_t>(trace_cap, 1);
+  bool ok = hipMalloc(&sa->d_st, (size_t)count * sizeof(StreamDev)) == hipSuccess &&
+            hipMalloc(&sa->d_ring, (size_t)count * W * 256 * 4) == hipSuccess &&
+            hipMalloc(&sa->d_slots, (size_t)count * nslot * sizeof(Decision)) == hipSuccess &&
+            hipMalloc(&sa->d_mode_trace, (size_t)count * tc) == hipSuccess &&
+            hipMalloc(&sa->d_pat_trace, (size_t)count * tc * 256 * 4) == hipSuccess;
+  if (!ok) {
+    stream_state_free(sa);
+    return HIST_ENOMEM;
+  }
+  std::vector<StreamDev> h(count);
+  for (uint32_t i = 0; i < count; ++i) {
+    StreamDev &x = h[i];
+    std::memset(&x, 0, sizeof(x));
+    x.W = W;
+    x.theta = theta;
+    x.S = S;
+    x.rmax = rmax;
+    x.lag = lag;
+    x.nslot = nslot;
+    x.trace_cap = trace_cap;
+    x.lookup_rr = rmax > 32 ? 64 : 32;
+    x.ring = sa->d_ring + (size_t)i * W * 256;
+    x.slots = sa->d_slots + (size_t)i * nslot;
+    x.mode_trace = sa->d_mode_trace + (size_t)i * tc;
+    x.pat_trace = sa->d_pat_trace + (size_t)i * tc * 256;
+  }
+  ok = hipMemcpy(sa->d_st, h.data(), (size_t)count * sizeof(StreamDev), hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemset(sa->d_ring, 0, (size_t)count * W * 256 * 4) == hipSuccess &&
+       hipMemset(sa->d_slots, 0, (size_t)count * nslot * sizeof(Decision)) == hipSuccess &&
+       hipMemset(sa->d_mode_trace, 0, (size_t)count * tc) == hipSuccess &&
+       hipMemset(sa->d_pat_trace, 0, (size_t)count * tc * 256 * 4) == hipSuccess;
+  if (!ok) {
+    stream_state_free(sa);
+    return HIST_EDEVICE;
+  }
+  return HIST_OK;
+}
+
+void stream_state_free(StreamAlloc *sa) {
+  if (sa->d_st) (void)hipFree(sa->d_st);
+  if (sa->d_ring) (void)hipFree(sa->d_ring);
+  if (sa->d_slots) (void)hipFree(sa->d_slots);
+  if (sa->d_mode_trace) (void)hipFree(sa->d_mode_trace);
+  if (sa->d_pat_trace) (void)hipFree(sa->d_pat_trace);
+  *sa = StreamAlloc();
+}
+
+}  // namespace rt
+}  // namespace histmi
+
+using namespace histmi;
+using namespace histmi::rt;
+
+struct hist_stream {
+  hist_stream_config_t cfg;
+  uint32_t nslot = 0;
+  uint64_t pushed = 0;
+  StreamAlloc sa;
+};
+
+struct hist_batch_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  Scratch sc;
+};
+
+extern "C" {
+
+const char *hist_strerror(hist_status_t e) {
+  switch (e) {
+    case HIST_OK: return "ok";
+    case HIST_EINVAL: return "invalid argument";
+    case HIST_ENOMEM: return "out of memory";
+    case HIST_EOVERFLOW: return "count could overflow its output";
+    case HIST_EBUSY: return "busy";
+    case HIST_EDEVICE: return "HIP device error";
+    case HIST_ENOTSUP: return "not supported on this device";
+    case HIST_ETIMEDOUT: return "timed out";
+    case HIST_ECANCELED: return "canceled";
+  }
+  return "unknown status";
+}
+
+hist_status_t hist_device_info(hist_device_info_t *info) {
+  if (!info) return HIST_EINVAL;
+  int dev = 0;
+  TRY_HIP(hipGetDevice(&dev));
+  hipDeviceProp_t pr;
+  TRY_HIP(hipGetDeviceProperties(&pr, dev));
+  std::memset(info, 0, sizeof(*info));
+  info->device = dev;
+  info->cu_count = pr.multiProcessorCount;
+  info->clock_khz = pr.clockRate;
+  info->lds_per_cu = pr.maxSharedMemoryPerMultiProcessor;
+  info->hbm_bytes = pr.totalGlobalMem;
+  std::snprintf(info->arch, sizeof(info->arch), "%s", pr.gcnArchName);
+  return HIST_OK;
+}
+
+hist_status_t hist_pattern_init(hist_pattern_t *p, hist_pattern_kind_t kind, uint32_t S, uint32_t rmax) {
+  (void)S;
+  if (!p) return HIST_EINVAL;
+  uint32_t r[256];
+  if (kind == HIST_PAT_IDENTITY) {
+    for (int v = 0; v < 256; ++v) r[v] = 1;
+    p->rmax = 1;
+  } else if (kind == HIST_PAT_PAPER960) {
+    static const uint32_t runs[8] = {1, 2, 4, 8, 8, 4, 2, 1};
+    for (int v = 0; v < 256; ++v) r[v] = runs[v / 32];
+    p->rmax = 8;
+  } else if (kind == HIST_PAT_FLAT) {
+    if (!is_pow2(rmax) || rmax > HIST_RMAX_MAX) return HIST_EINVAL;
+    for (int v = 0; v < 256; ++v) r[v] = rmax;
+    p->rmax = rmax;
+  } else {
+    return HIST_EINVAL;
+  }
+  uint32_t base = 0;
+  for (int v = 0; v < 256; ++v) {
+    p->word[v] = base | (log2u(r[v]) << 16);
+    base += r[v];
+  }
+  p->total_S = base;
+  return HIST_OK;
+}
+
+hist_status_t hist_pattern_validate(const hist_pattern_t *p) {
+  if (!p) return HIST_EINVAL;
+  return pattern_ok(p) ? HIST_OK : HIST_EINVAL;
+}
+
+hist_status_t hist_pattern_update(const uint64_t *d_hist, uint32_t S, uint32_t rmax, hist_pattern_t *d_pat,
+                                  void *stream) {
+  if (!d_hist || !d_pat || S < 256 || S > HIST_S_MAX || !is_pow2(rmax) || rmax > HIST_RMAX_MAX) return HIST_EINVAL;
+  DevCtx *d;
+  TRY(get_dev(&d));
+  return dev_err(launch_pattern_update(d_hist, S, rmax, d_pat, static_cast<hipStream_t>(stream)));
+}
+
+static hist_status_t hist_common(const void *d_in, size_t n, uint32_t *d_out, uint64_t *d_acc, hist_mode_t mode,
+                                 const hist_pattern_t *h_pat, void *stream) {
+  if (n && !d_in) return HIST_EINVAL;
+  if (!mode_ok(mode)) return HIST_EINVAL;
+  if (d_out && (uint64_t)n > kMaxSegBytes) return HIST_EOVERFLOW;
+  Params P;
+  init_params(&P);
+  TRY(select_kind(mode, h_pat, &P));
+  DevCtx *d;
+  TRY(get_dev(&d));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (d_out) {
+    P.seg0.ptr = static_cast<const uint8_t *>(d_in);
+    P.seg0.size = n;
+    P.seg0.out = d_out;
+    return run_single(d, P, s);
+  }
+  // accumulate in pieces whose counts fit the 32-bit partials
+  const uint64_t piece = 1ull << 31;
+  uint64_t done = 0;
+  do {
+    const uint64_t m = std::min<uint64_t>(piece, (uint64_t)n - done);
+    P.seg0.ptr = static_cast<const uint8_t *>(d_in) + done;
+    P.seg0.size = m;
+    P.seg0.acc = d_acc;
+    TRY(run_single(d, P, s));
+    done += m;
+  } while (done < (uint64_t)n);
+  return HIST_OK;
+}
+
+hist_status_t hist_u8(const void *d_in, size_t n, uint32_t *d_out, hist_mode_t mode, const hist_pattern_t *h_pat,
+                      void *stream) {
+  if (!d_out) return HIST_EINVAL;
+  return hist_common(d_in, n, d_out, nullptr, mode, h_pat, stream);
+}
+
+hist_status_t hist_u8_u64(const void *d_in, size_t n, uint64_t *d_acc, hist_mode_t mode, const hist_pattern_t *h_pat,
+                          void *stream) {
+  if (!d_acc) return HIST_EINVAL;
+  return hist_common(d_in, n, nullptr, d_acc, mode, h_pat, stream);
+}
+
+// ---------------------------------------------------------------- batches
+
+static hist_status_t batch_prepare(const void *const *h_ptrs, const uint64_t *h_sizes, uint32_t n, uint32_t *d_out,
+                                   hist_mode_t mode, const hist_pattern_t *h_pat, DevCtx **dout, Params *P,
+                                   MultiPlan *mp, uint32_t *copies) {
+  if (!h_ptrs || !h_sizes || !d_out) return HIST_EINVAL;
+  if (!mode_ok(mode)) return HIST_EINVAL;
+  init_params(P);
+  TRY(select_kind(mode, h_pat, P));
+  DevCtx *d;
+  TRY(get_dev(&d));
+  *dout = d;
+  const uint32_t fam = P->kind;
+  const uint64_t tile = (uint64_t)g_tune[fam].tile_kib * 1024;
+  const uint32_t maxg = (uint32_t)d->cus * blocks_per_cu(fam, lds_bytes(*P));
+  std::vector<SegDesc> segs(n);
+  for (uint32_t j = 0; j < n; ++j) {
+    std::memset(&segs[j], 0, sizeof(SegDesc));
+    segs[j].ptr = static_cast<const uint8_t *>(h_ptrs[j]);
+    segs[j].size = h_sizes[j];
+    segs[j].out = d_out + (size_t)j * 256;
+    segs[j].chunk = -1;
+  }
+  TRY(plan_multi(segs, tile, maxg, true, mp));
+  *copies = std::min<uint32_t>(64, pow2ceil32(std::max<uint32_t>(1, g_tune[fam].copies)));
+  return HIST_OK;
+}
+
+hist_status_t hist_batch(const void *const *h_ptrs, const uint64_t *h_sizes, uint32_t n, uint32_t *d_out,
+                         hist_mode_t mode, const hist_pattern_t *h_pat, void *stream) {
+  if (n == 0) return HIST_OK;
+  DevCtx *d = nullptr;
+  Params P;
+  MultiPlan mp;
+  uint32_t copies = 1;
+  TRY(batch_prepare(h_ptrs, h_sizes, n, d_out, mode, h_pat, &d, &P, &mp, &copies));
+  return run_multi(d, P, mp, copies, static_cast<hipStream_t>(stream), nullptr, false, true);
+}
+
+hist_status_t hist_batch_graph_destroy(hist_batch_graph_t *g);
+
+hist_status_t hist_batch_graph_create(hist_batch_graph_t **g, const void *const *h_ptrs, const uint64_t *h_sizes,
+                                      uint32_t n, uint32_t *d_out, hist_mode_t mode, const hist_pattern_t *h_pat) {
+  if (!g || n == 0) return HIST_EINVAL;
+  DevCtx *d = nullptr;
+  Params P;
+  MultiPlan mp;
+  uint32_t copies = 1;
+  TRY(batch_prepare(h_ptrs, h_sizes, n, d_out, mode, h_pat, &d, &P, &mp, &copies));
+  hist_batch_graph *bg = new hist_batch_graph();
+  hipStream_t cs = nullptr;
+  hist_status_t st = HIST_OK;
+  do {
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) { st = HIST_EDEVICE; break; }
+    // graph-owned scratch, zeroed and loaded before capture (no memset or copy nodes in the graph)
+    if ((st = alloc_scratch(&bg->sc, n, copies, mp.blob.size(), cs)) != HIST_OK) break;
+    if (hipMemcpyAsync(bg->sc.desc, mp.blob.data(), mp.blob.size(), hipMemcpyHostToDevice, cs) != hipSuccess ||
+        hipStreamSynchronize(cs) != hipSuccess) { st = HIST_EDEVICE; break; }
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) { st = HIST_EDEVICE; break; }
+    st = run_multi(d, P, mp, copies, cs, &bg->sc, false, false);
+    hipGraph_t graph = nullptr;
+    const hipError_t ce = hipStreamEndCapture(cs, &graph);
+    if (graph) bg->graph = graph;
+    if (st != HIST_OK) break;
+    if (ce != hipSuccess || !graph) { st = HIST_EDEVICE; break; }
+    if (hipGraphInstantiate(&bg->exec, graph, nullptr, nullptr, 0) != hipSuccess) { st = HIST_EDEVICE; break; }
+  } while (0);
+  if (cs) (void)hipStreamDestroy(cs);
+  if (st != HIST_OK) {
+    hist_batch_graph_destroy(bg);
+    return st;
+  }
+  *g = bg;
+  return HIST_OK;
+}
+
+hist_status_t hist_batch_graph_launch(hist_batch_graph_t *g, void *stream) {
+  if (!g || !g->exec) return HIST_EINVAL;
+  return dev_err(hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)));
+}
+
+hist_status_t hist_batch_graph_destroy(hist_batch_graph_t *g) {
+  if (!g) return HIST_EINVAL;
+  (void)hipDeviceSynchronize();
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  free_scratch(&g->sc);
+  delete g;
+  return HIST_OK;
+}
+
+// ---------------------------------------------------------------- streams
+
+hist_status_t hist_stream_destroy(hist_stream_t *st);
+
+hist_status_t hist_stream_create(hist_stream_t **out, const hist_stream_config_t *cfg) {
+  if (!out || !cfg) return HIST_EINVAL;
+  const hist_stream_config_t c = *cfg;
+  if (c.W < 1 || c.W > (1u << 16) || c.theta_pct > 100 || c.S < 256 || c.S > HIST_S_MAX || !is_pow2(c.rmax) ||
+      c.rmax > HIST_RMAX_MAX || c.lag > 4096 || c.trace_cap > (1u << 22))
+    return HIST_EINVAL;
+  DevCtx *d;
+  TRY(get_dev(&d));
+  hist_stream *st = new hist_stream();
+  st->cfg = c;
+  st->nslot = c.lag + 2;   // a slot is reused only after the chunk that needed it has finished
+  const hist_status_t r = stream_state_alloc(1, c.W, c.theta_pct, c.S, c.rmax, c.lag, st->nslot, c.trace_cap, &st->sa);
+  if (r != HIST_OK) {
+    delete st;
+    return r;
+  }
+  *out = st;
+  return HIST_OK;
+}
+
+hist_status_t hist_stream_push(hist_stream_t *st, const void *d_chunk, size_t n, hist_mode_t mode, uint32_t *d_out_k,
+                               void *stream) {
+  if (!st || (n && !d_chunk) || !mode_ok(mode)) return HIST_EINVAL;
+  if ((uint64_t)n > kMaxSegBytes) return HIST_EOVERFLOW;
+  DevCtx *d;
+  TRY(get_dev(&d));
+  Params P;
+  init_params(&P);
+  stream_layout(st->cfg.S, st->cfg.rmax, mode, &P);
+  P.st = st->sa.d_st;
+  P.seg0.ptr = static_cast<const uint8_t *>(d_chunk);
+  P.seg0.size = n;
+  P.seg0.out = d_out_k;
+  P.seg0.chunk = (int64_t)st->pushed;
+  P.seg0.stream_idx = 0;
+  TRY(run_single(d, P, static_cast<hipStream_t>(stream)));
+  st->pushed += 1;
+  return HIST_OK;
+}
+
+hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs, const uint64_t *h_sizes,
+                                    uint32_t count, hist_mode_t mode, uint32_t *d_out, void *stream) {
+  if (!st || !mode_ok(mode)) return HIST_EINVAL;
+  if (count == 0) return HIST_OK;
+  if (!h_ptrs || !h_sizes) return HIST_EINVAL;
+  DevCtx *d;
+  TRY(get_dev(&d));
+  Params P;
+  init_params(&P);
+  stream_layout(st->cfg.S, st->cfg.rmax, mode, &P);
+  P.st = st->sa.d_st;
+  const uint32_t fam = KIND_UNIFORM;
+  const uint64_t tile = (uint64_t)g_tune[fam].tile_kib * 1024;
+  const uint32_t maxg = (uint32_t)d->cus * blocks_per_cu(fam, lds_bytes(P));
+  std::vector<SegDesc> segs(count);
+  for (uint32_t j = 0; j < count; ++j) {
+    std::memset(&segs[j], 0, sizeof(SegDesc));
+    segs[j].ptr = static_cast<const uint8_t *>(h_ptrs[j]);
+    segs[j].size = h_sizes[j];
+    segs[j].out = d_out ? d_out + (size_t)j * 256 : nullptr;
+    segs[j].chunk = (int64_t)(st->pushed + j);
+    segs[j].stream_idx = 0;
+  }
+  MultiPlan mp;
+  TRY(plan_multi(segs, tile, maxg, false, &mp));
+  const uint32_t copies = std::min<uint32_t>(64, pow2ceil32(std::max<uint32_t>(1, g_tune[fam].copies)));
+  // tiles are handed out in chunk order, so a chunk waiting for an earlier chunk's decision
+  // never waits on a workgroup that has not started
+  TRY(run_multi(d, P, mp, copies, static_cast<hipStream_t>(stream), nullptr, true, true));
+  st->pushed += count;
+  return HIST_OK;
+}
+
+hist_status_t hist_stream_read(hist_stream_t *st, hist_stream_snapshot_t *snap, uint8_t *h_mode_trace,
+                               uint32_t *h_pattern_trace, uint32_t trace_len, void *stream) {
+  if (!st) return HIST_EINVAL;
+  TRY_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+  if (snap) {
+    StreamDev h;
+    TRY_HIP(hipMemcpy(&h, st->sa.d_st, sizeof(h), hipMemcpyDeviceToHost));
+    std::memset(snap, 0, sizeof(*snap));
+    snap->chunks = h.done;
+    std::memcpy(snap->acc, h.acc, sizeof(snap->acc));
+    std::memcpy(snap->mw, h.mw, sizeof(snap->mw));
+    if (h.done > 0) {
+      Decision dec;
+      TRY_HIP(hipMemcpy(&dec, st->sa.d_slots + (h.done - 1) % st->nslot, sizeof(dec), hipMemcpyDeviceToHost));
+      snap->next_mode = dec.mode;
+      std::memcpy(snap->next_pattern.word, dec.words, sizeof(dec.words));
+      snap->next_pattern.total_S = dec.S;
+      snap->next_pattern.rmax = dec.rmax;
+    } else {
+      snap->next_mode = HIST_MODE_WAVEHIST;
+      TRY(hist_pattern_init(&snap->next_pattern, HIST_PAT_IDENTITY, 0, 0));
+    }
+  }
+  const uint32_t n = std::min<uint32_t>(trace_len, st->cfg.trace_cap);
+  if (h_mode_trace && n) TRY_HIP(hipMemcpy(h_mode_trace, st->sa.d_mode_trace, n, hipMemcpyDeviceToHost));
+  if (h_pattern_trace && n)
+    TRY_HIP(hipMemcpy(h_pattern_trace, st->sa.d_pat_trace, (size_t)n * 256 * 4, hipMemcpyDeviceToHost));
+  return HIST_OK;
+}
+
+hist_status_t hist_stream_destroy(hist_stream_t *st) {
+  if (!st) return HIST_EINVAL;
+  (void)hipDeviceSynchronize();
+  stream_state_free(&st->sa);
+  delete st;
+  return HIST_OK;
+}
+
+// ---------------------------------------------------------------- diagnostics and tuning
+
+hist_status_t hist_diag_read(hist_diag_t *out) {
+  if (!out) return HIST_EINVAL;
+  DevCtx *d;
+  TRY(get_dev(&d));
+  uint32_t h[64];
+  TRY_HIP(hipMemcpy(h, d->diag, sizeof(h), hipMemcpyDeviceToHost));
+  out->invalid_patterns = h[0];
+  out->wait_timeouts = h[1];
+  return HIST_OK;
+}
+
+hist_status_t hist_tune_set(uint32_t family, const hist_tune_t *t) {
+  if (!t || family >= kFamilies) return HIST_EINVAL;
+  if (t->tile_kib && (t->tile_kib % 16 || t->tile_kib > (1u << 20))) return HIST_EINVAL;
+  if (t->merge_copies && (!is_pow2(t->merge_copies) || t->merge_copies > 64)) return HIST_EINVAL;
+  if (t->blocks_per_cu > 8) return HIST_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (t->blocks_per_cu) g_tune[family].bpc = t->blocks_per_cu;
+  if (t->tile_kib) g_tune[family].tile_kib = t->tile_kib;
+  if (t->merge_copies) g_tune[family].copies = t->merge_copies;
+  return HIST_OK;
+}
+
+hist_status_t hist_tune_get(uint32_t family, hist_tune_t *t) {
+  if (!t || family >= kFamilies) return HIST_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  t->blocks_per_cu = g_tune[family].bpc;
+  t->tile_kib = g_tune[family].tile_kib;
+  t->merge_copies = g_tune[family].copies;
+  return HIST_OK;
+}
+
+}  // extern "C"

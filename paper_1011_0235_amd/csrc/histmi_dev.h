@@ -1,0 +1,94 @@
+// Internal layout shared by the HIP kernels and the host runtime of libhistmi.
+#pragma once
+
+#include <stdint.h>
+
+#include "histmi.h"
+
+namespace histmi {
+
+constexpr uint32_t kBlock = 256;            // threads per workgroup (4 wavefronts of 64)
+constexpr uint32_t kWaves = kBlock / 64;
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr uint32_t kMaxCopiesLog2 = 6;      // at most 64 partial copies per segment
+
+// How a workgroup lays out its LDS counting table for one segment.
+enum Kind : uint32_t {
+  KIND_WAVE = 0,      // one 256-bin table per wavefront (NVHist style)
+  KIND_UNIFORM = 1,   // every value has r = 2^lg sub-bins at v*r + (lane mod r)
+  KIND_LOOKUP = 2     // per-value (base, r) from a binning pattern, via a lane-replicated index table
+};
+
+// A stream's kernel choice for one chunk: written by the epilogue of the chunk it was
+// derived from, read by the chunk that runs with it.
+struct Decision {
+  uint32_t words[256];   // binning pattern words (hist_pattern_t encoding)
+  uint32_t S, rmax;
+  uint32_t mode;         // HIST_MODE_AHIST or HIST_MODE_WAVEHIST
+  uint32_t gen;          // index of the producing chunk + 1; stored last (release)
+};
+
+// Device-resident state of one stream (Accumulator, moving window, decisions, traces).
+struct StreamDev {
+  uint32_t W, theta, S, rmax, lag, nslot, trace_cap, lookup_rr;
+  uint64_t done;         // number of chunk epilogues completed (stored with release)
+  uint64_t acc[256];
+  uint64_t mw[256];
+  uint32_t *ring;        // [W][256] histograms of the last W chunks
+  Decision *slots;       // [nslot]; decision made after chunk j lives in slot j % nslot
+  uint8_t *mode_trace;   // [trace_cap]
+  uint32_t *pat_trace;   // [trace_cap][256]
+};
+
+// One input buffer of a launch.
+struct SegDesc {
+  const uint8_t *ptr;
+  uint64_t size;
+  uint32_t *out;         // uint32[256] overwritten with the histogram, or null
+  uint64_t *acc;         // uint64[256] the histogram is added to, or null
+  int64_t chunk;         // >= 0: chunk index of an ordered stream; kServerChunk: server request; -1: none
+  uint32_t tile0;        // first tile (launch-global index)
+  uint32_t ntiles;       // >= 1 (an empty buffer still has one empty tile so it gets finalized)
+  uint32_t stream_idx;   // index into Params::st for stream chunks and server requests
+  uint32_t pad;
+};
+
+constexpr int64_t kServerChunk = -2;
+
+struct Params {
+  const SegDesc *segs;       // device array of nseg descriptors (unused when nseg == 1)
+  SegDesc seg0;              // the descriptor when nseg == 1
+  const uint32_t *tile_seg;  // device map tile -> segment, then per-workgroup tile bounds (unused when nseg == 1)
+  uint32_t nseg;
+  uint32_t ntiles;
+  uint64_t tile_bytes;
+  uint32_t dynamic;          // 1: tiles handed out in order by an atomic counter; 0: static
+  uint32_t clog2;            // log2 of the partial copies per segment
+  uint32_t *ctr;             // [0] next tile, [1] workgroups finished (both reset by the last one)
+  uint32_t *seg_done;        // [nseg] tiles finished per segment (reset by the finalizer)
+  uint32_t *partial;         // [nseg][copies][256] partial counts (reset by the finalizer)
+  uint32_t *diag;            // device diagnostics counters
+  // non-stream segments: one kind for every segment
+  uint32_t kind;             // Kind
+  uint32_t uni_lg;           // KIND_UNIFORM: log2 r
+  uint32_t pat_S;            // KIND_LOOKUP: pattern size; stream launches: counting-table capacity
+  uint32_t look_rr_lg;       // log2 of the lookup replication (5 or 6)
+  uint32_t pat_words[256];
+  // stream chunks and server requests
+  StreamDev *st;             // array of stream states
+  uint32_t forced;           // 0 = decided per chunk, else HIST_MODE_AHIST / HIST_MODE_WAVEHIST
+  uint32_t pad;
+  // LDS layout (in 32-bit words)
+  uint32_t table_words;      // counting table at word 0
+  uint32_t look_off;         // lane-replicated lookup table (byte addresses into the counting table)
+  uint32_t look_words;
+};
+
+// Launch configuration chosen by the host.
+struct LaunchShape {
+  uint32_t grid;
+  uint32_t lds_bytes;
+  uint32_t unroll;
+};
+
+}  // namespace histmi

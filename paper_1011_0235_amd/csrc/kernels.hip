@@ -1,0 +1,618 @@
+// HIP kernels of libhistmi for gfx950 (CDNA4, wave64).
+//
+// One persistent kernel family does every histogram launch.  A launch covers one or more
+// segments (input buffers); each segment is cut into tiles and each workgroup takes whole
+// tiles.  For every segment a workgroup touches it:
+//   1. stages an LDS counting table (kind chosen per segment, see Kind);
+//   2. streams its tiles with 16-byte loads (1 KiB per wavefront per load) and adds every
+//      byte into the table with one ds_add_u32 (the hot loop);
+//   3. sums the table down to 256 counts (one per thread) and merges them into one of
+//      several partial copies of the segment's histogram in global memory with
+//      no-return atomics (spread over copies so that same-address atomics do not serialize);
+//   4. takes a ticket; the workgroup finishing the segment's last tile sums the copies,
+//      writes the segment's histogram, resets the copies and, for a stream chunk, runs the
+//      stream epilogue (Accumulator, moving window, degeneracy switch, rule P).
+//
+// The counting tables follow the paper's two kernels (Sec. III.A, Table 2):
+//   KIND_WAVE    -- one 256-bin table per wavefront, the per-warp sub-histograms of the
+//                   NVIDIA SDK kernel the paper compares against;
+//   KIND_UNIFORM -- AHist with every value given r sub-bins, lane L adding into sub-bin
+//                   v*r + (L mod r) (the cyclic allotment of sub-bins to the threads of a
+//                   warp); with r >= 32 the 64 lanes of a wavefront never collide in a bank;
+//   KIND_LOOKUP  -- AHist with an arbitrary binning pattern (Figure 1): per value a base and
+//                   a power-of-two r; the lane-specific sub-bin address comes from an
+//                   LDS table replicated per lane so that the lookup itself is conflict free.
+
+#include <hip/hip_runtime.h>
+
+#include "histmi_dev.h"
+
+namespace histmi {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+// Global-address-space views: loads through them compile to global_load_* (vmcnt only)
+// instead of flat_load_*, which would also count against the LDS wait counter.
+typedef __attribute__((address_space(1))) const u32x4 gu32x4;
+typedef __attribute__((address_space(1))) const uint8_t gu8;
+
+// Small control block in static LDS.
+struct Ctl {
+  uint32_t next_tile;
+  uint32_t flag;
+  uint32_t kind;
+  uint32_t lg;
+  uint32_t used_mode;
+  uint32_t look_shift;
+  uint32_t red32[kWaves];
+  uint64_t red64[kWaves];
+  uint32_t cls_cnt[kWaves][8];
+  uint32_t words[256];     // binning pattern words of the current segment
+  uint32_t bitmap[512];    // overlap check of a pattern (up to HIST_S_MAX sub-bins)
+};
+
+// ------------------------------------------------------------------ block helpers
+
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
+__device__ __forceinline__ uint32_t wave_id() { return threadIdx.x >> 6; }
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int o) {
+  uint32_t lo = __shfl_xor((uint32_t)v, o, 64);
+  uint32_t hi = __shfl_xor((uint32_t)(v >> 32), o, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ uint32_t block_sum_u32(uint32_t v, Ctl &c) {
+  v = wave_sum_u32(v);
+  if (lane_id() == 0) c.red32[wave_id()] = v;
+  __syncthreads();
+  uint32_t s = 0;
+#pragma unroll
+  for (uint32_t w = 0; w < kWaves; ++w) s += c.red32[w];
+  __syncthreads();
+  return s;
+}
+
+__device__ bool block_all(bool p, Ctl &c) {
+  return block_sum_u32(p ? 0u : 1u, c) == 0u;
+}
+
+__device__ uint64_t block_sum_u64(uint64_t v, Ctl &c) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += shfl_xor_u64(v, o);
+  if (lane_id() == 0) c.red64[wave_id()] = v;
+  __syncthreads();
+  uint64_t s = 0;
+#pragma unroll
+  for (uint32_t w = 0; w < kWaves; ++w) s += c.red64[w];
+  __syncthreads();
+  return s;
+}
+
+__device__ uint64_t block_max_u64(uint64_t v, Ctl &c) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    uint64_t u = shfl_xor_u64(v, o);
+    v = u > v ? u : v;
+  }
+  if (lane_id() == 0) c.red64[wave_id()] = v;
+  __syncthreads();
+  uint64_t s = 0;
+#pragma unroll
+  for (uint32_t w = 0; w < kWaves; ++w) s = c.red64[w] > s ? c.red64[w] : s;
+  __syncthreads();
+  return s;
+}
+
+template <typename T>
+__device__ __forceinline__ T ld_agent(const T *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_agent(T *p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Bounded spin by thread 0 until *p == want.  Returns false on timeout (counted in diag[1]).
+__device__ bool spin_until_u32(const uint32_t *p, uint32_t want, uint32_t *diag) {
+  for (uint32_t i = 0; i < (1u << 24); ++i) {
+    if (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == want) return true;
+    __builtin_amdgcn_s_sleep(2);
+  }
+  atomicAdd(&diag[1], 1u);
+  return false;
+}
+__device__ bool spin_until_u64(const uint64_t *p, uint64_t want, uint32_t *diag) {
+  for (uint32_t i = 0; i < (1u << 24); ++i) {
+    if (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == want) return true;
+    __builtin_amdgcn_s_sleep(2);
+  }
+  atomicAdd(&diag[1], 1u);
+  return false;
+}
+
+// ------------------------------------------------------------------ rule P on the device
+//
+// Pattern from a past histogram (the paper recomputes the indices from the past stream's
+// histograms, Sec. III.B, without giving a rule).  Thread t holds h(t); N = sum h.
+//   256*rmax <= S: every value gets rmax.  N == 0: every value gets 1.
+//   Otherwise r_t(v) = min(rmax, pow2ceil(max(1, ceil(h(v) 2^t / N)))) at the largest t in
+//   [0, min(24, clz64(N))] with sum_v r_t(v) <= S (the sum grows with t: binary search).
+//   Values are laid out by (r descending, value ascending); bases are running sums.
+// Returns this thread's pattern word.
+
+__device__ __forceinline__ uint32_t rule_p_lg(uint64_t h, uint64_t N, uint32_t tt, uint32_t rmax, uint32_t rmax_lg) {
+  const uint64_t num = h << tt;
+  const uint64_t q = num / N + ((num % N) != 0 ? 1u : 0u);
+  if (q <= 1) return 0;
+  if (q >= rmax) return rmax_lg;
+  return 64u - (uint32_t)__clzll((long long)(q - 1));
+}
+
+__device__ uint32_t rule_p_word(uint64_t h, uint64_t N, uint32_t S, uint32_t rmax, Ctl &c) {
+  const uint32_t rmax_lg = 31u - (uint32_t)__clz((int)rmax);
+  uint32_t cls;
+  if (256u * rmax <= S) {
+    cls = rmax_lg;
+  } else if (N == 0) {
+    cls = 0;
+  } else {
+    const uint32_t lz = (uint32_t)__clzll((long long)N);
+    uint32_t lo = 0, hi = lz < 24u ? lz : 24u;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      const uint32_t s = block_sum_u32(1u << rule_p_lg(h, N, mid, rmax, rmax_lg), c);
+      if (s <= S) lo = mid;
+      else hi = mid - 1;
+    }
+    cls = rule_p_lg(h, N, lo, rmax, rmax_lg);
+  }
+  // layout by (r descending, value ascending)
+  const uint32_t lane = lane_id(), w = wave_id();
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  uint32_t rank = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < 7; ++k) {
+    const uint64_t m = __ballot(cls == k);
+    if (lane == 0) c.cls_cnt[w][k] = (uint32_t)__popcll(m);
+    if (cls == k) rank = (uint32_t)__popcll(m & below);
+  }
+  __syncthreads();
+  for (uint32_t w2 = 0; w2 < w; ++w2) rank += c.cls_cnt[w2][cls];
+  uint32_t offset = 0;
+  for (uint32_t k = cls + 1; k < 7; ++k) {
+    uint32_t cnt = 0;
+    for (uint32_t w2 = 0; w2 < kWaves; ++w2) cnt += c.cls_cnt[w2][k];
+    offset += cnt << k;
+  }
+  __syncthreads();
+  return (offset + (rank << cls)) | (cls << 16);
+}
+
+// ------------------------------------------------------------------ table staging
+
+__device__ __forceinline__ void zero_words(uint32_t *lds, uint32_t words) {
+  u32x4 *p = reinterpret_cast<u32x4 *>(lds);
+  const u32x4 z = {0u, 0u, 0u, 0u};
+  for (uint32_t i = threadIdx.x; i < (words >> 2); i += kBlock) p[i] = z;
+}
+
+// Check c.words as a pattern of S sub-bins and at most rmax per value; choose the kind.
+// Returns KIND_UNIFORM (c.lg set) or KIND_LOOKUP for a valid pattern, KIND_WAVE otherwise.
+__device__ uint32_t classify_pattern(Ctl &c, uint32_t S, uint32_t rmax, uint32_t S_cap, uint32_t rmax_cap,
+                                     bool have_lookup) {
+  const uint32_t t = threadIdx.x;
+  const uint32_t w = c.words[t];
+  const uint32_t base = w & 0xFFFFu, lg = (w >> 16) & 0xFFu, hi = w >> 24;
+  const bool rmax_ok = rmax >= 1 && rmax <= rmax_cap && (rmax & (rmax - 1)) == 0 && S <= S_cap;
+  bool ok = rmax_ok && hi == 0 && lg <= 6 && (1u << lg) <= rmax && base + (1u << lg) <= S;
+  for (uint32_t i = t; i < 512; i += kBlock) c.bitmap[i] = 0;
+  __syncthreads();
+  if (ok) {
+    const uint32_t lo_b = base, hi_b = base + (1u << lg);   // [lo_b, hi_b)
+    for (uint32_t wi = lo_b >> 5; wi <= ((hi_b - 1) >> 5); ++wi) {
+      const uint32_t s0 = wi << 5;
+      const uint32_t a = lo_b > s0 ? lo_b - s0 : 0u;
+      const uint32_t b = hi_b - s0 < 32u ? hi_b - s0 : 32u;
+      const uint32_t mask = (b - a == 32u) ? 0xFFFFFFFFu : (((1u << (b - a)) - 1u) << a);
+      const uint32_t old = atomicOr(&c.bitmap[wi], mask);
+      if (old & mask) ok = false;
+    }
+  }
+  if (!block_all(ok, c)) return KIND_WAVE;
+  const uint32_t lg0 = (c.words[0] >> 16) & 0xFFu;
+  const bool uni = (lg == lg0) && (base == (t << lg0));
+  if (block_all(uni, c)) {
+    c.lg = lg0;
+    return KIND_UNIFORM;
+  }
+  return have_lookup ? KIND_LOOKUP : KIND_WAVE;
+}
+
+// Zero the counting table for `kind` and (KIND_LOOKUP) build the lane-replicated lookup:
+// look[v * RR + j] = byte address of sub-bin base(v) + (j mod r(v)), j = lane mod RR.
+__device__ void stage_table(uint32_t *lds, const Params &P, Ctl &c, uint32_t kind, uint32_t lg, uint32_t S) {
+  const uint32_t t = threadIdx.x;
+  if (kind == KIND_WAVE) {
+    zero_words(lds, kWaves * 256);
+  } else if (kind == KIND_UNIFORM) {
+    zero_words(lds, 256u << lg);
+  } else {
+    zero_words(lds, (S + 3u) & ~3u);
+    const uint32_t w = c.words[t];
+    const uint32_t base = w & 0xFFFFu, rmask = (1u << ((w >> 16) & 0xFFu)) - 1u;
+    const uint32_t rr_lg = P.look_rr_lg, rr = 1u << rr_lg;
+    uint32_t *look = lds + P.look_off + (t << rr_lg);
+    for (uint32_t j = 0; j < rr; ++j) {
+      const uint32_t jj = (j + t) & (rr - 1u);     // rotate so a wavefront's stores hit distinct banks
+      look[jj] = (base + (jj & rmask)) << 2;
+    }
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------ the hot loop
+
+template <int KIND>
+struct Adder {
+  uint32_t a;      // KIND_WAVE: byte offset of this wave's table; UNIFORM: (lane mod r) * 4;
+                   // LOOKUP: byte offset of this lane's column of the lookup table
+  uint32_t s;      // UNIFORM: lg + 2; LOOKUP: log2(RR) + 2
+  __device__ __forceinline__ void add(uint32_t *lds, uint32_t v) const {
+    uint32_t byte_addr;
+    if (KIND == KIND_WAVE) {
+      byte_addr = a + (v << 2);
+    } else if (KIND == KIND_UNIFORM) {
+      byte_addr = (v << s) | a;
+    } else {
+      byte_addr = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(lds) + ((v << s) + a));
+    }
+    __hip_atomic_fetch_add(reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(lds) + byte_addr), 1u,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+  __device__ __forceinline__ void add16(uint32_t *lds, const u32x4 &x) const {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t d = x[q];
+      add(lds, d & 255u);
+      add(lds, (d >> 8) & 255u);
+      add(lds, (d >> 16) & 255u);
+      add(lds, d >> 24);
+    }
+  }
+};
+
+// Add bytes [p, p + len) into the table.  The 16-byte aligned middle goes through wide
+// loads; the unaligned head and tail (< 16 bytes each) through single-byte loads.
+template <int KIND, int U>
+__device__ void run_range(uint32_t *lds, const Adder<KIND> &ad, const uint8_t *p, uint64_t len) {
+  const uint32_t t = threadIdx.x;
+  const uintptr_t a0 = reinterpret_cast<uintptr_t>(p), a1 = a0 + len;
+  const uintptr_t b0 = (a0 + 15u) & ~static_cast<uintptr_t>(15u), b1 = a1 & ~static_cast<uintptr_t>(15u);
+  gu8 *pg = (gu8 *)p;
+  if (b0 >= b1) {
+    for (uint64_t i = t; i < len; i += kBlock) ad.add(lds, pg[i]);
+    return;
+  }
+  if (t < b0 - a0) ad.add(lds, pg[t]);
+  if (t < a1 - b1) ad.add(lds, ((gu8 *)b1)[t]);
+  gu32x4 *v = (gu32x4 *)b0;
+  const uint64_t nv = (b1 - b0) >> 4;
+  uint64_t i = t;
+  for (; i + (U - 1) * kBlock < nv; i += U * kBlock) {
+    u32x4 x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) x[u] = __builtin_nontemporal_load(v + i + u * kBlock);
+#pragma unroll
+    for (int u = 0; u < U; ++u) ad.add16(lds, x[u]);
+  }
+  for (; i < nv; i += kBlock) ad.add16(lds, __builtin_nontemporal_load(v + i));
+}
+
+// Sum this thread's bin (value t) out of the table.
+__device__ uint32_t table_bin(const uint32_t *lds, const Ctl &c, uint32_t kind, uint32_t lg) {
+  const uint32_t t = threadIdx.x;
+  uint32_t h = 0;
+  if (kind == KIND_WAVE) {
+#pragma unroll
+    for (uint32_t w = 0; w < kWaves; ++w) h += lds[(w << 8) | t];
+  } else if (kind == KIND_UNIFORM) {
+    const uint32_t r = 1u << lg;
+    for (uint32_t j = 0; j < r; ++j) h += lds[(t << lg) | ((j + t) & (r - 1u))];   // rotated: distinct banks
+  } else {
+    const uint32_t w = c.words[t];
+    const uint32_t base = w & 0xFFFFu, r = 1u << ((w >> 16) & 0xFFu);
+    for (uint32_t j = 0; j < r; ++j) h += lds[base + j];
+  }
+  return h;
+}
+
+// ------------------------------------------------------------------ segments
+
+__device__ __forceinline__ SegDesc load_seg(const Params &P, uint32_t s) {
+  return (P.nseg == 1) ? P.seg0 : P.segs[s];
+}
+
+// Stage segment `sd`: pick the table kind (from the launch, or from the stream's decision)
+// and prepare the LDS.  Returns the kind; sets c.lg / c.used_mode / c.words.
+__device__ uint32_t begin_segment(uint32_t *lds, const Params &P, Ctl &c, const SegDesc &sd) {
+  const uint32_t t = threadIdx.x;
+  uint32_t kind;
+  uint32_t S = P.pat_S;
+  if (sd.chunk < 0) {
+    kind = P.kind;
+    if (kind == KIND_UNIFORM) c.lg = P.uni_lg;
+    if (kind == KIND_LOOKUP) c.words[t] = P.pat_words[t];
+    c.used_mode = (kind == KIND_WAVE) ? HIST_MODE_WAVEHIST : HIST_MODE_AHIST;
+    __syncthreads();
+  } else {
+    StreamDev *st = P.st + sd.stream_idx;
+    const int64_t j = (sd.chunk == kServerChunk) ? -2 : sd.chunk - 1 - (int64_t)st->lag;
+    uint32_t dmode;
+    if (sd.chunk == kServerChunk) {
+      // served request: the stream's latest decision, whatever has been published (no wait)
+      const Decision *d = &st->slots[0];
+      const uint32_t gen = ld_agent(&d->gen);
+      if (gen == 0) {
+        c.words[t] = t;
+        dmode = HIST_MODE_WAVEHIST;
+        S = 256;
+      } else {
+        c.words[t] = ld_agent(&d->words[t]);
+        dmode = ld_agent(&d->mode);
+        S = ld_agent(&d->S);
+      }
+    } else if (j < 0) {
+      // no history: per-wavefront kernel, identity pattern
+      c.words[t] = t;
+      dmode = HIST_MODE_WAVEHIST;
+      S = 256;
+    } else {
+      const Decision *d = &st->slots[(uint64_t)j % st->nslot];
+      if (t == 0) spin_until_u32(&d->gen, (uint32_t)(j + 1), P.diag);
+      __syncthreads();
+      c.words[t] = ld_agent(&d->words[t]);
+      dmode = ld_agent(&d->mode);
+      S = ld_agent(&d->S);
+    }
+    const uint32_t mode = P.forced ? P.forced : dmode;
+    __syncthreads();
+    if (mode == HIST_MODE_AHIST) {
+      kind = classify_pattern(c, S, st->rmax, P.pat_S, HIST_RMAX_MAX, P.look_words != 0);
+      if (kind == KIND_WAVE && t == 0) atomicAdd(&P.diag[0], 1u);
+    } else {
+      kind = KIND_WAVE;
+    }
+    if (t == 0) c.used_mode = (kind == KIND_WAVE) ? HIST_MODE_WAVEHIST : HIST_MODE_AHIST;
+    __syncthreads();
+  }
+  stage_table(lds, P, c, kind, c.lg, S);
+  return kind;
+}
+
+// Epilogue of a served request (thread t holds bin t of its histogram h): the stream's
+// running histogram grows by h (atomically: requests of one stream may finish in any order)
+// and the stream's decision is recomputed from h alone (a window of one request).  Concurrent
+// requests of one stream may overwrite each other's decision; any mix of words that passes
+// the device check is still a valid pattern, so counts stay exact.
+__device__ void server_epilogue(const Params &P, Ctl &c, uint32_t sidx, uint32_t h) {
+  const uint32_t t = threadIdx.x;
+  StreamDev *st = P.st + sidx;
+  atomicAdd(reinterpret_cast<unsigned long long *>(&st->acc[t]), (unsigned long long)h);
+  st_agent(&st->mw[t], (uint64_t)h);
+  const uint64_t N = block_sum_u64(h, c);
+  const uint64_t mx = block_max_u64(h, c);
+  const uint32_t mode = (100ull * mx > (uint64_t)st->theta * N) ? HIST_MODE_AHIST : HIST_MODE_WAVEHIST;
+  const uint32_t word = rule_p_word(h, N, st->S, st->rmax, c);
+  Decision *d = &st->slots[0];
+  st_agent(&d->words[t], word);
+  if (t == 0) {
+    st_agent(&d->S, st->S);
+    st_agent(&d->rmax, st->rmax);
+    st_agent(&d->mode, mode);
+  }
+  __threadfence();
+  __syncthreads();
+  if (t == 0) __hip_atomic_fetch_add(&d->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Stream epilogue for chunk k with histogram h (thread t holds bin t): Accumulator, moving
+// window, degeneracy switch and rule P (Sec. III.B, Sec. III.C), then the trace of what
+// chunk k ran with.  Epilogues of one stream run in chunk order.
+__device__ void stream_epilogue(const Params &P, Ctl &c, uint32_t sidx, int64_t k, uint32_t h) {
+  const uint32_t t = threadIdx.x;
+  StreamDev *st = P.st + sidx;
+  if (t == 0) spin_until_u64(&st->done, (uint64_t)k, P.diag);
+  __syncthreads();
+  const uint32_t W = st->W;
+  st_agent(&st->acc[t], ld_agent(&st->acc[t]) + (uint64_t)h);
+  uint32_t *ring = st->ring + (size_t)((uint64_t)k % W) * 256u;
+  const uint32_t old = ((uint64_t)k >= W) ? ld_agent(&ring[t]) : 0u;
+  st_agent(&ring[t], h);
+  const uint64_t mw = ld_agent(&st->mw[t]) + (uint64_t)h - (uint64_t)old;
+  st_agent(&st->mw[t], mw);
+  // degeneracy of the window: AHist iff some bin exceeds theta percent (strict)
+  const uint64_t N = block_sum_u64(mw, c);
+  const uint64_t mx = block_max_u64(mw, c);
+  const uint32_t mode = (100ull * mx > (uint64_t)st->theta * N) ? HIST_MODE_AHIST : HIST_MODE_WAVEHIST;
+  const uint32_t word = rule_p_word(mw, N, st->S, st->rmax, c);
+  Decision *d = &st->slots[(uint64_t)k % st->nslot];
+  st_agent(&d->words[t], word);
+  if (t == 0) {
+    st_agent(&d->S, st->S);
+    st_agent(&d->rmax, st->rmax);
+    st_agent(&d->mode, mode);
+  }
+  if ((uint64_t)k < st->trace_cap) {
+    st_agent(&st->pat_trace[(size_t)k * 256u + t], c.words[t]);
+    if (t == 0) st->mode_trace[k] = (uint8_t)c.used_mode;
+  }
+  __threadfence();
+  __syncthreads();
+  if (t == 0) {
+    __hip_atomic_store(&d->gen, (uint32_t)(k + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&st->done, (uint64_t)(k + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Merge this workgroup's table for segment s (after nt of its tiles) and finalize the
+// segment if this was its last tile.
+__device__ void flush_segment(uint32_t *lds, const Params &P, Ctl &c, uint32_t s, const SegDesc &sd, uint32_t kind,
+                              uint32_t lg, uint32_t nt) {
+  const uint32_t t = threadIdx.x;
+  __syncthreads();
+  const uint32_t h = table_bin(lds, c, kind, lg);
+  const uint32_t copies = 1u << P.clog2;
+  uint32_t *part = P.partial + ((size_t)s << (P.clog2 + 8));
+  if (h) __hip_atomic_fetch_add(&part[((blockIdx.x & (copies - 1u)) << 8) | t], h, __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_AGENT);
+  __threadfence();
+  __syncthreads();
+  if (t == 0) {
+    const uint32_t before = atomicAdd(&P.seg_done[s], nt);
+    c.flag = (before + nt == sd.ntiles) ? 1u : 0u;
+  }
+  __syncthreads();
+  if (c.flag) {
+    __threadfence();
+    uint32_t tot = 0;
+    for (uint32_t q = 0; q < copies; ++q) {
+      tot += ld_agent(&part[(q << 8) | t]);
+      st_agent(&part[(q << 8) | t], 0u);
+    }
+    if (sd.out) sd.out[t] = tot;
+    if (sd.acc) atomicAdd(reinterpret_cast<unsigned long long *>(&sd.acc[t]), (unsigned long long)tot);
+    if (sd.chunk >= 0) stream_epilogue(P, c, sd.stream_idx, sd.chunk, tot);
+    else if (sd.chunk == kServerChunk) server_epilogue(P, c, sd.stream_idx, tot);
+    if (t == 0) st_agent(&P.seg_done[s], 0u);
+  }
+  __syncthreads();
+}
+
+template <int KIND, int U>
+__device__ __forceinline__ void run_tile(uint32_t *lds, const Params &P, const Ctl &c, const uint8_t *p, uint64_t len) {
+  Adder<KIND> ad;
+  const uint32_t lane = lane_id();
+  if (KIND == KIND_WAVE) {
+    ad.a = wave_id() << 10;
+    ad.s = 0;
+  } else if (KIND == KIND_UNIFORM) {
+    ad.a = (lane & ((1u << c.lg) - 1u)) << 2;
+    ad.s = c.lg + 2u;
+  } else {
+    const uint32_t rr_lg = P.look_rr_lg;
+    ad.a = (P.look_off << 2) + ((lane & ((1u << rr_lg) - 1u)) << 2);
+    ad.s = rr_lg + 2u;
+  }
+  run_range<KIND, U>(lds, ad, p, len);
+}
+
+template <int U>
+__global__ void __launch_bounds__(kBlock) hist_main(const Params P) {
+  extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+  __shared__ Ctl c;
+  const uint32_t t = threadIdx.x;
+
+  uint32_t tile;
+  uint32_t tile_end = P.ntiles;
+  if (P.dynamic) {
+    if (t == 0) c.next_tile = atomicAdd(&P.ctr[0], 1u);
+    __syncthreads();
+    tile = c.next_tile;
+    __syncthreads();
+  } else if (P.nseg == 1) {
+    tile = blockIdx.x;               // one tile per workgroup
+    tile_end = tile < P.ntiles ? tile + 1 : tile;
+  } else {
+    // contiguous, byte-balanced tile range per workgroup: bounds stored after the tile map
+    const uint32_t *bounds = P.tile_seg + P.ntiles;
+    tile = bounds[blockIdx.x];
+    tile_end = bounds[blockIdx.x + 1];
+  }
+
+  uint32_t cur = kNone, kind = KIND_WAVE, lg = 0, nt = 0;
+  SegDesc sd;
+  sd.ntiles = 0;
+  while (tile < tile_end) {
+    const uint32_t s = (P.nseg == 1) ? 0u : P.tile_seg[tile];
+    if (s != cur) {
+      if (cur != kNone) flush_segment(lds, P, c, cur, sd, kind, lg, nt);
+      sd = load_seg(P, s);
+      kind = begin_segment(lds, P, c, sd);
+      lg = c.lg;
+      cur = s;
+      nt = 0;
+    }
+    uint32_t next_req = 0;
+    if (P.dynamic && t == 0) next_req = atomicAdd(&P.ctr[0], 1u);   // hide the grab behind this tile
+    const uint64_t off = (uint64_t)(tile - sd.tile0) * P.tile_bytes;
+    const uint64_t len = off < sd.size ? (sd.size - off < P.tile_bytes ? sd.size - off : P.tile_bytes) : 0u;
+    if (kind == KIND_WAVE) run_tile<KIND_WAVE, U>(lds, P, c, sd.ptr + off, len);
+    else if (kind == KIND_UNIFORM) run_tile<KIND_UNIFORM, U>(lds, P, c, sd.ptr + off, len);
+    else run_tile<KIND_LOOKUP, U>(lds, P, c, sd.ptr + off, len);
+    ++nt;
+    if (P.dynamic) {
+      __syncthreads();
+      if (t == 0) c.next_tile = next_req;
+      __syncthreads();
+      tile = c.next_tile;
+    } else {
+      ++tile;
+    }
+  }
+  if (cur != kNone) flush_segment(lds, P, c, cur, sd, kind, lg, nt);
+  if (P.dynamic) {
+    __syncthreads();
+    if (t == 0) {
+      const uint32_t e = atomicAdd(&P.ctr[1], 1u);
+      if (e == gridDim.x - 1) {
+        st_agent(&P.ctr[0], 0u);
+        st_agent(&P.ctr[1], 0u);
+      }
+    }
+  }
+}
+
+// Rule P as a stand-alone call: one workgroup reads a uint64[256] histogram and writes a
+// hist_pattern_t.
+__global__ void __launch_bounds__(kBlock) pattern_update_kernel(const uint64_t *h, uint32_t S, uint32_t rmax,
+                                                                 hist_pattern_t *out) {
+  __shared__ Ctl c;
+  const uint32_t t = threadIdx.x;
+  const uint64_t v = h[t];
+  const uint64_t N = block_sum_u64(v, c);
+  out->word[t] = rule_p_word(v, N, S, rmax, c);
+  if (t == 0) {
+    out->total_S = S;
+    out->rmax = rmax;
+  }
+}
+
+// ------------------------------------------------------------------ host-side launchers
+
+hipError_t launch_hist(const Params &P, const LaunchShape &sh, hipStream_t s) {
+  hipLaunchKernelGGL(hist_main<4>, dim3(sh.grid), dim3(kBlock), sh.lds_bytes, s, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_pattern_update(const uint64_t *h, uint32_t S, uint32_t rmax, hist_pattern_t *out, hipStream_t s) {
+  hipLaunchKernelGGL(pattern_update_kernel, dim3(1), dim3(kBlock), 0, s, h, S, rmax, out);
+  return hipGetLastError();
+}
+
+hipError_t set_kernel_attrs(uint32_t max_dyn_lds) {
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(&hist_main<4>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_dyn_lds);
+}
+
+hipError_t occupancy(uint32_t lds_bytes, int *blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, reinterpret_cast<const void *>(&hist_main<4>),
+                                                      kBlock, lds_bytes);
+}
+
+}  // namespace histmi

@@ -1,0 +1,135 @@
+// Internal host runtime of libhistmi (shared by the C ABI and the server).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "histmi.h"
+#include "histmi_dev.h"
+
+namespace histmi {
+
+// kernels.hip
+hipError_t launch_hist(const Params &P, const LaunchShape &sh, hipStream_t s);
+hipError_t launch_pattern_update(const uint64_t *h, uint32_t S, uint32_t rmax, hist_pattern_t *out, hipStream_t s);
+hipError_t set_kernel_attrs(uint32_t max_dyn_lds);
+hipError_t occupancy(uint32_t lds_bytes, int *blocks_per_cu);
+
+namespace rt {
+
+constexpr uint32_t kStaticLdsReserve = 8192;       // static LDS of the kernel (control block), with margin
+constexpr uint64_t kMaxSegBytes = 0xFFFFFFFFull;   // per-segment counts must fit the 32-bit partials
+constexpr uint32_t kFamilies = 3;                  // one tuning entry per Kind
+
+#define TRY_HIP(x)                               \
+  do {                                           \
+    hipError_t e_ = (x);                         \
+    if (e_ != hipSuccess) return HIST_EDEVICE;   \
+  } while (0)
+#define TRY(x)                        \
+  do {                                \
+    hist_status_t s_ = (x);           \
+    if (s_ != HIST_OK) return s_;     \
+  } while (0)
+
+inline hist_status_t dev_err(hipError_t e) { return e == hipSuccess ? HIST_OK : HIST_EDEVICE; }
+inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+inline uint32_t pow2ceil32(uint32_t x) {
+  uint32_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+inline uint32_t log2u(uint32_t x) {
+  uint32_t l = 0;
+  while ((1u << l) < x) ++l;
+  return l;
+}
+inline bool is_pow2(uint32_t x) { return x && !(x & (x - 1)); }
+inline bool mode_ok(hist_mode_t m) {
+  return m == HIST_MODE_AUTO || m == HIST_MODE_AHIST || m == HIST_MODE_WAVEHIST;
+}
+
+struct Tune {
+  uint32_t bpc;        // workgroups per CU
+  uint32_t tile_kib;   // multi-segment tile size
+  uint32_t copies;     // partial copies per segment (multi-segment launches)
+};
+extern Tune g_tune[kFamilies];
+extern uint32_t g_single_copies;
+
+// Library-owned device scratch of one launch context (a HIP stream, a graph or a server slot).
+// ctr, seg_done and partial are all-zero between launches: each launch's finalizers reset them.
+struct Scratch {
+  uint32_t *ctr = nullptr;        // 64 words
+  size_t ctr_cap = 0;
+  uint32_t *seg_done = nullptr;
+  size_t seg_cap = 0;
+  uint32_t *partial = nullptr;    // words
+  size_t partial_cap = 0;
+  uint8_t *desc = nullptr;        // device descriptors (segments, tile map, bounds)
+  size_t desc_cap = 0;
+  uint8_t *stage[2] = {nullptr, nullptr};   // pinned host staging of descriptors
+  size_t stage_cap[2] = {0, 0};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int turn = 0;
+};
+void free_scratch(Scratch *sc);
+
+struct DevCtx {
+  int dev = 0;
+  int cus = 0;
+  size_t lds_cu = 0;
+  uint32_t *diag = nullptr;   // device counters (64 words)
+  std::unordered_map<hipStream_t, Scratch *> scratch;
+};
+
+hist_status_t get_dev(DevCtx **out);
+hist_status_t alloc_scratch(Scratch *sc, size_t nseg, uint32_t copies, size_t desc_bytes, hipStream_t s);
+hist_status_t get_scratch(DevCtx *d, hipStream_t s, size_t nseg, uint32_t copies, size_t desc_bytes, Scratch **out);
+hist_status_t upload_desc(Scratch *sc, const void *host, size_t bytes, hipStream_t s);
+
+bool pattern_ok(const hist_pattern_t *p);
+void init_params(Params *P);
+// Kind and LDS layout of a history-free launch.
+hist_status_t select_kind(hist_mode_t mode, const hist_pattern_t *h_pat, Params *P);
+// Kind capacity and LDS layout of a launch whose chunks follow device-resident decisions.
+void stream_layout(uint32_t S, uint32_t rmax, hist_mode_t mode, Params *P);
+uint32_t lds_bytes(const Params &P);
+uint32_t blocks_per_cu(uint32_t family, uint32_t lds);
+
+// One segment cut into one tile per workgroup.
+hist_status_t run_single(DevCtx *d, Params &P, hipStream_t s);
+
+// Segments + tile map + per-workgroup bounds in one host buffer.
+struct MultiPlan {
+  std::vector<uint8_t> blob;   // SegDesc[n] | uint32 tile_seg[ntiles] | uint32 bounds[grid + 1]
+  uint32_t nseg = 0;
+  uint32_t ntiles = 0;
+  uint32_t grid = 0;
+  size_t seg_bytes = 0;
+  uint64_t tile = 0;
+};
+// segs: ptr/size/out/acc/chunk/stream_idx filled; tile0/ntiles are filled here.
+hist_status_t plan_multi(std::vector<SegDesc> &segs, uint64_t tile, uint32_t max_grid, bool balanced, MultiPlan *mp);
+// own: a dedicated scratch (already sized, descriptors already on the device) or nullptr.
+hist_status_t run_multi(DevCtx *d, Params &P, const MultiPlan &mp, uint32_t copies, hipStream_t s, Scratch *own,
+                        bool dynamic, bool upload);
+
+// Device-resident stream states: allocation and release.
+struct StreamAlloc {
+  StreamDev *d_st = nullptr;
+  uint32_t *d_ring = nullptr;
+  Decision *d_slots = nullptr;
+  uint8_t *d_mode_trace = nullptr;
+  uint32_t *d_pat_trace = nullptr;
+};
+hist_status_t stream_state_alloc(uint32_t count, uint32_t W, uint32_t theta, uint32_t S, uint32_t rmax, uint32_t lag,
+                                 uint32_t nslot, uint32_t trace_cap, StreamAlloc *sa);
+void stream_state_free(StreamAlloc *sa);
+
+}  // namespace rt
+}  // namespace histmi
