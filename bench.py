@@ -1,0 +1,232 @@
+"""Benchmark of the adaptive-histogram hot path on one MI355X.
+
+One step = one pass of a single stream of 66 chunks x 4 MiB (264 MiB of 8-bit pixels:
+clipped Normal(128, sigma) chunks with sigma 96/32/8/2, a fully degenerate chunk and a
+two-spike chunk) through the device-resident stream: per-chunk exact histograms, the
+Accumulator, the moving window, the degeneracy switch and the pattern recomputation, all in
+one persistent launch.  Inputs are resident in HBM before timing starts; two copies of the
+stream are used in turn so no step reads bytes the 256 MB cache just saw.
+
+Prints ONE JSON line.  Extra fields: a roofline of the dominant kernel (algorithmic bytes
+per launch over the launch time measured with HIP events on the launching stream), the CPU
+oracle timed on the host's cores, the same stream at pipeline lag 0 and with the paper's
+960-entry sub-histogram, a 1 MiB single image, and the 8192 x 8192 input matrix of the
+paper's Table 2.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+MIB = 1 << 20
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--lag", type=int, default=None, help="pipeline lag of the headline stream")
+    ap.add_argument("--theta", type=int, default=None)
+    ap.add_argument("--S", type=int, default=None)
+    ap.add_argument("--rmax", type=int, default=None)
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    return ap.parse_args()
+
+
+def tuned_defaults():
+    """Stream settings written by the autotuner (tuning.json beside the library), else built-ins."""
+    d = {"lag": 31, "theta_pct": 0, "S": 8192, "rmax": 32}
+    p = os.path.join(ROOT, "paper_1011_0235_amd", "tuning.json")
+    if os.path.exists(p):
+        with open(p) as f:
+            d.update(json.load(f).get("stream", {}))
+    return d
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(each GPU would take whole streams or images; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1011_0235_amd as hm
+    import synthgen as G
+
+    hm.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    info = hm.device_info()
+    tune = tuned_defaults()
+    lag = tune["lag"] if args.lag is None else args.lag
+    theta = tune["theta_pct"] if args.theta is None else args.theta
+    S = tune["S"] if args.S is None else args.S
+    rmax = tune["rmax"] if args.rmax is None else args.rmax
+
+    # ---- inputs: the config-2 stream, twice, resident in HBM
+    chunks = G.stream_chunks(4 * MIB)
+    host = np.concatenate(chunks)
+    nbytes = host.size
+    arenas = [torch.from_numpy(host).to(dev), None]
+    arenas[1] = arenas[0].clone()
+    nchunk = len(chunks)
+    bufs = [[(int(a.data_ptr()) + k * 4 * MIB, 4 * MIB) for k in range(nchunk)] for a in arenas]
+    outs = torch.zeros((nchunk, 256), dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def run_stream(st, steps, warmup, per_launch_events=True):
+        for i in range(warmup):
+            st.push_many(bufs[i & 1], d_out=outs, stream=stream)
+        torch.cuda.synchronize()
+        evs = []
+        t_start = torch.cuda.Event(enable_timing=True)
+        t_end = torch.cuda.Event(enable_timing=True)
+        t_start.record(stream)
+        for i in range(steps):
+            if per_launch_events:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+            st.push_many(bufs[(warmup + i) & 1], d_out=outs, stream=stream)
+            if per_launch_events:
+                e1.record(stream)
+                evs.append((e0, e1))
+        t_end.record(stream)
+        torch.cuda.synchronize()
+        total_ms = t_start.elapsed_time(t_end)
+        launch_ms = [a.elapsed_time(b) for a, b in evs]
+        return total_ms, launch_ms
+
+    # ---- headline
+    st = hm.Stream(W=1, theta_pct=theta, S=S, rmax=rmax, lag=lag, trace_cap=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    total_ms, launch_ms = run_stream(st, args.steps, args.warmup)
+    wall = time.perf_counter() - t0
+    ms_per_step = total_ms / args.steps
+    value = nbytes * args.steps / (total_ms * 1e-3) / 1e9
+
+    # parity of the last step's outputs against the oracle (exact)
+    from oracle import oracle as O
+    got = outs.cpu().numpy().astype(np.int64)
+    exp = np.stack([O.hist(c) for c in chunks]).astype(np.int64)
+    parity = bool(np.array_equal(got, exp))
+    snap, _, _ = st.read(0, stream=stream)
+    acc_ok = bool(np.array_equal(np.array(snap.acc, dtype=np.uint64),
+                                 exp.sum(axis=0).astype(np.uint64) * (args.warmup + args.steps)))
+    st.close()
+
+    # roofline of the dominant kernel: one persistent launch per step
+    avg_launch_ms = float(np.mean(launch_ms)) if launch_ms else ms_per_step
+    alg_bytes = nbytes + nchunk * 1024 + nchunk * 4096   # input + u32 outputs + u64 Accumulator read/write
+    achieved = alg_bytes / (avg_launch_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "histmi::hist_main<4>", "avg_launch_ms": round(avg_launch_ms, 5),
+                "alg_bytes_per_launch": alg_bytes}
+
+    res = {
+        "metric": "input GB/s and % of HBM peak (bit-exact); batched/served GB/s + p50/p99 latency",
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": "single stream, 66 chunks x 4 MiB (264 MiB u8): clipped Normal(128, sigma) with sigma "
+                               "96/32/8/2, one all-127 chunk, one two-spike chunk; adaptive switch, pattern from "
+                               "past chunks, per-chunk u32 histograms + u64 Accumulator on device",
+                   "chunk_bytes": 4 * MIB, "chunks": nchunk, "mode": "auto", "W": 1, "theta_pct": theta,
+                   "S": S, "rmax": rmax, "lag": lag},
+        "pct_of_hbm_peak": round(100.0 * value / HBM_PEAK_GBS, 2),
+        "parity_exact": parity and acc_ok,
+        "roofline": roofline,
+        "device": {"arch": info.arch.decode(), "cus": info.cu_count, "clock_khz": info.clock_khz},
+        "wall_s_timed": round(wall, 3),
+    }
+
+    # ---- CPU baseline: the oracle's plain counting loop on the host's cores
+    if not args.no_cpu:
+        threads = max(1, min(16, os.cpu_count() or 1))
+        secs, reps = 0.0, 0
+        while secs < max(1.0, 10.0 / threads) and reps < 200:
+            t, h = O.hist_timed(host, threads)
+            secs += t
+            reps += 1
+        assert np.array_equal(h.astype(np.int64), exp.sum(axis=0))
+        res["cpu_baseline"] = {"value": round(nbytes * reps / secs / 1e9, 3), "unit": "GB/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": "the same 264 MiB stream bytes in host RAM, %d passes of the plain C "
+                                         "counting loop split over %d threads (%.1f s wall)" % (reps, threads, secs)}
+
+    if not args.no_extras:
+        extras = {}
+        # the same stream, sequential semantics (pattern for chunk k+1 from chunk k) and paper sizes
+        for name, (l, th, s_, r_) in {"stream_lag0_auto": (0, theta, S, rmax),
+                                      "stream_paper960_theta45_lag0": (0, 45, 960, 8),
+                                      "stream_paper960_theta45_lag%d" % lag: (lag, 45, 960, 8)}.items():
+            st = hm.Stream(W=1, theta_pct=th, S=s_, rmax=r_, lag=l, trace_cap=0)
+            tms, _ = run_stream(st, 5, 2, per_launch_events=False)
+            st.close()
+            extras[name] = {"GB/s": round(nbytes * 5 / (tms * 1e-3) / 1e9, 1), "ms_per_step": round(tms / 5, 4)}
+        # one 1 MiB image (config 1): latency of one call, back to back
+        x = torch.from_numpy(G.image_1mib()).to(dev)
+        o1 = torch.zeros(256, dtype=torch.int32, device=dev)
+        for mode, nm in ((hm.MODE_AUTO, "auto"), (hm.MODE_WAVEHIST, "wavehist"), (hm.MODE_AHIST, "ahist_identity")):
+            for _ in range(5):
+                hm.hist_u8(x, o1, mode=mode, stream=stream)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(100):
+                hm.hist_u8(x, o1, mode=mode, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            extras["image_1mib_us_%s" % nm] = round(e0.elapsed_time(e1) * 10.0, 2)
+        # the paper's Table 2 inputs at 8192 x 8192 (64 MiB), each kernel
+        t2 = {}
+        pats = {"auto": (hm.MODE_AUTO, None), "wavehist": (hm.MODE_WAVEHIST, None),
+                "ahist_paper960": (hm.MODE_AHIST, hm.pattern_init(hm.PAT_PAPER960))}
+        for kind in G.TABLE2_KINDS:
+            xs = torch.from_numpy(G.table2_input(kind)).to(dev)
+            row = {}
+            for nm, (mode, pat) in pats.items():
+                for _ in range(3):
+                    hm.hist_u8(xs, o1, mode=mode, pattern=pat, stream=stream)
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(20):
+                    hm.hist_u8(xs, o1, mode=mode, pattern=pat, stream=stream)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                row[nm] = round(xs.numel() * 20 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+            t2[kind] = row
+            del xs
+        extras["table2_64mib_GBps"] = t2
+        res["extras"] = extras
+
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

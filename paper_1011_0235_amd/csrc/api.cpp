@@ -20,7 +20,7 @@ namespace rt {
 // Defaults from the gfx950 probes: the lane-cyclic table streams best with 2 workgroups of
 // 4 wavefronts per CU and 4 loads in flight per lane.
 Tune g_tune[kFamilies] = {{4, 256, 4}, {2, 256, 4}, {2, 256, 4}};
-uint32_t g_single_copies = 64;   // partial copies for a launch with one large segment
+uint32_t g_single_copies = 16;   // partial copies for a launch with one large segment
 
 static std::mutex g_mu;
 static std::unordered_map<int, DevCtx *> g_dev;
@@ -78,7 +78,11 @@ hist_status_t alloc_scratch(Scratch *sc, size_t nseg, uint32_t copies, size_t de
   TRY(ensure(&sc->ctr, &sc->ctr_cap, 64, s, true));
   TRY(ensure(&sc->seg_done, &sc->seg_cap, std::max<size_t>(nseg, 1), s, true));
   TRY(ensure(&sc->partial, &sc->partial_cap, std::max<size_t>(nseg, 1) * copies * 256, s, true));
-  if (desc_bytes) TRY(ensure(&sc->desc, &sc->desc_cap, desc_bytes, s, false));
+  if (desc_bytes) {
+    if (desc_bytes > sc->desc_cap) TRY(ensure(&sc->desc_buf, &sc->desc_cap, desc_bytes, s, false));
+    sc->desc = sc->desc_buf;
+    sc->cur = -1;
+  }
   return HIST_OK;
 }
 
@@ -86,7 +90,11 @@ void free_scratch(Scratch *sc) {
   if (sc->ctr) (void)hipFree(sc->ctr);
   if (sc->seg_done) (void)hipFree(sc->seg_done);
   if (sc->partial) (void)hipFree(sc->partial);
-  if (sc->desc) (void)hipFree(sc->desc);
+  if (sc->desc_buf) (void)hipFree(sc->desc_buf);
+  for (auto &e : sc->cache) {
+    if (e.dev) (void)hipFree(e.dev);
+    if (e.ev) (void)hipEventDestroy(e.ev);
+  }
   for (int k = 0; k < 2; ++k) {
     if (sc->stage[k]) (void)hipHostFree(sc->stage[k]);
     if (sc->ev[k]) (void)hipEventDestroy(sc->ev[k]);
@@ -112,9 +120,36 @@ hist_status_t get_scratch(DevCtx *d, hipStream_t s, size_t nseg, uint32_t copies
   return HIST_OK;
 }
 
-// Copy `bytes` of host data to sc->desc asynchronously through pinned staging (two buffers,
-// each reused only after its previous copy has finished).
+// Make the descriptors `host` available on the device and point sc->desc at them.  A set
+// identical to one of the last few uploaded is reused as is; otherwise the least recently
+// used cache entry is refilled through pinned staging (two buffers, each reused only after
+// its previous copy finished).
 hist_status_t upload_desc(Scratch *sc, const void *host, size_t bytes, hipStream_t s) {
+  ++sc->tick;
+  for (int i = 0; i < 4; ++i) {
+    Scratch::Cached &e = sc->cache[i];
+    if (e.dev && e.blob.size() == bytes && std::memcmp(e.blob.data(), host, bytes) == 0) {
+      e.used = sc->tick;
+      sc->desc = e.dev;
+      sc->cur = i;
+      return HIST_OK;
+    }
+  }
+  int vi = 0;
+  for (int i = 1; i < 4; ++i)
+    if (sc->cache[i].used < sc->cache[vi].used) vi = i;
+  Scratch::Cached *victim = &sc->cache[vi];
+  if (victim->ev) TRY_HIP(hipEventSynchronize(victim->ev));   // launches still reading it are done
+  else TRY_HIP(hipEventCreateWithFlags(&victim->ev, hipEventDisableTiming));
+  if (victim->cap < bytes) {
+    if (victim->dev) TRY_HIP(hipFree(victim->dev));
+    victim->dev = nullptr;
+    victim->cap = 0;
+    victim->blob.clear();
+    const size_t cap = std::max<size_t>(bytes, 1 << 16);
+    if (hipMalloc(&victim->dev, cap) != hipSuccess) return HIST_ENOMEM;
+    victim->cap = cap;
+  }
   const int k = sc->turn;
   sc->turn ^= 1;
   if (sc->ev[k]) TRY_HIP(hipEventSynchronize(sc->ev[k]));
@@ -129,8 +164,17 @@ hist_status_t upload_desc(Scratch *sc, const void *host, size_t bytes, hipStream
     sc->stage_cap[k] = cap;
   }
   std::memcpy(sc->stage[k], host, bytes);
-  TRY_HIP(hipMemcpyAsync(sc->desc, sc->stage[k], bytes, hipMemcpyHostToDevice, s));
+  TRY_HIP(hipMemcpyAsync(victim->dev, sc->stage[k], bytes, hipMemcpyHostToDevice, s));
   TRY_HIP(hipEventRecord(sc->ev[k], s));
+  victim->blob.assign(static_cast<const uint8_t *>(host), static_cast<const uint8_t *>(host) + bytes);
+  victim->used = sc->tick;
+  sc->desc = victim->dev;
+  sc->cur = vi;
+  return HIST_OK;
+}
+
+hist_status_t desc_used(Scratch *sc, hipStream_t s) {
+  if (sc->cur >= 0) TRY_HIP(hipEventRecord(sc->cache[sc->cur].ev, s));
   return HIST_OK;
 }
 
@@ -214,12 +258,23 @@ void stream_layout(uint32_t S, uint32_t rmax, hist_mode_t mode, Params *P) {
   set_lds(P, std::max<uint32_t>(S, 256u * rmax), !saturated, rmax > 32 ? 6 : 5);
 }
 
-uint32_t lds_bytes(const Params &P) { return (P.table_words + P.look_words) * 4u; }
+uint32_t lds_bytes(const Params &P) { return (P.table_words + P.look_words) * 4u + ctl_bytes(); }
 
 // Workgroups per CU: the family's tuned value, capped by what fits.
 uint32_t blocks_per_cu(uint32_t family, uint32_t lds) {
-  int occ = 1;
-  if (occupancy(lds, &occ) != hipSuccess || occ < 1) occ = 1;
+  static std::mutex mu;
+  static std::unordered_map<uint32_t, int> cache;   // dynamic LDS bytes -> resident workgroups per CU
+  int occ = 0;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(lds);
+    if (it != cache.end()) occ = it->second;
+  }
+  if (occ == 0) {
+    if (occupancy(lds, &occ) != hipSuccess || occ < 1) occ = 1;
+    std::lock_guard<std::mutex> lk(mu);
+    cache[lds] = occ;
+  }
   return std::max<uint32_t>(1, std::min<uint32_t>(g_tune[family].bpc, (uint32_t)occ));
 }
 
@@ -236,6 +291,7 @@ hist_status_t run_single(DevCtx *d, Params &P, hipStream_t s) {
   P.seg0.tile0 = 0;
   P.seg0.ntiles = ntiles;
   P.nseg = 1;
+  P.single = 1;
   P.ntiles = ntiles;
   P.tile_bytes = tile;
   P.dynamic = 0;
@@ -296,12 +352,13 @@ hist_status_t plan_multi(std::vector<SegDesc> &segs, uint64_t tile, uint32_t max
 hist_status_t run_multi(DevCtx *d, Params &P, const MultiPlan &mp, uint32_t copies, hipStream_t s, Scratch *own,
                         bool dynamic, bool upload) {
   Scratch *sc = own;
-  if (!sc) TRY(get_scratch(d, s, mp.nseg, copies, mp.blob.size(), &sc));
-  else TRY(alloc_scratch(sc, mp.nseg, copies, mp.blob.size(), s));
+  if (!sc) TRY(get_scratch(d, s, mp.nseg, copies, 0, &sc));
+  else TRY(alloc_scratch(sc, mp.nseg, copies, upload ? 0 : mp.blob.size(), s));
   if (upload) TRY(upload_desc(sc, mp.blob.data(), mp.blob.size(), s));
   P.segs = reinterpret_cast<const SegDesc *>(sc->desc);
   P.tile_seg = reinterpret_cast<const uint32_t *>(sc->desc + mp.seg_bytes);
   P.nseg = mp.nseg;
+  P.single = 0;
   P.ntiles = mp.ntiles;
   P.tile_bytes = mp.tile;
   P.dynamic = dynamic ? 1u : 0u;
@@ -311,7 +368,8 @@ hist_status_t run_multi(DevCtx *d, Params &P, const MultiPlan &mp, uint32_t copi
   P.partial = sc->partial;
   P.diag = d->diag;
   const LaunchShape sh{mp.grid, lds_bytes(P), 4};
-  return dev_err(launch_hist(P, sh, s));
+  TRY(dev_err(launch_hist(P, sh, s)));
+  return upload ? desc_used(sc, s) : HIST_OK;
 }
 
 hist_status_t stream_state_alloc(uint32_t count, uint32_t W, uint32_t theta, uint32_t S, uint32_t rmax, uint32_t lag,
@@ -604,7 +662,9 @@ hist_status_t hist_stream_create(hist_stream_t **out, const hist_stream_config_t
   TRY(get_dev(&d));
   hist_stream *st = new hist_stream();
   st->cfg = c;
-  st->nslot = c.lag + 2;   // a slot is reused only after the chunk that needed it has finished
+  // one launch never reuses a decision slot: a launch spans at most kMaxChunksPerLaunch chunks
+  // plus the lag + 1 decisions made before it
+  st->nslot = c.lag + 2 + kMaxChunksPerLaunch;
   const hist_status_t r = stream_state_alloc(1, c.W, c.theta_pct, c.S, c.rmax, c.lag, st->nslot, c.trace_cap, &st->sa);
   if (r != HIST_OK) {
     delete st;
@@ -627,7 +687,8 @@ hist_status_t hist_stream_push(hist_stream_t *st, const void *d_chunk, size_t n,
   P.seg0.ptr = static_cast<const uint8_t *>(d_chunk);
   P.seg0.size = n;
   P.seg0.out = d_out_k;
-  P.seg0.chunk = (int64_t)st->pushed;
+  P.chunk_base = st->pushed;
+  P.seg0.chunk = 0;
   P.seg0.stream_idx = 0;
   TRY(run_single(d, P, static_cast<hipStream_t>(stream)));
   st->pushed += 1;
@@ -639,31 +700,47 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
   if (!st || !mode_ok(mode)) return HIST_EINVAL;
   if (count == 0) return HIST_OK;
   if (!h_ptrs || !h_sizes) return HIST_EINVAL;
+  for (uint32_t j = 0; j < count; ++j) {
+    if (h_sizes[j] > kMaxSegBytes) return HIST_EOVERFLOW;
+    if (h_sizes[j] && !h_ptrs[j]) return HIST_EINVAL;
+  }
   DevCtx *d;
   TRY(get_dev(&d));
-  Params P;
-  init_params(&P);
-  stream_layout(st->cfg.S, st->cfg.rmax, mode, &P);
-  P.st = st->sa.d_st;
-  const uint32_t fam = KIND_UNIFORM;
-  const uint64_t tile = (uint64_t)g_tune[fam].tile_kib * 1024;
-  const uint32_t maxg = (uint32_t)d->cus * blocks_per_cu(fam, lds_bytes(P));
-  std::vector<SegDesc> segs(count);
-  for (uint32_t j = 0; j < count; ++j) {
-    std::memset(&segs[j], 0, sizeof(SegDesc));
-    segs[j].ptr = static_cast<const uint8_t *>(h_ptrs[j]);
-    segs[j].size = h_sizes[j];
-    segs[j].out = d_out ? d_out + (size_t)j * 256 : nullptr;
-    segs[j].chunk = (int64_t)(st->pushed + j);
-    segs[j].stream_idx = 0;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (uint32_t first = 0; first < count; first += kMaxChunksPerLaunch) {
+    const uint32_t m = std::min<uint32_t>(kMaxChunksPerLaunch, count - first);
+    Params P;
+    init_params(&P);
+    stream_layout(st->cfg.S, st->cfg.rmax, mode, &P);
+    P.st = st->sa.d_st;
+    P.chunk_base = st->pushed;
+    const uint32_t fam = KIND_UNIFORM;
+    const uint32_t maxg = (uint32_t)d->cus * blocks_per_cu(fam, lds_bytes(P));
+    // tiles small enough that the lag + 1 chunks which may run at once still fill the grid
+    uint64_t total = 0;
+    for (uint32_t j = 0; j < m; ++j) total += h_sizes[first + j];
+    const uint64_t per_chunk = std::max<uint64_t>(1, total / m);
+    const uint64_t inflight = (uint64_t)std::min<uint32_t>(st->cfg.lag + 1, m);
+    uint64_t tile = (uint64_t)g_tune[fam].tile_kib * 1024;
+    const uint64_t fill = ceil_div(per_chunk * inflight, maxg);
+    tile = std::min<uint64_t>(tile, std::max<uint64_t>(16384, ceil_div(fill, 16384) * 16384));
+    std::vector<SegDesc> segs(m);
+    for (uint32_t j = 0; j < m; ++j) {
+      std::memset(&segs[j], 0, sizeof(SegDesc));
+      segs[j].ptr = static_cast<const uint8_t *>(h_ptrs[first + j]);
+      segs[j].size = h_sizes[first + j];
+      segs[j].out = d_out ? d_out + (size_t)(first + j) * 256 : nullptr;
+      segs[j].chunk = (int64_t)j;
+      segs[j].stream_idx = 0;
+    }
+    MultiPlan mp;
+    TRY(plan_multi(segs, tile, maxg, false, &mp));
+    const uint32_t copies = std::min<uint32_t>(64, pow2ceil32(std::max<uint32_t>(1, g_tune[fam].copies)));
+    // tiles are handed out in chunk order, so a chunk waiting for an earlier chunk's decision
+    // never waits on a workgroup that has not started
+    TRY(run_multi(d, P, mp, copies, s, nullptr, true, true));
+    st->pushed += m;
   }
-  MultiPlan mp;
-  TRY(plan_multi(segs, tile, maxg, false, &mp));
-  const uint32_t copies = std::min<uint32_t>(64, pow2ceil32(std::max<uint32_t>(1, g_tune[fam].copies)));
-  // tiles are handed out in chunk order, so a chunk waiting for an earlier chunk's decision
-  // never waits on a workgroup that has not started
-  TRY(run_multi(d, P, mp, copies, static_cast<hipStream_t>(stream), nullptr, true, true));
-  st->pushed += count;
   return HIST_OK;
 }
 
@@ -682,6 +759,8 @@ hist_status_t hist_stream_read(hist_stream_t *st, hist_stream_snapshot_t *snap, 
       Decision dec;
       TRY_HIP(hipMemcpy(&dec, st->sa.d_slots + (h.done - 1) % st->nslot, sizeof(dec), hipMemcpyDeviceToHost));
       snap->next_mode = dec.mode;
+      if (st->cfg.W == 1)
+        for (int v = 0; v < 256; ++v) snap->mw[v] = dec.hist[v];
       std::memcpy(snap->next_pattern.word, dec.words, sizeof(dec.words));
       snap->next_pattern.total_S = dec.S;
       snap->next_pattern.rmax = dec.rmax;

@@ -23,6 +23,7 @@ enum Kind : uint32_t {
 // derived from, read by the chunk that runs with it.
 struct Decision {
   uint32_t words[256];   // binning pattern words (hist_pattern_t encoding)
+  uint32_t hist[256];    // histogram of the producing chunk (the moving window when W = 1)
   uint32_t S, rmax;
   uint32_t mode;         // HIST_MODE_AHIST or HIST_MODE_WAVEHIST
   uint32_t gen;          // index of the producing chunk + 1; stored last (release)
@@ -31,7 +32,7 @@ struct Decision {
 // Device-resident state of one stream (Accumulator, moving window, decisions, traces).
 struct StreamDev {
   uint32_t W, theta, S, rmax, lag, nslot, trace_cap, lookup_rr;
-  uint64_t done;         // number of chunk epilogues completed (stored with release)
+  uint64_t done;         // chunk epilogues completed (W > 1: stored in order with release; W = 1: counted)
   uint64_t acc[256];
   uint64_t mw[256];
   uint32_t *ring;        // [W][256] histograms of the last W chunks
@@ -46,7 +47,7 @@ struct SegDesc {
   uint64_t size;
   uint32_t *out;         // uint32[256] overwritten with the histogram, or null
   uint64_t *acc;         // uint64[256] the histogram is added to, or null
-  int64_t chunk;         // >= 0: chunk index of an ordered stream; kServerChunk: server request; -1: none
+  int64_t chunk;         // >= 0: stream chunk index relative to Params::chunk_base; kServerChunk: server request; -1: none
   uint32_t tile0;        // first tile (launch-global index)
   uint32_t ntiles;       // >= 1 (an empty buffer still has one empty tile so it gets finalized)
   uint32_t stream_idx;   // index into Params::st for stream chunks and server requests
@@ -56,12 +57,13 @@ struct SegDesc {
 constexpr int64_t kServerChunk = -2;
 
 struct Params {
-  const SegDesc *segs;       // device array of nseg descriptors (unused when nseg == 1)
-  SegDesc seg0;              // the descriptor when nseg == 1
-  const uint32_t *tile_seg;  // device map tile -> segment, then per-workgroup tile bounds (unused when nseg == 1)
+  const SegDesc *segs;       // device array of nseg descriptors (unused when single)
+  SegDesc seg0;              // the descriptor when single
+  const uint32_t *tile_seg;  // device map tile -> segment, then per-workgroup tile bounds (unused when single)
   uint32_t nseg;
   uint32_t ntiles;
   uint64_t tile_bytes;
+  uint32_t single;           // 1: one buffer described by seg0, spread over the whole grid
   uint32_t dynamic;          // 1: tiles handed out in order by an atomic counter; 0: static
   uint32_t clog2;            // log2 of the partial copies per segment
   uint32_t *ctr;             // [0] next tile, [1] workgroups finished (both reset by the last one)
@@ -76,6 +78,7 @@ struct Params {
   uint32_t pat_words[256];
   // stream chunks and server requests
   StreamDev *st;             // array of stream states
+  uint64_t chunk_base;       // absolute index of relative chunk 0
   uint32_t forced;           // 0 = decided per chunk, else HIST_MODE_AHIST / HIST_MODE_WAVEHIST
   uint32_t pad;
   // LDS layout (in 32-bit words)

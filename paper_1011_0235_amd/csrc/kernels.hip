@@ -34,6 +34,12 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // instead of flat_load_*, which would also count against the LDS wait counter.
 typedef __attribute__((address_space(1))) const u32x4 gu32x4;
 typedef __attribute__((address_space(1))) const uint8_t gu8;
+// LDS addressed by integer byte address: the table base is folded into per-lane constants
+// once, so each byte costs one extract and one shift-add before its ds_add_u32.
+typedef __attribute__((address_space(3))) uint32_t lu32;
+__device__ __forceinline__ uint32_t lds_addr_of(const uint32_t *p) {
+  return (uint32_t)(uintptr_t)(const lu32 *)p;
+}
 
 // Small control block in static LDS.
 struct Ctl {
@@ -118,19 +124,28 @@ __device__ __forceinline__ void st_agent(T *p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Bounded spin by thread 0 until *p == want.  Returns false on timeout (counted in diag[1]).
+// Bounded spin by thread 0 until *p == want.  Polls with relaxed loads (no cache
+// invalidation per poll) and ends with one acquire fence.  Returns false on timeout
+// (counted in diag[1]); the callers then go on with what they have, which can only cost
+// speed or a stale trace, never counts.
 __device__ bool spin_until_u32(const uint32_t *p, uint32_t want, uint32_t *diag) {
-  for (uint32_t i = 0; i < (1u << 24); ++i) {
-    if (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == want) return true;
-    __builtin_amdgcn_s_sleep(2);
+  for (uint32_t i = 0; i < (1u << 22); ++i) {
+    if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == want) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      return true;
+    }
+    __builtin_amdgcn_s_sleep(8);
   }
   atomicAdd(&diag[1], 1u);
   return false;
 }
 __device__ bool spin_until_u64(const uint64_t *p, uint64_t want, uint32_t *diag) {
-  for (uint32_t i = 0; i < (1u << 24); ++i) {
-    if (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == want) return true;
-    __builtin_amdgcn_s_sleep(2);
+  for (uint32_t i = 0; i < (1u << 22); ++i) {
+    if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == want) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      return true;
+    }
+    __builtin_amdgcn_s_sleep(8);
   }
   atomicAdd(&diag[1], 1u);
   return false;
@@ -248,9 +263,10 @@ __device__ void stage_table(uint32_t *lds, const Params &P, Ctl &c, uint32_t kin
     const uint32_t base = w & 0xFFFFu, rmask = (1u << ((w >> 16) & 0xFFu)) - 1u;
     const uint32_t rr_lg = P.look_rr_lg, rr = 1u << rr_lg;
     uint32_t *look = lds + P.look_off + (t << rr_lg);
+    const uint32_t tb = lds_addr_of(lds);
     for (uint32_t j = 0; j < rr; ++j) {
       const uint32_t jj = (j + t) & (rr - 1u);     // rotate so a wavefront's stores hit distinct banks
-      look[jj] = (base + (jj & rmask)) << 2;
+      look[jj] = tb + ((base + (jj & rmask)) << 2);
     }
   }
   __syncthreads();
@@ -260,58 +276,124 @@ __device__ void stage_table(uint32_t *lds, const Params &P, Ctl &c, uint32_t kin
 
 template <int KIND>
 struct Adder {
-  uint32_t a;      // KIND_WAVE: byte offset of this wave's table; UNIFORM: (lane mod r) * 4;
-                   // LOOKUP: byte offset of this lane's column of the lookup table
+  uint32_t a;      // LDS byte address: KIND_WAVE: this wave's table; UNIFORM: table + (lane mod r) * 4;
+                   // LOOKUP: this lane's column of the lookup table
   uint32_t s;      // UNIFORM: lg + 2; LOOKUP: log2(RR) + 2
-  __device__ __forceinline__ void add(uint32_t *lds, uint32_t v) const {
-    uint32_t byte_addr;
+  __device__ __forceinline__ void add(uint32_t v) const {
+    uint32_t addr;
     if (KIND == KIND_WAVE) {
-      byte_addr = a + (v << 2);
+      addr = a + (v << 2);
     } else if (KIND == KIND_UNIFORM) {
-      byte_addr = (v << s) | a;
+      addr = (v << s) + a;
     } else {
-      byte_addr = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(lds) + ((v << s) + a));
+      addr = *(const lu32 *)(uintptr_t)((v << s) + a);   // absolute address of this lane's sub-bin
     }
-    __hip_atomic_fetch_add(reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(lds) + byte_addr), 1u,
-                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add((lu32 *)(uintptr_t)addr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
-  __device__ __forceinline__ void add16(uint32_t *lds, const u32x4 &x) const {
+  __device__ __forceinline__ void add16(const u32x4 &x) const {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const uint32_t d = x[q];
-      add(lds, d & 255u);
-      add(lds, (d >> 8) & 255u);
-      add(lds, (d >> 16) & 255u);
-      add(lds, d >> 24);
+      add(d & 255u);
+      add((d >> 8) & 255u);
+      add((d >> 16) & 255u);
+      add(d >> 24);
     }
   }
 };
 
-// Add bytes [p, p + len) into the table.  The 16-byte aligned middle goes through wide
-// loads; the unaligned head and tail (< 16 bytes each) through single-byte loads.
+// Count U 16-byte vectors per lane while the next U are already in flight: the loads of
+// step q + 1 are issued before the bytes of step q go into the table, so every wave keeps
+// U x 1 KiB of HBM reads outstanding while it works on the LDS.
 template <int KIND, int U>
-__device__ void run_range(uint32_t *lds, const Adder<KIND> &ad, const uint8_t *p, uint64_t len) {
+struct Pipe {
+  u32x4 cur[U];
+  __device__ __forceinline__ void load(gu32x4 *v, uint64_t i, uint64_t stride) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) cur[u] = __builtin_nontemporal_load(v + i + u * stride);
+  }
+};
+
+// Add bytes [p, p + len) into the table.  The 16-byte aligned middle goes through wide
+// loads (1 KiB per wavefront per load, U loads per step, next step prefetched); the
+// unaligned head and tail (< 16 bytes each) through single-byte loads.  `rot` rotates where
+// in the range the workgroup starts, so that workgroups working on equal-sized tiles at the
+// same time do not all address the same HBM channels.
+template <int KIND, int U>
+__device__ void run_range(uint32_t *lds, const Adder<KIND> &ad, const uint8_t *p, uint64_t len, uint32_t rot) {
   const uint32_t t = threadIdx.x;
   const uintptr_t a0 = reinterpret_cast<uintptr_t>(p), a1 = a0 + len;
   const uintptr_t b0 = (a0 + 15u) & ~static_cast<uintptr_t>(15u), b1 = a1 & ~static_cast<uintptr_t>(15u);
   gu8 *pg = (gu8 *)p;
   if (b0 >= b1) {
-    for (uint64_t i = t; i < len; i += kBlock) ad.add(lds, pg[i]);
+    for (uint64_t i = t; i < len; i += kBlock) ad.add(pg[i]);
     return;
   }
-  if (t < b0 - a0) ad.add(lds, pg[t]);
-  if (t < a1 - b1) ad.add(lds, ((gu8 *)b1)[t]);
+  if (t < b0 - a0) ad.add(pg[t]);
+  if (t < a1 - b1) ad.add(((gu8 *)b1)[t]);
   gu32x4 *v = (gu32x4 *)b0;
   const uint64_t nv = (b1 - b0) >> 4;
-  uint64_t i = t;
-  for (; i + (U - 1) * kBlock < nv; i += U * kBlock) {
-    u32x4 x[U];
+  constexpr uint64_t step = (uint64_t)U * kBlock;
+  const uint64_t nfull = nv / step;                  // whole steps of U x 4 KiB
+  if (nfull) {
+    const uint64_t r0 = (uint64_t)rot % nfull;
+    Pipe<KIND, U> a, b;
+    a.load(v, r0 * step + t, kBlock);
+    for (uint64_t q = 0; q < nfull; ++q) {
+      const bool more = q + 1 < nfull;
+      if (more) {
+        uint64_t s1 = q + 1 + r0;
+        if (s1 >= nfull) s1 -= nfull;
+        b.load(v, s1 * step + t, kBlock);
+      }
 #pragma unroll
-    for (int u = 0; u < U; ++u) x[u] = __builtin_nontemporal_load(v + i + u * kBlock);
-#pragma unroll
-    for (int u = 0; u < U; ++u) ad.add16(lds, x[u]);
+      for (int u = 0; u < U; ++u) ad.add16(a.cur[u]);
+      if (more) a = b;
+    }
   }
-  for (; i < nv; i += kBlock) ad.add16(lds, __builtin_nontemporal_load(v + i));
+  for (uint64_t i = nfull * step + t; i < nv; i += kBlock) ad.add16(__builtin_nontemporal_load(v + i));
+}
+
+// One buffer spread over the whole grid: workgroup g takes the 4 KiB blocks g, g + G,
+// g + 2G, ... of the aligned middle, U blocks per step (next step prefetched); workgroup 0
+// also takes the unaligned head and tail.
+template <int KIND, int U>
+__device__ void run_strided(uint32_t *lds, const Adder<KIND> &ad, const uint8_t *p, uint64_t len) {
+  const uint32_t t = threadIdx.x, g = blockIdx.x, G = gridDim.x;
+  const uintptr_t a0 = reinterpret_cast<uintptr_t>(p), a1 = a0 + len;
+  const uintptr_t b0 = (a0 + 15u) & ~static_cast<uintptr_t>(15u), b1 = a1 & ~static_cast<uintptr_t>(15u);
+  gu8 *pg = (gu8 *)p;
+  if (b0 >= b1) {
+    if (g == 0)
+      for (uint64_t i = t; i < len; i += kBlock) ad.add(pg[i]);
+    return;
+  }
+  if (g == 0) {
+    if (t < b0 - a0) ad.add(pg[t]);
+    if (t < a1 - b1) ad.add(((gu8 *)b1)[t]);
+  }
+  gu32x4 *v = (gu32x4 *)b0;
+  const uint64_t nv = (b1 - b0) >> 4;
+  const uint64_t stride = (uint64_t)G * kBlock;
+  // block base of this workgroup's s-th full step: g*256 + s*U*stride; full iff its last
+  // vector (lane 255 of block U-1) is inside
+  uint64_t base = (uint64_t)g * kBlock;
+  const uint64_t span = (uint64_t)(U - 1) * stride + (kBlock - 1);
+  if (base + span < nv) {
+    Pipe<KIND, U> a, b;
+    a.load(v, base + t, stride);
+    for (;;) {
+      const uint64_t nb = base + (uint64_t)U * stride;
+      const bool more = nb + span < nv;
+      if (more) b.load(v, nb + t, stride);
+#pragma unroll
+      for (int u = 0; u < U; ++u) ad.add16(a.cur[u]);
+      base = nb;
+      if (!more) break;
+      a = b;
+    }
+  }
+  for (uint64_t i = base + t; i < nv; i += stride) ad.add16(__builtin_nontemporal_load(v + i));
 }
 
 // Sum this thread's bin (value t) out of the table.
@@ -335,7 +417,7 @@ __device__ uint32_t table_bin(const uint32_t *lds, const Ctl &c, uint32_t kind, 
 // ------------------------------------------------------------------ segments
 
 __device__ __forceinline__ SegDesc load_seg(const Params &P, uint32_t s) {
-  return (P.nseg == 1) ? P.seg0 : P.segs[s];
+  return P.single ? P.seg0 : P.segs[s];
 }
 
 // Stage segment `sd`: pick the table kind (from the launch, or from the stream's decision)
@@ -352,7 +434,8 @@ __device__ uint32_t begin_segment(uint32_t *lds, const Params &P, Ctl &c, const 
     __syncthreads();
   } else {
     StreamDev *st = P.st + sd.stream_idx;
-    const int64_t j = (sd.chunk == kServerChunk) ? -2 : sd.chunk - 1 - (int64_t)st->lag;
+    const int64_t k = (int64_t)P.chunk_base + sd.chunk;
+    const int64_t j = (sd.chunk == kServerChunk) ? -2 : k - 1 - (int64_t)st->lag;
     uint32_t dmode;
     if (sd.chunk == kServerChunk) {
       // served request: the stream's latest decision, whatever has been published (no wait)
@@ -423,19 +506,26 @@ __device__ void server_epilogue(const Params &P, Ctl &c, uint32_t sidx, uint32_t
 
 // Stream epilogue for chunk k with histogram h (thread t holds bin t): Accumulator, moving
 // window, degeneracy switch and rule P (Sec. III.B, Sec. III.C), then the trace of what
-// chunk k ran with.  Epilogues of one stream run in chunk order.
+// chunk k ran with.  With a window of one chunk (W = 1) the decision after chunk k depends
+// on h_k alone, so epilogues of different chunks run independently; with W > 1 the moving
+// window is updated in chunk order.
 __device__ void stream_epilogue(const Params &P, Ctl &c, uint32_t sidx, int64_t k, uint32_t h) {
   const uint32_t t = threadIdx.x;
   StreamDev *st = P.st + sidx;
-  if (t == 0) spin_until_u64(&st->done, (uint64_t)k, P.diag);
-  __syncthreads();
   const uint32_t W = st->W;
-  st_agent(&st->acc[t], ld_agent(&st->acc[t]) + (uint64_t)h);
-  uint32_t *ring = st->ring + (size_t)((uint64_t)k % W) * 256u;
-  const uint32_t old = ((uint64_t)k >= W) ? ld_agent(&ring[t]) : 0u;
-  st_agent(&ring[t], h);
-  const uint64_t mw = ld_agent(&st->mw[t]) + (uint64_t)h - (uint64_t)old;
-  st_agent(&st->mw[t], mw);
+  atomicAdd(reinterpret_cast<unsigned long long *>(&st->acc[t]), (unsigned long long)h);
+  uint64_t mw;
+  if (W == 1) {
+    mw = h;
+  } else {
+    if (t == 0) spin_until_u64(&st->done, (uint64_t)k, P.diag);
+    __syncthreads();
+    uint32_t *ring = st->ring + (size_t)((uint64_t)k % W) * 256u;
+    const uint32_t old = ((uint64_t)k >= W) ? ld_agent(&ring[t]) : 0u;
+    st_agent(&ring[t], h);
+    mw = ld_agent(&st->mw[t]) + (uint64_t)h - (uint64_t)old;
+    st_agent(&st->mw[t], mw);
+  }
   // degeneracy of the window: AHist iff some bin exceeds theta percent (strict)
   const uint64_t N = block_sum_u64(mw, c);
   const uint64_t mx = block_max_u64(mw, c);
@@ -443,6 +533,7 @@ __device__ void stream_epilogue(const Params &P, Ctl &c, uint32_t sidx, int64_t 
   const uint32_t word = rule_p_word(mw, N, st->S, st->rmax, c);
   Decision *d = &st->slots[(uint64_t)k % st->nslot];
   st_agent(&d->words[t], word);
+  st_agent(&d->hist[t], h);
   if (t == 0) {
     st_agent(&d->S, st->S);
     st_agent(&d->rmax, st->rmax);
@@ -456,7 +547,8 @@ __device__ void stream_epilogue(const Params &P, Ctl &c, uint32_t sidx, int64_t 
   __syncthreads();
   if (t == 0) {
     __hip_atomic_store(&d->gen, (uint32_t)(k + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&st->done, (uint64_t)(k + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (W == 1) __hip_atomic_fetch_add(&st->done, (uint64_t)1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    else __hip_atomic_store(&st->done, (uint64_t)(k + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -479,43 +571,63 @@ __device__ void flush_segment(uint32_t *lds, const Params &P, Ctl &c, uint32_t s
   }
   __syncthreads();
   if (c.flag) {
-    __threadfence();
+    __threadfence();   // acquire: every workgroup's partial adds happen before these reads
+    // read the copies eight at a time (all eight loads in flight), then clear them
     uint32_t tot = 0;
-    for (uint32_t q = 0; q < copies; ++q) {
-      tot += ld_agent(&part[(q << 8) | t]);
-      st_agent(&part[(q << 8) | t], 0u);
+    if (copies >= 8) {
+      for (uint32_t q = 0; q < copies; q += 8) {
+        uint32_t x[8];
+#pragma unroll
+        for (uint32_t u = 0; u < 8; ++u) x[u] = part[((q + u) << 8) | t];
+#pragma unroll
+        for (uint32_t u = 0; u < 8; ++u) tot += x[u];
+      }
+    } else {
+      for (uint32_t q = 0; q < copies; ++q) tot += part[(q << 8) | t];
     }
+    for (uint32_t q = 0; q < copies; ++q) st_agent(&part[(q << 8) | t], 0u);
     if (sd.out) sd.out[t] = tot;
     if (sd.acc) atomicAdd(reinterpret_cast<unsigned long long *>(&sd.acc[t]), (unsigned long long)tot);
-    if (sd.chunk >= 0) stream_epilogue(P, c, sd.stream_idx, sd.chunk, tot);
+    if (sd.chunk >= 0) stream_epilogue(P, c, sd.stream_idx, (int64_t)P.chunk_base + sd.chunk, tot);
     else if (sd.chunk == kServerChunk) server_epilogue(P, c, sd.stream_idx, tot);
     if (t == 0) st_agent(&P.seg_done[s], 0u);
   }
   __syncthreads();
 }
 
-template <int KIND, int U>
-__device__ __forceinline__ void run_tile(uint32_t *lds, const Params &P, const Ctl &c, const uint8_t *p, uint64_t len) {
+template <int KIND>
+__device__ __forceinline__ Adder<KIND> make_adder(const uint32_t *lds, const Params &P, const Ctl &c) {
   Adder<KIND> ad;
   const uint32_t lane = lane_id();
+  const uint32_t tb = lds_addr_of(lds);
   if (KIND == KIND_WAVE) {
-    ad.a = wave_id() << 10;
+    ad.a = tb + (wave_id() << 10);
     ad.s = 0;
   } else if (KIND == KIND_UNIFORM) {
-    ad.a = (lane & ((1u << c.lg) - 1u)) << 2;
+    ad.a = tb + ((lane & ((1u << c.lg) - 1u)) << 2);
     ad.s = c.lg + 2u;
   } else {
     const uint32_t rr_lg = P.look_rr_lg;
-    ad.a = (P.look_off << 2) + ((lane & ((1u << rr_lg) - 1u)) << 2);
+    ad.a = tb + (P.look_off << 2) + ((lane & ((1u << rr_lg) - 1u)) << 2);
     ad.s = rr_lg + 2u;
   }
-  run_range<KIND, U>(lds, ad, p, len);
+  return ad;
+}
+
+template <int KIND, int U>
+__device__ __forceinline__ void run_tile(uint32_t *lds, const Params &P, const Ctl &c, const uint8_t *p, uint64_t len,
+                                         bool strided, uint32_t rot) {
+  const Adder<KIND> ad = make_adder<KIND>(lds, P, c);
+  if (strided) run_strided<KIND, U>(lds, ad, p, len);
+  else run_range<KIND, U>(lds, ad, p, len, rot);
 }
 
 template <int U>
 __global__ void __launch_bounds__(kBlock) hist_main(const Params P) {
+  // one dynamic LDS block: the counting table at address 0 (so table addresses need no
+  // base offset), the lookup table after it, the control block at the end
   extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
-  __shared__ Ctl c;
+  Ctl &c = *reinterpret_cast<Ctl *>(lds + P.table_words + P.look_words);
   const uint32_t t = threadIdx.x;
 
   uint32_t tile;
@@ -525,7 +637,7 @@ __global__ void __launch_bounds__(kBlock) hist_main(const Params P) {
     __syncthreads();
     tile = c.next_tile;
     __syncthreads();
-  } else if (P.nseg == 1) {
+  } else if (P.single) {
     tile = blockIdx.x;               // one tile per workgroup
     tile_end = tile < P.ntiles ? tile + 1 : tile;
   } else {
@@ -539,7 +651,7 @@ __global__ void __launch_bounds__(kBlock) hist_main(const Params P) {
   SegDesc sd;
   sd.ntiles = 0;
   while (tile < tile_end) {
-    const uint32_t s = (P.nseg == 1) ? 0u : P.tile_seg[tile];
+    const uint32_t s = P.single ? 0u : P.tile_seg[tile];
     if (s != cur) {
       if (cur != kNone) flush_segment(lds, P, c, cur, sd, kind, lg, nt);
       sd = load_seg(P, s);
@@ -550,11 +662,18 @@ __global__ void __launch_bounds__(kBlock) hist_main(const Params P) {
     }
     uint32_t next_req = 0;
     if (P.dynamic && t == 0) next_req = atomicAdd(&P.ctr[0], 1u);   // hide the grab behind this tile
-    const uint64_t off = (uint64_t)(tile - sd.tile0) * P.tile_bytes;
-    const uint64_t len = off < sd.size ? (sd.size - off < P.tile_bytes ? sd.size - off : P.tile_bytes) : 0u;
-    if (kind == KIND_WAVE) run_tile<KIND_WAVE, U>(lds, P, c, sd.ptr + off, len);
-    else if (kind == KIND_UNIFORM) run_tile<KIND_UNIFORM, U>(lds, P, c, sd.ptr + off, len);
-    else run_tile<KIND_LOOKUP, U>(lds, P, c, sd.ptr + off, len);
+    // a one-buffer static launch spreads the whole buffer over the grid; otherwise the
+    // workgroup takes its tile, starting at a rotated position
+    const bool strided = P.single && !P.dynamic;
+    uint64_t off = 0, len = sd.size;
+    if (!strided) {
+      off = (uint64_t)(tile - sd.tile0) * P.tile_bytes;
+      len = off < sd.size ? (sd.size - off < P.tile_bytes ? sd.size - off : P.tile_bytes) : 0u;
+    }
+    const uint32_t rot = blockIdx.x * 7u;
+    if (kind == KIND_WAVE) run_tile<KIND_WAVE, U>(lds, P, c, sd.ptr + off, len, strided, rot);
+    else if (kind == KIND_UNIFORM) run_tile<KIND_UNIFORM, U>(lds, P, c, sd.ptr + off, len, strided, rot);
+    else run_tile<KIND_LOOKUP, U>(lds, P, c, sd.ptr + off, len, strided, rot);
     ++nt;
     if (P.dynamic) {
       __syncthreads();
@@ -594,6 +713,8 @@ __global__ void __launch_bounds__(kBlock) pattern_update_kernel(const uint64_t *
 }
 
 // ------------------------------------------------------------------ host-side launchers
+
+uint32_t ctl_bytes() { return (uint32_t)((sizeof(Ctl) + 15) & ~(size_t)15); }
 
 hipError_t launch_hist(const Params &P, const LaunchShape &sh, hipStream_t s) {
   hipLaunchKernelGGL(hist_main<4>, dim3(sh.grid), dim3(kBlock), sh.lds_bytes, s, P);

@@ -18,12 +18,14 @@ hipError_t launch_hist(const Params &P, const LaunchShape &sh, hipStream_t s);
 hipError_t launch_pattern_update(const uint64_t *h, uint32_t S, uint32_t rmax, hist_pattern_t *out, hipStream_t s);
 hipError_t set_kernel_attrs(uint32_t max_dyn_lds);
 hipError_t occupancy(uint32_t lds_bytes, int *blocks_per_cu);
+uint32_t ctl_bytes();   // control block at the end of the dynamic LDS
 
 namespace rt {
 
 constexpr uint32_t kStaticLdsReserve = 8192;       // static LDS of the kernel (control block), with margin
 constexpr uint64_t kMaxSegBytes = 0xFFFFFFFFull;   // per-segment counts must fit the 32-bit partials
 constexpr uint32_t kFamilies = 3;                  // one tuning entry per Kind
+constexpr uint32_t kMaxChunksPerLaunch = 1024;     // stream chunks in one persistent launch, at most
 
 #define TRY_HIP(x)                               \
   do {                                           \
@@ -70,13 +72,28 @@ struct Scratch {
   size_t seg_cap = 0;
   uint32_t *partial = nullptr;    // words
   size_t partial_cap = 0;
-  uint8_t *desc = nullptr;        // device descriptors (segments, tile map, bounds)
+  uint8_t *desc = nullptr;        // device descriptors the next launch reads (segments, tile map, bounds)
+  uint8_t *desc_buf = nullptr;    // dedicated descriptor buffer (graphs), owned
   size_t desc_cap = 0;
   uint8_t *stage[2] = {nullptr, nullptr};   // pinned host staging of descriptors
   size_t stage_cap[2] = {0, 0};
   hipEvent_t ev[2] = {nullptr, nullptr};
   int turn = 0;
+  // recently uploaded descriptor sets, each in its own device buffer (an identical set is
+  // reused without a copy); `desc` points at the one the next launch uses
+  struct Cached {
+    std::vector<uint8_t> blob;
+    uint8_t *dev = nullptr;
+    size_t cap = 0;
+    uint64_t used = 0;
+    hipEvent_t ev = nullptr;      // recorded after the last launch that read this entry
+  };
+  Cached cache[4];
+  int cur = -1;                   // cache entry `desc` points at (-1: desc_buf)
+  uint64_t tick = 0;
 };
+// After a launch that read sc->desc: mark the cache entry as in use until `s` gets there.
+hist_status_t desc_used(Scratch *sc, hipStream_t s);
 void free_scratch(Scratch *sc);
 
 struct DevCtx {

@@ -1,0 +1,136 @@
+"""GPU parity of batched histograms (many slices in one asynchronous call, Sec. III.B):
+every output against the oracle, uneven and empty images, byte-packed (unaligned) arenas,
+all modes, and HIP-graph replays with eager work between them."""
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+import synthgen as G
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def run_batch(hm, arena, offs, sizes, mode=0, pattern=None):
+    d = dev(arena)
+    base = int(d.data_ptr())
+    bufs = [(base + int(o), int(n)) for o, n in zip(offs, sizes)]
+    out = torch.full((len(bufs), 256), -1, dtype=torch.int32, device="cuda")
+    hm.hist_batch(bufs, out, mode=mode, pattern=pattern)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+
+
+@pytest.mark.parametrize("align", [256, 1])
+def test_batch_config4_shapes(hm, align):
+    specs = G.batch_specs(96, 64, 1024)          # config-4 distributions, sides up to 1024
+    arena, offs, sizes = G.batch_arena(specs, align=align)
+    exp = O.hist_many(arena, offs, sizes).astype(np.int64)
+    for mode, pat in ((hm.MODE_AUTO, None), (hm.MODE_WAVEHIST, None), (hm.MODE_AHIST, None),
+                      (hm.MODE_AHIST, hm.pattern_init(hm.PAT_PAPER960))):
+        got = run_batch(hm, arena, offs, sizes, mode, pat)
+        assert np.array_equal(got, exp), (align, mode)
+
+
+def test_batch_uneven_with_empty_and_large(hm):
+    g = np.random.default_rng(3)
+    sizes = [0, 1, 15, 16, 17, 4096, 0, (16 << 20) + 3, 1 << 20, 777, 0, 65536 * 3 + 5]
+    offs, pos = [], 0
+    for n in sizes:
+        pos += int(g.integers(0, 16))
+        offs.append(pos)
+        pos += n
+    arena = g.integers(0, 256, size=pos + 16, dtype=np.uint8)
+    arena[offs[7]:offs[7] + (1 << 20)] = 9          # a degenerate stretch inside the big image
+    exp = O.hist_many(arena, offs, sizes).astype(np.int64)
+    for mode in (hm.MODE_AUTO, hm.MODE_WAVEHIST, hm.MODE_AHIST):
+        assert np.array_equal(run_batch(hm, arena, offs, sizes, mode), exp), mode
+
+
+def test_batch_many_tiny(hm):
+    g = np.random.default_rng(4)
+    sizes = g.integers(0, 300, size=3000)
+    offs = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+    arena = g.integers(0, 256, size=int(sizes.sum()) + 1, dtype=np.uint8)
+    exp = O.hist_many(arena, offs, sizes).astype(np.int64)
+    assert np.array_equal(run_batch(hm, arena, offs, sizes), exp)
+
+
+def test_batch_graph_replays(hm):
+    specs = G.batch_specs(64, 64, 512)
+    arena, offs, sizes = G.batch_arena(specs, align=256)
+    d = dev(arena)
+    base = int(d.data_ptr())
+    bufs = [(base + int(o), int(n)) for o, n in zip(offs, sizes)]
+    out = torch.full((len(bufs), 256), -1, dtype=torch.int32, device="cuda")
+    graph = hm.BatchGraph(bufs, out, mode=hm.MODE_AUTO)
+    exp = O.hist_many(arena, offs, sizes).astype(np.int64)
+    for rep in range(5):
+        out.fill_(-1)
+        graph.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy().astype(np.int64), exp), rep
+        # eager work between replays on the same buffers (also changes them, then restores)
+        tmp = torch.zeros(256, dtype=torch.int32, device="cuda")
+        hm.hist_u8(d, tmp)
+        d.add_(1)
+        graph.launch()
+        torch.cuda.synchronize()
+        shifted = O.hist_many((arena + 1).astype(np.uint8), offs, sizes).astype(np.int64)
+        assert np.array_equal(out.cpu().numpy().astype(np.int64), shifted), rep
+        d.sub_(1)
+    graph.close()
+
+
+def test_batch_sampled_full_size_config4(hm):
+    # the full config-4 batch (4096 images, about 3.85 GB), generated on the device; a sample of
+    # images is checked against the oracle one by one, and every output against sum == size
+    specs = G.batch_specs(4096)
+    sizes = np.array([s.size for s in specs], dtype=np.int64)
+    offs = np.zeros_like(sizes)
+    offs[1:] = np.cumsum((sizes + 255) // 256 * 256)[:-1]
+    total = int(offs[-1] + sizes[-1])
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(G.ROOT_SEED)
+    arena = torch.randint(0, 256, (total,), dtype=torch.uint8, device="cuda", generator=gen)
+    # make a third of the images degenerate-heavy (90 % one value) so every kernel path runs
+    for j in range(0, 4096, 3):
+        n = int(sizes[j])
+        arena[int(offs[j]):int(offs[j]) + (9 * n) // 10] = j % 256
+    base = int(arena.data_ptr())
+    bufs = [(base + int(o), int(n)) for o, n in zip(offs, sizes)]
+    out = torch.full((4096, 256), -1, dtype=torch.int32, device="cuda")
+    hm.hist_batch(bufs, out, mode=hm.MODE_AUTO)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.int64)
+    assert np.array_equal(got.sum(axis=1), sizes)
+    rng = np.random.default_rng(5)
+    sample = sorted(set(rng.integers(0, 4096, 40).tolist()) | {0, 4095, int(np.argmax(sizes))})
+    for j in sample:
+        host = arena[int(offs[j]):int(offs[j] + sizes[j])].cpu().numpy()
+        assert np.array_equal(got[j], O.hist(host).astype(np.int64)), j
+
+
+def test_batch_errors(hm):
+    out = torch.zeros((2, 256), dtype=torch.int32, device="cuda")
+    with pytest.raises(hm.HistError) as e:
+        hm.hist_batch([(0, 10), (0, 0)], out)
+    assert e.value.status == hm.EINVAL
+    with pytest.raises(hm.HistError) as e:
+        hm.hist_batch([(int(out.data_ptr()), 1 << 32)], out)
+    assert e.value.status == hm.EOVERFLOW
+
+
+@pytest.mark.parametrize("n", [0, 5, 300_000, 5 << 20])
+def test_batch_of_one(hm, n):
+    # a one-buffer batch goes through the descriptor table like any other batch
+    host = G.uniform_bytes(n + 3, G.rng(6, n))
+    for mode in (hm.MODE_AUTO, hm.MODE_WAVEHIST):
+        got = run_batch(hm, host, [3], [n], mode)
+        assert np.array_equal(got[0], O.hist(host[3:3 + n]).astype(np.int64)), (n, mode)

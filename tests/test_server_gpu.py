@@ -1,0 +1,153 @@
+"""GPU tests of the continuous-batching server: every request's histogram equals the oracle
+and equals the same request run alone (tolerance 0: counts are integers); each stream id's
+running uint64 histogram equals the oracle sum of its requests; admission never exceeds the
+HBM budget or the slot limit; micro-batches overlap; destroy cancels queued requests."""
+
+import threading
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+import synthgen as G
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def pools(n_streams, pool_bytes):
+    return [G.serve_pool(s, pool_bytes, piece=1 << 18) for s in range(n_streams)]
+
+
+def requests(n, n_streams, pool_bytes, seed, size_hi=None):
+    g = np.random.default_rng(seed)
+    hi = size_hi or pool_bytes
+    out = []
+    for _ in range(n):
+        size = int(np.floor(np.exp(g.uniform(np.log(1), np.log(hi)))))
+        if g.random() < 0.05:
+            size = 0
+        sid = int(g.integers(0, n_streams))
+        off = int(g.integers(0, pool_bytes - size + 1))
+        out.append((sid, off, size))
+    return out
+
+
+def test_alone_equals_mix_equals_oracle(hm):
+    n_streams, pool_bytes = 8, 4 << 20
+    hp = pools(n_streams, pool_bytes)
+    dp = [torch.from_numpy(p).cuda() for p in hp]
+    reqs = requests(400, n_streams, pool_bytes, 1)
+    # alone: one hist_u8 per request
+    alone = torch.zeros((len(reqs), 256), dtype=torch.int32, device="cuda")
+    for i, (sid, off, n) in enumerate(reqs):
+        hm.hist_u8(int(dp[sid].data_ptr()) + off, alone[i], n=n)
+    torch.cuda.synchronize()
+    # mixed: all through the server at once, submitted from two threads
+    sv = hm.Server(hbm_budget_bytes=8 << 20, max_slots=64, n_stream_ids=n_streams, n_hip_streams=3, max_batch=16,
+                   S=960, rmax=8)
+    mix = torch.full((len(reqs), 256), -1, dtype=torch.int32, device="cuda")
+    tickets = [0] * len(reqs)
+
+    def submit(part):
+        for i in part:
+            sid, off, n = reqs[i]
+            tickets[i] = sv.submit(sid, int(dp[sid].data_ptr()) + off, d_out=mix[i], n=n)
+
+    th = [threading.Thread(target=submit, args=(range(k, len(reqs), 2),)) for k in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    sv.drain()
+    for i, tk in enumerate(tickets):
+        r = sv.poll(tk)
+        assert r.status == hm.OK and r.bytes == reqs[i][2]
+        assert r.t_submit_ns <= r.t_admit_ns <= r.t_done_ns
+    a = alone.cpu().numpy().astype(np.int64)
+    m = mix.cpu().numpy().astype(np.int64)
+    assert np.array_equal(a, m)
+    for i, (sid, off, n) in enumerate(reqs[:60]):
+        assert np.array_equal(m[i], O.hist(hp[sid][off:off + n]).astype(np.int64)), i
+    for s in range(n_streams):
+        exp = np.zeros(256, dtype=np.uint64)
+        for (sid, off, n) in reqs:
+            if sid == s:
+                exp += O.hist(hp[s][off:off + n])
+        assert np.array_equal(sv.stream_acc(s), exp), s
+    st = sv.stats()
+    assert st.completed == len(reqs) and st.canceled == 0
+    assert st.max_inflight_bytes <= 8 << 20 and st.max_inflight_requests <= 64
+    sv.close()
+
+
+def test_budget_and_slots_bound_admission(hm):
+    pool = torch.randint(0, 256, (8 << 20,), dtype=torch.uint8, device="cuda")
+    sv = hm.Server(hbm_budget_bytes=3 << 20, max_slots=5, n_stream_ids=2, n_hip_streams=2, max_batch=4)
+    outs = torch.zeros((200, 256), dtype=torch.int32, device="cuda")
+    tks = []
+    g = np.random.default_rng(2)
+    for i in range(200):
+        n = int(g.integers(1, 1 << 20))
+        tks.append(sv.submit(i % 2, int(pool.data_ptr()), d_out=outs[i], n=n))
+    # a request above the budget can never be admitted
+    st, _ = sv.try_submit(0, int(pool.data_ptr()), n=(3 << 20) + 1)
+    assert st == hm.EINVAL
+    sv.drain()
+    s = sv.stats()
+    assert s.completed == 200
+    assert s.max_inflight_bytes <= 3 << 20 and s.max_inflight_requests <= 5
+    assert s.max_concurrent_batches >= 1
+    host = pool.cpu().numpy()
+    o = outs.cpu().numpy().astype(np.int64)
+    for i in (0, 1, 57, 199):
+        n = int(sv.poll(tks[i]).bytes)
+        assert np.array_equal(o[i], O.hist(host[:n]).astype(np.int64))
+    sv.close()
+
+
+def test_wait_poll_and_cancel(hm):
+    pool = torch.randint(0, 256, (64 << 20,), dtype=torch.uint8, device="cuda")
+    sv = hm.Server(hbm_budget_bytes=64 << 20, max_slots=1, n_stream_ids=1, n_hip_streams=1, max_batch=1)
+    tks = [sv.submit(0, pool, n=64 << 20) for _ in range(50)]
+    r = sv.wait(tks[0])
+    assert r.status == hm.OK
+    # bad ids and tickets
+    st, _ = sv.try_submit(5, pool, n=16)
+    assert st == hm.EINVAL
+    with pytest.raises(hm.HistError):
+        sv.poll(10 ** 9)
+    sv.close()                      # cancels what is still queued, waits for the running batch
+    # a fresh server still works
+    sv2 = hm.Server(n_stream_ids=1)
+    out = torch.zeros(256, dtype=torch.int32, device="cuda")
+    t = sv2.submit(0, pool, d_out=out, n=1 << 20)
+    assert sv2.wait(t).status == hm.OK
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().astype(np.int64), O.hist(pool[:1 << 20].cpu().numpy()).astype(np.int64))
+    sv2.close()
+
+
+def test_server_decisions_stay_exact_under_degenerate_streams(hm):
+    # streams alternate degenerate and wide requests so decisions flip between kernels while
+    # requests of the same stream are in flight together
+    n = 1 << 18
+    bufs = [torch.full((n,), 7, dtype=torch.uint8, device="cuda"),
+            torch.randint(0, 256, (n,), dtype=torch.uint8, device="cuda")]
+    hosts = [b.cpu().numpy() for b in bufs]
+    sv = hm.Server(hbm_budget_bytes=64 << 20, max_slots=128, n_stream_ids=4, n_hip_streams=4, max_batch=8,
+                   theta_pct=45, S=960, rmax=8)
+    outs = torch.zeros((300, 256), dtype=torch.int32, device="cuda")
+    kinds = []
+    for i in range(300):
+        k = (i // 3) % 2
+        kinds.append(k)
+        sv.submit(i % 4, bufs[k], d_out=outs[i])
+    sv.drain()
+    o = outs.cpu().numpy().astype(np.int64)
+    ref = [O.hist(h).astype(np.int64) for h in hosts]
+    for i in range(300):
+        assert np.array_equal(o[i], ref[kinds[i]]), i
+    assert hm.diag().wait_timeouts == 0
+    sv.close()

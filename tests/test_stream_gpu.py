@@ -1,0 +1,187 @@
+"""GPU parity of device-resident streams (Sec. III.B Accumulator / moving window, Sec. III.C switch).
+
+Checked exactly against ``oracle.stream_reference`` on the same chunks: every per-chunk
+histogram, the Accumulator, the moving window, and the (mode, pattern) each chunk ran with,
+for several windows W, lags, sub-histogram budgets and forced modes, through both the
+one-launch-per-chunk path and the persistent multi-chunk path.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+import synthgen as G
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def config2_like(chunk_bytes, count=None):
+    """The config-2 chunk order (Normal sigma 96/32/8/2, a degenerate and a two-spike chunk)."""
+    return G.stream_chunks(chunk_bytes, count)
+
+
+def mixed_chunks(seed, count, max_bytes):
+    """Uneven chunk sizes (including empty and unaligned), alternating peaked and wide data."""
+    g = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        n = int(g.integers(0, max_bytes))
+        if k % 7 == 3:
+            n = 0
+        kind = k % 4
+        if kind == 0:
+            out.append(G.constant_bytes(n, int(g.integers(0, 256))))
+        elif kind == 1:
+            out.append(G.clipped_normal_bytes(n, float(g.uniform(0, 255)), float(g.uniform(1, 60)), g))
+        elif kind == 2:
+            out.append(G.mixture_bytes(n, float(g.uniform(0.3, 0.7)), int(g.integers(0, 256)), g))
+        else:
+            out.append(G.uniform_bytes(n, g))
+    return out
+
+
+def run_stream(hm, chunks, W, theta, S, rmax, lag, mode, many, unaligned=False):
+    st = hm.Stream(W=W, theta_pct=theta, S=S, rmax=rmax, lag=lag, trace_cap=len(chunks) + 4)
+    # pack all chunks into one arena (optionally at odd offsets)
+    offs, pos = [], 0
+    for c in chunks:
+        pos += (3 if unaligned else 0)
+        offs.append(pos)
+        pos += c.size
+        pos = (pos + 255) // 256 * 256 if not unaligned else pos
+    arena = np.zeros(pos + 16, dtype=np.uint8)
+    for o, c in zip(offs, chunks):
+        arena[o:o + c.size] = c
+    d = dev(arena)
+    base = int(d.data_ptr())
+    bufs = [(base + o, c.size) for o, c in zip(offs, chunks)]
+    outs = torch.full((len(chunks), 256), -1, dtype=torch.int32, device="cuda")
+    if many:
+        st.push_many(bufs, mode=mode, d_out=outs)
+    else:
+        for k, (p, n) in enumerate(bufs):
+            st.push(p, mode=mode, d_out=outs[k], n=n)
+    snap, modes, pats = st.read(len(chunks))
+    got = outs.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+    st.close()
+    return got, snap, modes, pats
+
+
+def check(hm, chunks, W=1, theta=45, S=960, rmax=8, lag=0, mode=0, many=True, unaligned=False):
+    ref = O.stream_reference(chunks, W=W, theta_pct=theta, S=S, rmax=rmax, lag=lag, mode=mode)
+    got, snap, modes, pats = run_stream(hm, chunks, W, theta, S, rmax, lag, mode, many, unaligned)
+    tag = (W, theta, S, rmax, lag, mode, many)
+    assert np.array_equal(got, ref["hists"].astype(np.int64)), tag
+    assert [int(x) for x in snap.acc] == ref["acc"], tag
+    assert [int(x) for x in snap.mw] == ref["mw"], tag
+    assert int(snap.chunks) == len(chunks)
+    assert [int(m) for m in modes] == ref["modes"], tag
+    assert [list(map(int, p)) for p in pats] == ref["patterns"], tag
+    # the snapshot's next decision is the decision after the last chunk
+    assert int(snap.next_mode) == O.decide_mode(ref["mw"], theta)
+    assert snap.next_pattern.words() == O.rule_p(ref["mw"], S, rmax)
+    d = hm.diag()
+    assert d.invalid_patterns == 0 and d.wait_timeouts == 0
+    return ref
+
+
+@pytest.mark.parametrize("many", [True, False])
+@pytest.mark.parametrize("lag", [0, 1, 3])
+def test_config2_order_small_chunks(hm, many, lag):
+    chunks = config2_like(1 << 16)
+    ref = check(hm, chunks, W=1, theta=45, S=960, rmax=8, lag=lag, many=many)
+    # the switch fires right after the degenerate and the two-spike chunk
+    ahist = [k for k, m in enumerate(ref["modes"]) if m == O.MODE_AHIST]
+    assert ahist == [33 + lag, 50 + lag]
+
+
+@pytest.mark.parametrize("W", [2, 4, 32])
+def test_windows(hm, W):
+    chunks = mixed_chunks(W, 40, 200_000)
+    check(hm, chunks, W=W, theta=45, S=960, rmax=8, lag=0, many=True)
+    check(hm, chunks, W=W, theta=30, S=2048, rmax=16, lag=2, many=True)
+
+
+@pytest.mark.parametrize("S,rmax", [(960, 8), (8192, 32), (300, 64), (16384, 64), (4096, 32)])
+def test_budgets(hm, S, rmax):
+    chunks = mixed_chunks(S + rmax, 24, 300_000)
+    check(hm, chunks, W=1, theta=45, S=S, rmax=rmax, lag=0, many=True, unaligned=True)
+    check(hm, chunks, W=3, theta=20, S=S, rmax=rmax, lag=1, many=False)
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_forced_modes(hm, mode):
+    chunks = mixed_chunks(50 + mode, 20, 150_000)
+    check(hm, chunks, W=1, theta=45, S=960, rmax=8, lag=0, mode=mode, many=True)
+    check(hm, chunks, W=2, theta=45, S=8192, rmax=32, lag=2, mode=mode, many=False)
+
+
+def test_theta_edges(hm):
+    # two-spike chunk: exactly 50 %: switches at theta 45 and 49, not at theta 50
+    two = G.two_spike_bytes(1 << 16, G.rng(9, 1))
+    chunks = [G.uniform_bytes(1 << 16, G.rng(9, 2)), two, G.uniform_bytes(1 << 16, G.rng(9, 3))]
+    for theta, want in ((45, 1), (49, 1), (50, 2), (0, 1), (100, 2)):
+        ref = check(hm, chunks, W=1, theta=theta, S=960, rmax=8, lag=0)
+        assert ref["modes"][2] == want
+
+
+def test_push_and_push_many_agree_across_calls(hm):
+    # a stream continued over several calls equals one long call
+    chunks = mixed_chunks(77, 30, 120_000)
+    ref = O.stream_reference(chunks, W=2, theta_pct=40, S=960, rmax=8, lag=1)
+    st = hm.Stream(W=2, theta_pct=40, S=960, rmax=8, lag=1, trace_cap=64)
+    ds = [dev(c) if c.size else None for c in chunks]
+    outs = torch.zeros((len(chunks), 256), dtype=torch.int32, device="cuda")
+    bufs = [(int(x.data_ptr()) if x is not None else 0, c.size) for x, c in zip(ds, chunks)]
+    st.push_many(bufs[:7], d_out=outs[:7])
+    for k in range(7, 12):
+        st.push(bufs[k][0], d_out=outs[k], n=bufs[k][1])
+    st.push_many(bufs[12:], d_out=outs[12:])
+    snap, modes, pats = st.read(len(chunks))
+    assert np.array_equal(outs.cpu().numpy().astype(np.int64), ref["hists"].astype(np.int64))
+    assert [int(m) for m in modes] == ref["modes"]
+    assert [list(map(int, p)) for p in pats] == ref["patterns"]
+    assert [int(x) for x in snap.acc] == ref["acc"]
+    st.close()
+
+
+def test_full_size_config2(hm):
+    # the config-2 stream at its real size: 66 chunks of 4 MiB, lag 0 and a pipelined lag
+    chunks = config2_like(4 << 20)
+    hists = [O.hist(c) for c in chunks]
+    for lag, S, rmax, theta in ((0, 960, 8, 45), (15, 8192, 32, 45), (7, 960, 8, 0)):
+        ref = O.stream_reference(None, W=1, theta_pct=theta, S=S, rmax=rmax, lag=lag, hists=hists)
+        got, snap, modes, pats = run_stream(hm, chunks, 1, theta, S, rmax, lag, 0, True)
+        assert np.array_equal(got, ref["hists"].astype(np.int64)), lag
+        assert [int(m) for m in modes] == ref["modes"], lag
+        assert [list(map(int, p)) for p in pats] == ref["patterns"], lag
+        assert [int(x) for x in snap.acc] == ref["acc"]
+
+
+def test_long_stream_over_launch_limit(hm):
+    # more chunks than one persistent launch holds: split into launches, same semantics
+    chunks = [G.constant_bytes(512, k % 256) if k % 5 else G.uniform_bytes(700, G.rng(8, k)) for k in range(1100)]
+    check(hm, chunks, W=1, theta=45, S=960, rmax=8, lag=2, many=True)
+
+
+def test_push_many_single_chunk(hm):
+    # one chunk per persistent launch, repeatedly: same semantics as one long call
+    chunks = mixed_chunks(91, 9, 400_000)
+    ref = O.stream_reference(chunks, W=2, theta_pct=45, S=960, rmax=8, lag=1)
+    st = hm.Stream(W=2, theta_pct=45, S=960, rmax=8, lag=1, trace_cap=16)
+    ds = [dev(c) if c.size else None for c in chunks]
+    outs = torch.zeros((len(chunks), 256), dtype=torch.int32, device="cuda")
+    for k, (x, c) in enumerate(zip(ds, chunks)):
+        st.push_many([(int(x.data_ptr()) if x is not None else 0, c.size)], d_out=outs[k:k + 1])
+    snap, modes, pats = st.read(len(chunks))
+    assert np.array_equal(outs.cpu().numpy().astype(np.int64), ref["hists"].astype(np.int64))
+    assert [int(m) for m in modes] == ref["modes"]
+    assert [list(map(int, p)) for p in pats] == ref["patterns"]
+    assert [int(x) for x in snap.acc] == ref["acc"]
+    st.close()
