@@ -115,6 +115,22 @@ __device__ uint64_t block_max_u64(uint64_t v, Ctl &c) {
   return s;
 }
 
+// Ordering of cross-workgroup communication.  Every location that workgroups share inside a
+// launch (partial counts, tickets, decisions, stream state) is only touched through
+// agent-scope atomics and agent-scope (sc1) loads and stores, which are performed at the
+// device's coherence point.  What remains to order is a thread's earlier accesses before its
+// later signal (a ticket or a flag): waiting until the earlier ones are acknowledged does
+// that.  An agent-scope fence would also write back and invalidate the whole L2 of the XCD,
+// which costs about a microsecond each and serialises the many flushes of a launch.
+// Building with -DHISTMI_STRICT_FENCES uses those fences instead.
+__device__ __forceinline__ void order_global() {
+#ifdef HISTMI_STRICT_FENCES
+  __threadfence();
+#else
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+#endif
+}
+
 template <typename T>
 __device__ __forceinline__ T ld_agent(const T *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -124,14 +140,16 @@ __device__ __forceinline__ void st_agent(T *p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Bounded spin by thread 0 until *p == want.  Polls with relaxed loads (no cache
-// invalidation per poll) and ends with one acquire fence.  Returns false on timeout
+// Bounded spin by thread 0 until *p == want.  Polls with relaxed agent-scope loads (no
+// cache invalidation per poll); what the flag guards is then read with agent-scope loads.  Returns false on timeout
 // (counted in diag[1]); the callers then go on with what they have, which can only cost
 // speed or a stale trace, never counts.
 __device__ bool spin_until_u32(const uint32_t *p, uint32_t want, uint32_t *diag) {
   for (uint32_t i = 0; i < (1u << 22); ++i) {
     if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == want) {
+#ifdef HISTMI_STRICT_FENCES
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+#endif
       return true;
     }
     __builtin_amdgcn_s_sleep(8);
@@ -142,7 +160,9 @@ __device__ bool spin_until_u32(const uint32_t *p, uint32_t want, uint32_t *diag)
 __device__ bool spin_until_u64(const uint64_t *p, uint64_t want, uint32_t *diag) {
   for (uint32_t i = 0; i < (1u << 22); ++i) {
     if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == want) {
+#ifdef HISTMI_STRICT_FENCES
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+#endif
       return true;
     }
     __builtin_amdgcn_s_sleep(8);
@@ -499,9 +519,9 @@ __device__ void server_epilogue(const Params &P, Ctl &c, uint32_t sidx, uint32_t
     st_agent(&d->rmax, st->rmax);
     st_agent(&d->mode, mode);
   }
-  __threadfence();
+  order_global();
   __syncthreads();
-  if (t == 0) __hip_atomic_fetch_add(&d->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if (t == 0) __hip_atomic_fetch_add(&d->gen, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Stream epilogue for chunk k with histogram h (thread t holds bin t): Accumulator, moving
@@ -543,12 +563,12 @@ __device__ void stream_epilogue(const Params &P, Ctl &c, uint32_t sidx, int64_t 
     st_agent(&st->pat_trace[(size_t)k * 256u + t], c.words[t]);
     if (t == 0) st->mode_trace[k] = (uint8_t)c.used_mode;
   }
-  __threadfence();
+  order_global();
   __syncthreads();
   if (t == 0) {
-    __hip_atomic_store(&d->gen, (uint32_t)(k + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    if (W == 1) __hip_atomic_fetch_add(&st->done, (uint64_t)1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    else __hip_atomic_store(&st->done, (uint64_t)(k + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&d->gen, (uint32_t)(k + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (W == 1) __hip_atomic_fetch_add(&st->done, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else __hip_atomic_store(&st->done, (uint64_t)(k + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -563,7 +583,7 @@ __device__ void flush_segment(uint32_t *lds, const Params &P, Ctl &c, uint32_t s
   uint32_t *part = P.partial + ((size_t)s << (P.clog2 + 8));
   if (h) __hip_atomic_fetch_add(&part[((blockIdx.x & (copies - 1u)) << 8) | t], h, __ATOMIC_RELAXED,
                                 __HIP_MEMORY_SCOPE_AGENT);
-  __threadfence();
+  order_global();
   __syncthreads();
   if (t == 0) {
     const uint32_t before = atomicAdd(&P.seg_done[s], nt);
@@ -571,19 +591,21 @@ __device__ void flush_segment(uint32_t *lds, const Params &P, Ctl &c, uint32_t s
   }
   __syncthreads();
   if (c.flag) {
-    __threadfence();   // acquire: every workgroup's partial adds happen before these reads
-    // read the copies eight at a time (all eight loads in flight), then clear them
+#ifdef HISTMI_STRICT_FENCES
+    __threadfence();
+#endif
+    // read the copies eight at a time (all eight agent-scope loads in flight), then clear them
     uint32_t tot = 0;
     if (copies >= 8) {
       for (uint32_t q = 0; q < copies; q += 8) {
         uint32_t x[8];
 #pragma unroll
-        for (uint32_t u = 0; u < 8; ++u) x[u] = part[((q + u) << 8) | t];
+        for (uint32_t u = 0; u < 8; ++u) x[u] = ld_agent(&part[((q + u) << 8) | t]);
 #pragma unroll
         for (uint32_t u = 0; u < 8; ++u) tot += x[u];
       }
     } else {
-      for (uint32_t q = 0; q < copies; ++q) tot += part[(q << 8) | t];
+      for (uint32_t q = 0; q < copies; ++q) tot += ld_agent(&part[(q << 8) | t]);
     }
     for (uint32_t q = 0; q < copies; ++q) st_agent(&part[(q << 8) | t], 0u);
     if (sd.out) sd.out[t] = tot;
