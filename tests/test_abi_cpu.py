@@ -1,0 +1,130 @@
+"""Host-only checks of the C ABI (no GPU calls): the library loads, exports every symbol the
+header declares, the binding declares exactly those, and argument errors that are decided
+before any device work come back synchronously with the documented status."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "histmi.h")
+
+
+@pytest.fixture(scope="module")
+def hm():
+    import paper_1011_0235_amd as m
+    if not os.path.exists(m.LIB_PATH):
+        from paper_1011_0235_amd import build
+        build.build()
+    m.load()
+    return m
+
+
+def header_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:hist_status_t|const char \*)\s*(hist_[a-z0-9_]+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_boundary():
+    syms = header_symbols()
+    for must in ("hist_u8", "hist_u8_u64", "hist_pattern_update", "hist_batch", "hist_server_create",
+                 "hist_server_submit", "hist_stream_push", "hist_strerror"):
+        assert must in syms
+
+
+def test_library_exports_every_declared_symbol(hm):
+    lib = ctypes.CDLL(hm.LIB_PATH)
+    for name in header_symbols():
+        assert hasattr(lib, name), name
+    assert sorted(hm.declared_symbols()) == header_symbols()
+
+
+def test_strerror(hm):
+    for st in (hm.OK, hm.EINVAL, hm.ENOMEM, hm.EOVERFLOW, hm.EBUSY, hm.EDEVICE, hm.ENOTSUP, hm.ETIMEDOUT,
+               hm.ECANCELED):
+        assert hm.strerror(st) and hm.strerror(st) != "unknown status"
+    assert hm.strerror(-99) == "unknown status"
+
+
+def test_pattern_presets_match_the_oracle(hm):
+    assert hm.pattern_init(hm.PAT_IDENTITY).words() == O.pattern_identity()
+    p = hm.pattern_init(hm.PAT_PAPER960)
+    assert p.words() == O.pattern_paper960() and p.total_S == 960 and p.rmax == 8
+    for r in (1, 2, 8, 32, 64):
+        p = hm.pattern_init(hm.PAT_FLAT, 0, r)
+        assert p.words() == O.pattern_flat(r) and p.total_S == 256 * r
+    with pytest.raises(hm.HistError):
+        hm.pattern_init(hm.PAT_FLAT, 0, 3)
+    with pytest.raises(hm.HistError):
+        hm.pattern_init(7)
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_pattern_validate_agrees_with_oracle(hm, seed):
+    rnd = np.random.default_rng(seed)
+    S = int(rnd.choice([256, 300, 960, 4096, 16384, 20000]))
+    rmax = int(rnd.choice([1, 2, 8, 32, 64, 128]))
+    kind = seed % 3
+    if kind == 0:
+        words = O.rule_p(rnd.integers(0, 1000, 256).tolist(), max(256, min(S, 16384)), min(rmax, 64))
+    elif kind == 1:
+        words = [int(x) for x in rnd.integers(0, 1 << 20, 256)]
+    else:
+        words = O.pattern_identity()
+        i, j = rnd.integers(0, 256, 2)
+        words[int(i)] = words[int(j)]
+    p = hm.Pattern.from_words(words, S, rmax)
+    ok = (hm.pattern_validate(p) == hm.OK)
+    expect = (rmax <= 64 and S <= 16384 and O.pattern_valid(words, S, rmax))
+    assert ok == expect
+
+
+def test_synchronous_argument_errors(hm):
+    lib = hm.load()
+    # NULL input with n > 0, NULL output, bad mode, n too large: refused before any device work
+    out = ctypes.c_void_p(0x1000)
+    assert lib.hist_u8(None, 10, out, 0, None, None) == hm.EINVAL
+    assert lib.hist_u8(ctypes.c_void_p(0x1000), 10, None, 0, None, None) == hm.EINVAL
+    assert lib.hist_u8(ctypes.c_void_p(0x1000), 10, out, 9, None, None) == hm.EINVAL
+    assert lib.hist_u8(ctypes.c_void_p(0x1000), 1 << 32, out, 0, None, None) == hm.EOVERFLOW
+    bad = hm.pattern_init(hm.PAT_IDENTITY)
+    bad.word[5] = bad.word[6]
+    assert lib.hist_u8(ctypes.c_void_p(0x1000), 10, out, hm.MODE_AHIST, ctypes.byref(bad), None) == hm.EINVAL
+    assert lib.hist_u8_u64(None, 10, out, 0, None, None) == hm.EINVAL
+    assert lib.hist_pattern_update(None, 960, 8, out, None) == hm.EINVAL
+    assert lib.hist_pattern_update(out, 255, 8, out, None) == hm.EINVAL
+    assert lib.hist_pattern_update(out, 960, 3, out, None) == hm.EINVAL
+
+
+def test_stream_and_server_config_errors(hm):
+    lib = hm.load()
+    h = ctypes.c_void_p()
+    for cfg in (hm._lib.StreamConfig(0, 45, 960, 8, 0, 1), hm._lib.StreamConfig(1, 101, 960, 8, 0, 1),
+                hm._lib.StreamConfig(1, 45, 100, 8, 0, 1), hm._lib.StreamConfig(1, 45, 960, 6, 0, 1),
+                hm._lib.StreamConfig(1, 45, 20000, 8, 0, 1)):
+        assert lib.hist_stream_create(ctypes.byref(h), ctypes.byref(cfg)) == hm.EINVAL
+    for cfg in (hm._lib.ServerConfig(0, 4, 4, 1, 4, 0, 45, 960, 8), hm._lib.ServerConfig(1 << 20, 0, 4, 1, 4, 0, 45, 960, 8),
+                hm._lib.ServerConfig(1 << 20, 4, 4, 17, 4, 0, 45, 960, 8),
+                hm._lib.ServerConfig(1 << 20, 4, 4, 1, 4, 5, 45, 960, 8)):
+        assert lib.hist_server_create(ctypes.byref(h), ctypes.byref(cfg)) == hm.EINVAL
+    assert lib.hist_stream_push(None, None, 0, 0, None, None) == hm.EINVAL
+    assert lib.hist_server_submit(None, 0, None, 0, None, None) == hm.EINVAL
+
+
+def test_tuning_table(hm):
+    old = hm.tune_get(1)
+    hm.tune_set(1, blocks_per_cu=3, tile_kib=128, merge_copies=8)
+    t = hm.tune_get(1)
+    assert (t.blocks_per_cu, t.tile_kib, t.merge_copies) == (3, 128, 8)
+    with pytest.raises(hm.HistError):
+        hm.tune_set(1, tile_kib=17)
+    with pytest.raises(hm.HistError):
+        hm.tune_set(1, merge_copies=3)
+    with pytest.raises(hm.HistError):
+        hm.tune_set(5, blocks_per_cu=1)
+    hm.tune_set(1, old.blocks_per_cu, old.tile_kib, old.merge_copies)
