@@ -78,6 +78,125 @@ def profiled_traffic():
     return None
 
 
+def timed(torch, stream, fn, reps):
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def bench_batched(hm, G, O, torch, dev, stream):
+    """The 4096-image batch (sides log-uniform 64..4096; uniform / Normal / 90 % spike images), generated
+    on the device: one persistent launch, the same launch replayed from a HIP graph, and 4096 sequential
+    single-image launches."""
+    specs = G.batch_specs(4096)
+    sizes = np.array([sp.size for sp in specs], dtype=np.int64)
+    offs = np.zeros_like(sizes)
+    offs[1:] = np.cumsum((sizes + 255) // 256 * 256)[:-1]
+    total = int(offs[-1] + sizes[-1])
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(G.ROOT_SEED + 4)
+    arena = torch.randint(0, 256, (total,), dtype=torch.uint8, device=dev, generator=gen)
+    for j, sp in enumerate(specs):
+        a, n = int(offs[j]), int(sizes[j])
+        if sp.kind == "normal":
+            z = torch.randn(n, device=dev, generator=gen) * sp.sigma + sp.mu
+            arena[a:a + n] = z.round().clamp_(0, 255).to(torch.uint8)
+        elif sp.kind == "spike":
+            m = torch.rand(n, device=dev, generator=gen) < 0.9
+            arena[a:a + n].masked_fill_(m, sp.value)
+    base = int(arena.data_ptr())
+    bufs = [(base + int(o), int(n)) for o, n in zip(offs, sizes)]
+    out = torch.zeros((4096, 256), dtype=torch.int32, device=dev)
+    nb = int(sizes.sum())
+    ms_batch = timed(torch, stream, lambda: hm.hist_batch(bufs, out, mode=hm.MODE_AUTO, stream=stream), 5)
+    graph = hm.BatchGraph(bufs, out, mode=hm.MODE_AUTO)
+    ms_graph = timed(torch, stream, lambda: graph.launch(stream=stream), 5)
+    got = out.cpu().numpy().astype(np.int64)
+    ok = bool(np.array_equal(got.sum(axis=1), sizes))
+    for j in (0, 1, 2, int(np.argmax(sizes)), 4095):
+        host = arena[int(offs[j]):int(offs[j] + sizes[j])].cpu().numpy()
+        ok = ok and bool(np.array_equal(got[j], O.hist(host).astype(np.int64)))
+    graph.close()
+    outs1 = [out[j] for j in range(4096)]
+
+    def seq():
+        for j in range(4096):
+            hm.hist_u8(bufs[j][0], outs1[j], mode=hm.MODE_AUTO, stream=stream, n=bufs[j][1])
+    ms_seq = timed(torch, stream, seq, 1)
+    del arena
+    return {"images": 4096, "bytes": nb,
+            "persistent_GBps": round(nb / (ms_batch * 1e-3) / 1e9, 1), "persistent_ms": round(ms_batch, 3),
+            "graph_GBps": round(nb / (ms_graph * 1e-3) / 1e9, 1), "graph_ms": round(ms_graph, 3),
+            "sequential_hist_u8_GBps": round(nb / (ms_seq * 1e-3) / 1e9, 1), "sequential_ms": round(ms_seq, 3),
+            "speedup_vs_sequential": round(ms_seq / ms_graph, 2), "parity_sampled_exact": ok}
+
+
+def bench_served(hm, G, O, torch, dev, stream, rates=(1000, 10000, 50000), duration=2.0):
+    """Open-loop Poisson arrivals (sizes log-uniform 4 KiB..64 MiB, 64 stream ids) into the
+    continuous-batching server; latency from scheduled arrival to host-observed completion."""
+    n_streams, pool = 64, 64 * MIB
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(G.ROOT_SEED + 5)
+    pools = []
+    for sid in range(n_streams):
+        mu = float(40 + (sid * 2654435761 % 176))
+        z = torch.randn(pool, device=dev, generator=gen) * 20.0 + mu
+        pools.append(z.round().clamp_(0, 255).to(torch.uint8))
+    out = {}
+    for rate in rates:
+        reqs = G.serve_requests(float(rate), duration, n_streams=n_streams, pool_bytes=pool, item=rate)
+        outs = torch.zeros((len(reqs), 256), dtype=torch.int32, device=dev)
+        ptrs = [int(pools[r.stream_id].data_ptr()) + r.offset for r in reqs]
+        optr = int(outs.data_ptr())
+        sv = hm.Server(hbm_budget_bytes=1 << 30, max_slots=256, n_stream_ids=n_streams, n_hip_streams=4,
+                       max_batch=64, mode=hm.MODE_AUTO, theta_pct=45, S=8192, rmax=32)
+        tickets, sched = [], []
+        t0 = time.perf_counter_ns()
+        for i, r in enumerate(reqs):
+            due = t0 + int(r.t_arrival * 1e9)
+            while time.perf_counter_ns() < due:
+                pass
+            st, tk = sv.try_submit(r.stream_id, ptrs[i], d_out=optr + 1024 * i, n=r.size)
+            tickets.append(tk if st == hm.OK else 0)
+            sched.append(due)
+        sv.drain()
+        res = [sv.poll(tk) for tk in tickets if tk]
+        stats = sv.stats()
+        # steady_clock in the library and perf_counter_ns here share CLOCK_MONOTONIC
+        lat = np.array([(r_.t_done_ns - sched[i]) / 1e3 for i, r_ in enumerate(res)])
+        span = (max(r_.t_done_ns for r_ in res) - t0) / 1e9
+        nbytes = sum(r.size for r in reqs)
+        got = outs.cpu().numpy().astype(np.int64)
+        ok = bool(all(int(got[i].sum()) == reqs[i].size for i in range(len(reqs))))
+        for i in (0, len(reqs) // 2, len(reqs) - 1):
+            host = pools[reqs[i].stream_id][reqs[i].offset:reqs[i].offset + reqs[i].size].cpu().numpy()
+            ok = ok and bool(np.array_equal(got[i], O.hist(host).astype(np.int64)))
+        acc_ok = True
+        for sid in range(n_streams):
+            exp = got[[i for i, r in enumerate(reqs) if r.stream_id == sid]].sum(axis=0) if reqs else 0
+            acc_ok = acc_ok and bool(np.array_equal(sv.stream_acc(sid).astype(np.int64), exp))
+        sv.close()
+        # the plain kernel: one single-image launch per request, in arrival order, back to back
+        ms_fifo = timed(torch, stream, lambda: [hm.hist_u8(ptrs[i], outs[i], stream=stream, n=reqs[i].size)
+                                                for i in range(len(reqs))], 1)
+        out["%d_per_s" % rate] = {
+            "requests": len(reqs), "bytes": nbytes, "offered_GBps": round(nbytes / duration / 1e9, 2),
+            "served_GBps": round(nbytes / span / 1e9, 2),
+            "p50_us": round(float(np.percentile(lat, 50)), 1), "p99_us": round(float(np.percentile(lat, 99)), 1),
+            "batches": int(stats.batches), "max_concurrent_batches": int(stats.max_concurrent_batches),
+            "fifo_hist_u8_GBps": round(nbytes / (ms_fifo * 1e-3) / 1e9, 1),
+            "parity_exact": ok and acc_ok}
+        del outs
+    del pools
+    return out
+
+
 def tuned_defaults():
     """Stream settings written by the autotuner (tuning.json beside the library), else built-ins."""
     d = {"lag": 31, "theta_pct": 0, "S": 8192, "rmax": 32}
@@ -261,6 +380,8 @@ def main():
             t2[kind] = row
             del xs
         extras["table2_64mib_GBps"] = t2
+        extras["batched_config4"] = bench_batched(hm, G, O, torch, dev, stream)
+        extras["served_config5"] = bench_served(hm, G, O, torch, dev, stream)
         res["extras"] = extras
 
     print(json.dumps(res), flush=True)

@@ -57,7 +57,9 @@ typedef enum {
      * derived from the moving window when the window is degenerate, else per-wavefront. */
     HIST_MODE_AUTO = 0,
     HIST_MODE_AHIST = 1,     /* sub-bins indexed by the binning pattern */
-    HIST_MODE_WAVEHIST = 2   /* one 256-bin table per wavefront (NVHist style) */
+    HIST_MODE_WAVEHIST = 2,  /* one 256-bin table per wavefront (NVHist style) */
+    HIST_MODE_WAVEAGG = 3    /* per-wavefront tables; per byte position, the lanes whose value equals the
+                                first active lane's are merged into one add of their count (64-lane ballot) */
 } hist_mode_t;
 
 typedef enum {

@@ -48,6 +48,7 @@ import numpy as np
 MODE_AUTO = 0
 MODE_AHIST = 1
 MODE_WAVEHIST = 2
+MODE_WAVEAGG = 3      # a forced-only kernel choice; the switch itself picks AHist or per-wavefront
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")

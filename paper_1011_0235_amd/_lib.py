@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhistmi.so")
 
 OK, EINVAL, ENOMEM, EOVERFLOW, EBUSY, EDEVICE, ENOTSUP, ETIMEDOUT, ECANCELED = 0, -1, -2, -3, -4, -5, -6, -7, -8
-MODE_AUTO, MODE_AHIST, MODE_WAVEHIST = 0, 1, 2
+MODE_AUTO, MODE_AHIST, MODE_WAVEHIST, MODE_WAVEAGG = 0, 1, 2, 3
 PAT_IDENTITY, PAT_PAPER960, PAT_FLAT = 0, 1, 2
 S_MAX = 16384
 RMAX_MAX = 64
@@ -133,7 +133,24 @@ def declared_symbols():
     return [name for name, _, _ in _SIGS]
 
 
-def load(path: Optional[str] = None):
+TUNING_PATH = os.path.join(HERE, "tuning.json")
+_FAMILIES = {"wavehist": 0, "uniform": 1, "lookup": 2, "waveagg": 3}
+
+
+def apply_tuning(path: str = TUNING_PATH):
+    """Apply the launch shapes an autotuner run wrote (no-op if there is none)."""
+    import json
+    if not os.path.exists(path):
+        return
+    with open(path) as f:
+        t = json.load(f)
+    for name, fam in t.get("families", {}).items():
+        if name in _FAMILIES:
+            tune_set(_FAMILIES[name], int(fam.get("blocks_per_cu", 0)), int(fam.get("tile_kib", 0)),
+                     int(fam.get("merge_copies", 0)))
+
+
+def load(path: Optional[str] = None, apply_tuning: bool = True):
     """Load libhistmi.so (once).  Raises if it is missing: there is no fallback path."""
     global _lib
     if _lib is not None:
@@ -147,6 +164,8 @@ def load(path: Optional[str] = None):
         fn.restype = res
         fn.argtypes = args
     _lib = lib
+    if apply_tuning:
+        globals()["apply_tuning"]()
     return lib
 
 

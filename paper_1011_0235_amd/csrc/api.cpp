@@ -19,7 +19,7 @@ namespace rt {
 
 // Defaults from the gfx950 probes: the lane-cyclic table streams best with 2 workgroups of
 // 4 wavefronts per CU and 4 loads in flight per lane.
-Tune g_tune[kFamilies] = {{4, 256, 4}, {2, 256, 4}, {2, 256, 4}};
+Tune g_tune[kFamilies] = {{4, 256, 4}, {2, 256, 4}, {2, 256, 4}, {4, 256, 4}};
 uint32_t g_single_copies = 16;   // partial copies for a launch with one large segment
 
 static std::mutex g_mu;
@@ -216,6 +216,8 @@ hist_status_t select_kind(hist_mode_t mode, const hist_pattern_t *h_pat, Params 
   uint32_t rr_lg = 5;
   if (mode == HIST_MODE_WAVEHIST) {
     P->kind = KIND_WAVE;
+  } else if (mode == HIST_MODE_WAVEAGG) {
+    P->kind = KIND_WAVE_AGG;
   } else if (mode == HIST_MODE_AUTO) {
     P->kind = KIND_UNIFORM;
     P->uni_lg = log2u(HIST_AUTO_FLAT_R);

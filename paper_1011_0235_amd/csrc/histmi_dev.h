@@ -16,7 +16,8 @@ constexpr uint32_t kMaxCopiesLog2 = 6;      // at most 64 partial copies per seg
 enum Kind : uint32_t {
   KIND_WAVE = 0,      // one 256-bin table per wavefront (NVHist style)
   KIND_UNIFORM = 1,   // every value has r = 2^lg sub-bins at v*r + (lane mod r)
-  KIND_LOOKUP = 2     // per-value (base, r) from a binning pattern, via a lane-replicated index table
+  KIND_LOOKUP = 2,    // per-value (base, r) from a binning pattern, via a lane-replicated index table
+  KIND_WAVE_AGG = 3   // per-wavefront tables; lanes holding the same value as the first lane merge their adds
 };
 
 // A stream's kernel choice for one chunk: written by the epilogue of the chunk it was

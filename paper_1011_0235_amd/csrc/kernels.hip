@@ -21,7 +21,10 @@
 //                   warp); with r >= 32 the 64 lanes of a wavefront never collide in a bank;
 //   KIND_LOOKUP  -- AHist with an arbitrary binning pattern (Figure 1): per value a base and
 //                   a power-of-two r; the lane-specific sub-bin address comes from an
-//                   LDS table replicated per lane so that the lookup itself is conflict free.
+//                   LDS table replicated per lane so that the lookup itself is conflict free;
+//   KIND_WAVE_AGG -- per-wavefront tables, with the lanes that hold the first active lane's
+//                   value merged into one add (a 64-lane ballot): another way to cut the
+//                   serialised same-address atomics of peaked data.
 
 #include <hip/hip_runtime.h>
 
@@ -273,7 +276,7 @@ __device__ uint32_t classify_pattern(Ctl &c, uint32_t S, uint32_t rmax, uint32_t
 // look[v * RR + j] = byte address of sub-bin base(v) + (j mod r(v)), j = lane mod RR.
 __device__ void stage_table(uint32_t *lds, const Params &P, Ctl &c, uint32_t kind, uint32_t lg, uint32_t S) {
   const uint32_t t = threadIdx.x;
-  if (kind == KIND_WAVE) {
+  if (kind == KIND_WAVE || kind == KIND_WAVE_AGG) {
     zero_words(lds, kWaves * 256);
   } else if (kind == KIND_UNIFORM) {
     zero_words(lds, 256u << lg);
@@ -299,9 +302,21 @@ struct Adder {
   uint32_t a;      // LDS byte address: KIND_WAVE: this wave's table; UNIFORM: table + (lane mod r) * 4;
                    // LOOKUP: this lane's column of the lookup table
   uint32_t s;      // UNIFORM: lg + 2; LOOKUP: log2(RR) + 2
+  uint32_t lane;   // WAVE_AGG: this lane's index in the wavefront
   __device__ __forceinline__ void add(uint32_t v) const {
     uint32_t addr;
-    if (KIND == KIND_WAVE) {
+    if (KIND == KIND_WAVE_AGG) {
+      // peel the first active lane's value: its holders add once, by their count
+      const uint32_t v0 = __builtin_amdgcn_readfirstlane(v);
+      const uint64_t eq = __ballot(v == v0);
+      if (v != v0) {
+        __hip_atomic_fetch_add((lu32 *)(uintptr_t)(a + (v << 2)), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      } else if (lane == (uint32_t)__builtin_ctzll(eq)) {
+        __hip_atomic_fetch_add((lu32 *)(uintptr_t)(a + (v0 << 2)), (uint32_t)__popcll(eq), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+      return;
+    } else if (KIND == KIND_WAVE) {
       addr = a + (v << 2);
     } else if (KIND == KIND_UNIFORM) {
       addr = (v << s) + a;
@@ -420,7 +435,7 @@ __device__ void run_strided(uint32_t *lds, const Adder<KIND> &ad, const uint8_t 
 __device__ uint32_t table_bin(const uint32_t *lds, const Ctl &c, uint32_t kind, uint32_t lg) {
   const uint32_t t = threadIdx.x;
   uint32_t h = 0;
-  if (kind == KIND_WAVE) {
+  if (kind == KIND_WAVE || kind == KIND_WAVE_AGG) {
 #pragma unroll
     for (uint32_t w = 0; w < kWaves; ++w) h += lds[(w << 8) | t];
   } else if (kind == KIND_UNIFORM) {
@@ -450,7 +465,8 @@ __device__ uint32_t begin_segment(uint32_t *lds, const Params &P, Ctl &c, const 
     kind = P.kind;
     if (kind == KIND_UNIFORM) c.lg = P.uni_lg;
     if (kind == KIND_LOOKUP) c.words[t] = P.pat_words[t];
-    c.used_mode = (kind == KIND_WAVE) ? HIST_MODE_WAVEHIST : HIST_MODE_AHIST;
+    c.used_mode = (kind == KIND_WAVE) ? HIST_MODE_WAVEHIST : (kind == KIND_WAVE_AGG) ? HIST_MODE_WAVEAGG
+                                                                                       : HIST_MODE_AHIST;
     __syncthreads();
   } else {
     StreamDev *st = P.st + sd.stream_idx;
@@ -488,10 +504,14 @@ __device__ uint32_t begin_segment(uint32_t *lds, const Params &P, Ctl &c, const 
     if (mode == HIST_MODE_AHIST) {
       kind = classify_pattern(c, S, st->rmax, P.pat_S, HIST_RMAX_MAX, P.look_words != 0);
       if (kind == KIND_WAVE && t == 0) atomicAdd(&P.diag[0], 1u);
+    } else if (mode == HIST_MODE_WAVEAGG) {
+      kind = KIND_WAVE_AGG;
     } else {
       kind = KIND_WAVE;
     }
-    if (t == 0) c.used_mode = (kind == KIND_WAVE) ? HIST_MODE_WAVEHIST : HIST_MODE_AHIST;
+    if (t == 0)
+      c.used_mode = (kind == KIND_WAVE) ? HIST_MODE_WAVEHIST : (kind == KIND_WAVE_AGG) ? HIST_MODE_WAVEAGG
+                                                                                       : HIST_MODE_AHIST;
     __syncthreads();
   }
   stage_table(lds, P, c, kind, c.lg, S);
@@ -622,7 +642,8 @@ __device__ __forceinline__ Adder<KIND> make_adder(const uint32_t *lds, const Par
   Adder<KIND> ad;
   const uint32_t lane = lane_id();
   const uint32_t tb = lds_addr_of(lds);
-  if (KIND == KIND_WAVE) {
+  ad.lane = lane;
+  if (KIND == KIND_WAVE || KIND == KIND_WAVE_AGG) {
     ad.a = tb + (wave_id() << 10);
     ad.s = 0;
   } else if (KIND == KIND_UNIFORM) {
@@ -694,6 +715,7 @@ __global__ void __launch_bounds__(kBlock) hist_main(const Params P) {
     }
     const uint32_t rot = blockIdx.x * 7u;
     if (kind == KIND_WAVE) run_tile<KIND_WAVE, U>(lds, P, c, sd.ptr + off, len, strided, rot);
+    else if (kind == KIND_WAVE_AGG) run_tile<KIND_WAVE_AGG, U>(lds, P, c, sd.ptr + off, len, strided, rot);
     else if (kind == KIND_UNIFORM) run_tile<KIND_UNIFORM, U>(lds, P, c, sd.ptr + off, len, strided, rot);
     else run_tile<KIND_LOOKUP, U>(lds, P, c, sd.ptr + off, len, strided, rot);
     ++nt;

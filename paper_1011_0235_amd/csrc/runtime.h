@@ -24,7 +24,7 @@ namespace rt {
 
 constexpr uint32_t kStaticLdsReserve = 8192;       // static LDS of the kernel (control block), with margin
 constexpr uint64_t kMaxSegBytes = 0xFFFFFFFFull;   // per-segment counts must fit the 32-bit partials
-constexpr uint32_t kFamilies = 3;                  // one tuning entry per Kind
+constexpr uint32_t kFamilies = 4;                  // one tuning entry per Kind
 constexpr uint32_t kMaxChunksPerLaunch = 1024;     // stream chunks in one persistent launch, at most
 
 #define TRY_HIP(x)                               \
@@ -52,7 +52,7 @@ inline uint32_t log2u(uint32_t x) {
 }
 inline bool is_pow2(uint32_t x) { return x && !(x & (x - 1)); }
 inline bool mode_ok(hist_mode_t m) {
-  return m == HIST_MODE_AUTO || m == HIST_MODE_AHIST || m == HIST_MODE_WAVEHIST;
+  return m == HIST_MODE_AUTO || m == HIST_MODE_AHIST || m == HIST_MODE_WAVEHIST || m == HIST_MODE_WAVEAGG;
 }
 
 struct Tune {

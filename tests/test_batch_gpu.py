@@ -49,7 +49,7 @@ def test_batch_uneven_with_empty_and_large(hm):
     arena = g.integers(0, 256, size=pos + 16, dtype=np.uint8)
     arena[offs[7]:offs[7] + (1 << 20)] = 9          # a degenerate stretch inside the big image
     exp = O.hist_many(arena, offs, sizes).astype(np.int64)
-    for mode in (hm.MODE_AUTO, hm.MODE_WAVEHIST, hm.MODE_AHIST):
+    for mode in (hm.MODE_AUTO, hm.MODE_WAVEHIST, hm.MODE_AHIST, hm.MODE_WAVEAGG):
         assert np.array_equal(run_batch(hm, arena, offs, sizes, mode), exp), mode
 
 

@@ -27,7 +27,7 @@ def run_u8(hm, d_in, n, mode, pattern=None, offset=0):
 def patterns(hm):
     """(name, mode, host pattern) for every kernel variant."""
     rnd = np.random.default_rng(7)
-    out = [("auto", hm.MODE_AUTO, None), ("wavehist", hm.MODE_WAVEHIST, None),
+    out = [("auto", hm.MODE_AUTO, None), ("wavehist", hm.MODE_WAVEHIST, None), ("waveagg", hm.MODE_WAVEAGG, None),
            ("ahist-identity", hm.MODE_AHIST, None),
            ("ahist-paper960", hm.MODE_AHIST, hm.pattern_init(hm.PAT_PAPER960)),
            ("ahist-flat2", hm.MODE_AHIST, hm.pattern_init(hm.PAT_FLAT, 0, 2)),
@@ -67,7 +67,7 @@ def test_every_offset(hm):
     g = np.random.default_rng(12)
     host = G.clipped_normal_bytes((1 << 20) + 64, 90.0, 3.0, g)
     d = dev(host)
-    for name, mode, pat in patterns(hm)[:6]:
+    for name, mode, pat in patterns(hm)[:7]:
         for off in range(16):
             n = (1 << 20) + 1 - off
             got = run_u8(hm, d, n, mode, pat, off)
@@ -80,7 +80,7 @@ def test_table2_inputs_full_size(hm, kind):
     host = G.table2_input(kind)
     exp = O.hist(host).astype(np.int64)
     d = dev(host)
-    for name, mode, pat in patterns(hm)[:7]:
+    for name, mode, pat in patterns(hm)[:8]:
         got = run_u8(hm, d, host.size, mode, pat)
         assert np.array_equal(got, exp), (kind, name)
         assert int(got.sum()) == host.size
@@ -99,11 +99,11 @@ def test_u64_accumulates(hm):
     host = g.integers(0, 256, size=3 << 20, dtype=np.uint8)
     d = dev(host)
     acc = torch.zeros(256, dtype=torch.int64, device="cuda")
-    for mode in (hm.MODE_AUTO, hm.MODE_WAVEHIST, hm.MODE_AHIST):
+    for mode in (hm.MODE_AUTO, hm.MODE_WAVEHIST, hm.MODE_AHIST, hm.MODE_WAVEAGG):
         hm.hist_u8_u64(d, acc, mode=mode)
     hm.hist_u8_u64(d, acc, mode=hm.MODE_AUTO, n=0)
     torch.cuda.synchronize()
-    assert np.array_equal(acc.cpu().numpy(), 3 * O.hist(host).astype(np.int64))
+    assert np.array_equal(acc.cpu().numpy(), 4 * O.hist(host).astype(np.int64))
 
 
 def test_repeat_is_deterministic(hm):

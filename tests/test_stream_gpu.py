@@ -115,7 +115,7 @@ def test_budgets(hm, S, rmax):
     check(hm, chunks, W=3, theta=20, S=S, rmax=rmax, lag=1, many=False)
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 3])
 def test_forced_modes(hm, mode):
     chunks = mixed_chunks(50 + mode, 20, 150_000)
     check(hm, chunks, W=1, theta=45, S=960, rmax=8, lag=0, mode=mode, many=True)
