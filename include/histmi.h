@@ -289,6 +289,7 @@ hist_status_t hist_server_destroy(hist_server_t *sv);
 typedef struct {
     uint64_t invalid_patterns;   /* device-side checks of stream patterns that failed (chunk ran per-wavefront) */
     uint64_t wait_timeouts;      /* bounded in-kernel waits that gave up (stream state may be stale) */
+    uint64_t merge_timeouts;     /* finalizers whose partial counts never reached the segment size */
 } hist_diag_t;
 /* Synchronous read of the current device's counters. */
 hist_status_t hist_diag_read(hist_diag_t *d);

@@ -67,7 +67,8 @@ class StreamSnapshot(ctypes.Structure):
 
 
 class Diag(ctypes.Structure):
-    _fields_ = [("invalid_patterns", ctypes.c_uint64), ("wait_timeouts", ctypes.c_uint64)]
+    _fields_ = [("invalid_patterns", ctypes.c_uint64), ("wait_timeouts", ctypes.c_uint64),
+                ("merge_timeouts", ctypes.c_uint64)]
 
 
 class Tune(ctypes.Structure):

@@ -572,8 +572,12 @@ static hist_status_t batch_prepare(const void *const *h_ptrs, const uint64_t *h_
   TRY(get_dev(&d));
   *dout = d;
   const uint32_t fam = P->kind;
-  const uint64_t tile = (uint64_t)g_tune[fam].tile_kib * 1024;
   const uint32_t maxg = (uint32_t)d->cus * blocks_per_cu(fam, lds_bytes(*P));
+  // tiles: at most the tuned size, and small enough that every workgroup gets several
+  uint64_t total = 0;
+  for (uint32_t j = 0; j < n; ++j) total += h_sizes[j];
+  const uint64_t want = ceil_div(ceil_div(total, (uint64_t)maxg * 6), 16384) * 16384;
+  const uint64_t tile = std::max<uint64_t>(16384, std::min<uint64_t>((uint64_t)g_tune[fam].tile_kib * 1024, want));
   std::vector<SegDesc> segs(n);
   for (uint32_t j = 0; j < n; ++j) {
     std::memset(&segs[j], 0, sizeof(SegDesc));
@@ -724,8 +728,9 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
     const uint64_t per_chunk = std::max<uint64_t>(1, total / m);
     const uint64_t inflight = (uint64_t)std::min<uint32_t>(st->cfg.lag + 1, m);
     uint64_t tile = (uint64_t)g_tune[fam].tile_kib * 1024;
-    const uint64_t fill = ceil_div(per_chunk * inflight, maxg);
-    tile = std::min<uint64_t>(tile, std::max<uint64_t>(16384, ceil_div(fill, 16384) * 16384));
+    const uint64_t fill = ceil_div(per_chunk * inflight, maxg);     // lag + 1 chunks cover the grid
+    const uint64_t several = ceil_div(total, (uint64_t)maxg * 4);  // every workgroup gets several tiles
+    tile = std::min<uint64_t>(tile, std::max<uint64_t>(16384, ceil_div(std::min(fill, several), 16384) * 16384));
     std::vector<SegDesc> segs(m);
     for (uint32_t j = 0; j < m; ++j) {
       std::memset(&segs[j], 0, sizeof(SegDesc));
@@ -796,6 +801,7 @@ hist_status_t hist_diag_read(hist_diag_t *out) {
   TRY_HIP(hipMemcpy(h, d->diag, sizeof(h), hipMemcpyDeviceToHost));
   out->invalid_patterns = h[0];
   out->wait_timeouts = h[1];
+  out->merge_timeouts = h[2];
   return HIST_OK;
 }
 

@@ -27,7 +27,8 @@ struct Decision {
   uint32_t hist[256];    // histogram of the producing chunk (the moving window when W = 1)
   uint32_t S, rmax;
   uint32_t mode;         // HIST_MODE_AHIST or HIST_MODE_WAVEHIST
-  uint32_t gen;          // index of the producing chunk + 1; stored last (release)
+  uint32_t kind_lg;      // table kind of the pattern (KIND_UNIFORM or KIND_LOOKUP) << 8 | log2 r if uniform
+  uint32_t gen;          // index of the producing chunk + 1; stored last
 };
 
 // Device-resident state of one stream (Accumulator, moving window, decisions, traces).

@@ -51,7 +51,7 @@ struct Ctl {
   uint32_t kind;
   uint32_t lg;
   uint32_t used_mode;
-  uint32_t look_shift;
+  uint32_t tmp;
   uint32_t red32[kWaves];
   uint64_t red64[kWaves];
   uint32_t cls_cnt[kWaves][8];
@@ -232,6 +232,17 @@ __device__ uint32_t rule_p_word(uint64_t h, uint64_t N, uint32_t S, uint32_t rma
   return (offset + (rank << cls)) | (cls << 16);
 }
 
+// Table kind of the pattern whose word for value t is `word` (all threads call): uniform iff
+// every value has the same r and sits at v * r.
+__device__ uint32_t pattern_kind_lg(uint32_t word, Ctl &c) {
+  const uint32_t t = threadIdx.x;
+  if (t == 0) c.tmp = word;
+  __syncthreads();
+  const uint32_t lg0 = (c.tmp >> 16) & 0xFFu;
+  const bool uni = (((word >> 16) & 0xFFu) == lg0) && ((word & 0xFFFFu) == (t << lg0));
+  return block_all(uni, c) ? (((uint32_t)KIND_UNIFORM << 8) | lg0) : ((uint32_t)KIND_LOOKUP << 8);
+}
+
 // ------------------------------------------------------------------ table staging
 
 __device__ __forceinline__ void zero_words(uint32_t *lds, uint32_t words) {
@@ -274,7 +285,7 @@ __device__ uint32_t classify_pattern(Ctl &c, uint32_t S, uint32_t rmax, uint32_t
 
 // Zero the counting table for `kind` and (KIND_LOOKUP) build the lane-replicated lookup:
 // look[v * RR + j] = byte address of sub-bin base(v) + (j mod r(v)), j = lane mod RR.
-__device__ void stage_table(uint32_t *lds, const Params &P, Ctl &c, uint32_t kind, uint32_t lg, uint32_t S) {
+__device__ __forceinline__ void stage_table(uint32_t *lds, const Params &P, Ctl &c, uint32_t kind, uint32_t lg, uint32_t S) {
   const uint32_t t = threadIdx.x;
   if (kind == KIND_WAVE || kind == KIND_WAVE_AGG) {
     zero_words(lds, kWaves * 256);
@@ -457,7 +468,7 @@ __device__ __forceinline__ SegDesc load_seg(const Params &P, uint32_t s) {
 
 // Stage segment `sd`: pick the table kind (from the launch, or from the stream's decision)
 // and prepare the LDS.  Returns the kind; sets c.lg / c.used_mode / c.words.
-__device__ uint32_t begin_segment(uint32_t *lds, const Params &P, Ctl &c, const SegDesc &sd) {
+__device__ __forceinline__ uint32_t begin_segment(uint32_t *lds, const Params &P, Ctl &c, const SegDesc &sd) {
   const uint32_t t = threadIdx.x;
   uint32_t kind;
   uint32_t S = P.pat_S;
@@ -486,18 +497,45 @@ __device__ uint32_t begin_segment(uint32_t *lds, const Params &P, Ctl &c, const 
         dmode = ld_agent(&d->mode);
         S = ld_agent(&d->S);
       }
-    } else if (j < 0) {
-      // no history: per-wavefront kernel, identity pattern
-      c.words[t] = t;
-      dmode = HIST_MODE_WAVEHIST;
-      S = 256;
     } else {
-      const Decision *d = &st->slots[(uint64_t)j % st->nslot];
-      if (t == 0) spin_until_u32(&d->gen, (uint32_t)(j + 1), P.diag);
+      // an ordered stream's decision was made by this library's own epilogue: its table kind
+      // comes with it, and the pattern words are read only when the lookup table or the
+      // trace needs them
+      uint32_t kind_lg = ((uint32_t)KIND_UNIFORM << 8);   // no history: identity pattern
+      dmode = HIST_MODE_WAVEHIST;
+      const bool traced = (uint64_t)k < st->trace_cap;
+      if (j >= 0) {
+        const Decision *d = &st->slots[(uint64_t)j % st->nslot];
+        if (t == 0) spin_until_u32(&d->gen, (uint32_t)(j + 1), P.diag);
+        __syncthreads();
+        dmode = ld_agent(&d->mode);
+        kind_lg = ld_agent(&d->kind_lg);
+        if (traced || (kind_lg >> 8) == KIND_LOOKUP) {
+          c.words[t] = ld_agent(&d->words[t]);
+          S = ld_agent(&d->S);
+        }
+      } else {
+        c.words[t] = t;
+        S = 256;
+      }
+      const uint32_t mode = P.forced ? P.forced : dmode;
+      if (mode == HIST_MODE_AHIST) {
+        kind = kind_lg >> 8;
+        c.lg = kind_lg & 0xFFu;
+        if ((kind == KIND_LOOKUP && (P.look_words == 0 || S > P.pat_S)) ||
+            (kind == KIND_UNIFORM && (256u << c.lg) > P.table_words) || kind > KIND_LOOKUP) {
+          kind = KIND_WAVE;   // no room for this pattern's tables (cannot happen with rule P)
+          if (t == 0) atomicAdd(&P.diag[0], 1u);
+        }
+      } else {
+        kind = (mode == HIST_MODE_WAVEAGG) ? KIND_WAVE_AGG : KIND_WAVE;
+      }
+      if (t == 0)
+        c.used_mode = (kind == KIND_WAVE) ? HIST_MODE_WAVEHIST : (kind == KIND_WAVE_AGG) ? HIST_MODE_WAVEAGG
+                                                                                         : HIST_MODE_AHIST;
       __syncthreads();
-      c.words[t] = ld_agent(&d->words[t]);
-      dmode = ld_agent(&d->mode);
-      S = ld_agent(&d->S);
+      stage_table(lds, P, c, kind, c.lg, S);
+      return kind;
     }
     const uint32_t mode = P.forced ? P.forced : dmode;
     __syncthreads();
@@ -523,7 +561,7 @@ __device__ uint32_t begin_segment(uint32_t *lds, const Params &P, Ctl &c, const 
 // and the stream's decision is recomputed from h alone (a window of one request).  Concurrent
 // requests of one stream may overwrite each other's decision; any mix of words that passes
 // the device check is still a valid pattern, so counts stay exact.
-__device__ void server_epilogue(const Params &P, Ctl &c, uint32_t sidx, uint32_t h) {
+__device__ __forceinline__ void server_epilogue(const Params &P, Ctl &c, uint32_t sidx, uint32_t h) {
   const uint32_t t = threadIdx.x;
   StreamDev *st = P.st + sidx;
   atomicAdd(reinterpret_cast<unsigned long long *>(&st->acc[t]), (unsigned long long)h);
@@ -532,12 +570,14 @@ __device__ void server_epilogue(const Params &P, Ctl &c, uint32_t sidx, uint32_t
   const uint64_t mx = block_max_u64(h, c);
   const uint32_t mode = (100ull * mx > (uint64_t)st->theta * N) ? HIST_MODE_AHIST : HIST_MODE_WAVEHIST;
   const uint32_t word = rule_p_word(h, N, st->S, st->rmax, c);
+  const uint32_t kind_lg = pattern_kind_lg(word, c);
   Decision *d = &st->slots[0];
   st_agent(&d->words[t], word);
   if (t == 0) {
     st_agent(&d->S, st->S);
     st_agent(&d->rmax, st->rmax);
     st_agent(&d->mode, mode);
+    st_agent(&d->kind_lg, kind_lg);
   }
   order_global();
   __syncthreads();
@@ -549,7 +589,7 @@ __device__ void server_epilogue(const Params &P, Ctl &c, uint32_t sidx, uint32_t
 // chunk k ran with.  With a window of one chunk (W = 1) the decision after chunk k depends
 // on h_k alone, so epilogues of different chunks run independently; with W > 1 the moving
 // window is updated in chunk order.
-__device__ void stream_epilogue(const Params &P, Ctl &c, uint32_t sidx, int64_t k, uint32_t h) {
+__device__ __forceinline__ void stream_epilogue(const Params &P, Ctl &c, uint32_t sidx, int64_t k, uint32_t h) {
   const uint32_t t = threadIdx.x;
   StreamDev *st = P.st + sidx;
   const uint32_t W = st->W;
@@ -571,6 +611,7 @@ __device__ void stream_epilogue(const Params &P, Ctl &c, uint32_t sidx, int64_t 
   const uint64_t mx = block_max_u64(mw, c);
   const uint32_t mode = (100ull * mx > (uint64_t)st->theta * N) ? HIST_MODE_AHIST : HIST_MODE_WAVEHIST;
   const uint32_t word = rule_p_word(mw, N, st->S, st->rmax, c);
+  const uint32_t kind_lg = pattern_kind_lg(word, c);
   Decision *d = &st->slots[(uint64_t)k % st->nslot];
   st_agent(&d->words[t], word);
   st_agent(&d->hist[t], h);
@@ -578,6 +619,7 @@ __device__ void stream_epilogue(const Params &P, Ctl &c, uint32_t sidx, int64_t 
     st_agent(&d->S, st->S);
     st_agent(&d->rmax, st->rmax);
     st_agent(&d->mode, mode);
+    st_agent(&d->kind_lg, kind_lg);
   }
   if ((uint64_t)k < st->trace_cap) {
     st_agent(&st->pat_trace[(size_t)k * 256u + t], c.words[t]);
@@ -592,10 +634,20 @@ __device__ void stream_epilogue(const Params &P, Ctl &c, uint32_t sidx, int64_t 
   }
 }
 
-// Merge this workgroup's table for segment s (after nt of its tiles) and finalize the
-// segment if this was its last tile.
-__device__ void flush_segment(uint32_t *lds, const Params &P, Ctl &c, uint32_t s, const SegDesc &sd, uint32_t kind,
-                              uint32_t lg, uint32_t nt) {
+// Merge of a segment, in two halves so the ticket's round trip overlaps other work.
+//
+// flush_issue: sum the LDS table down to this thread's bin and add it, with no-return
+// agent-scope atomics, into one of the segment's partial copies; thread 0 then takes a
+// ticket (tiles done so far) without waiting for its value.
+//
+// flush_resolve (later, after the next segment's descriptor loads): thread 0 reads the
+// ticket; the workgroup that completed the segment's last tile finalizes it.  The
+// finalizer does not rely on the other workgroups' atomics having landed before their
+// tickets: it re-reads the copies until the 256 totals add up to the segment's byte count.
+// Counts only grow and the exact total is known, so a matching sum means every
+// contribution is in -- no per-flush acknowledgement wait is needed.
+__device__ __forceinline__ uint32_t flush_issue(uint32_t *lds, const Params &P, Ctl &c, uint32_t s, uint32_t kind,
+                                                uint32_t lg, uint32_t nt) {
   const uint32_t t = threadIdx.x;
   __syncthreads();
   const uint32_t h = table_bin(lds, c, kind, lg);
@@ -603,29 +655,46 @@ __device__ void flush_segment(uint32_t *lds, const Params &P, Ctl &c, uint32_t s
   uint32_t *part = P.partial + ((size_t)s << (P.clog2 + 8));
   if (h) __hip_atomic_fetch_add(&part[((blockIdx.x & (copies - 1u)) << 8) | t], h, __ATOMIC_RELAXED,
                                 __HIP_MEMORY_SCOPE_AGENT);
-  order_global();
-  __syncthreads();
-  if (t == 0) {
-    const uint32_t before = atomicAdd(&P.seg_done[s], nt);
-    c.flag = (before + nt == sd.ntiles) ? 1u : 0u;
-  }
+#ifdef HISTMI_STRICT_FENCES
+  __threadfence();
+#endif
+  uint32_t before = 0;
+  if (t == 0) before = __hip_atomic_fetch_add(&P.seg_done[s], nt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return before;
+}
+
+__device__ __forceinline__ void flush_resolve(const Params &P, Ctl &c, uint32_t s, const SegDesc &sd, uint32_t before,
+                                              uint32_t nt) {
+  const uint32_t t = threadIdx.x;
+  if (t == 0) c.flag = (before + nt == sd.ntiles) ? 1u : 0u;
   __syncthreads();
   if (c.flag) {
 #ifdef HISTMI_STRICT_FENCES
     __threadfence();
 #endif
-    // read the copies eight at a time (all eight agent-scope loads in flight), then clear them
+    const uint32_t copies = 1u << P.clog2;
+    uint32_t *part = P.partial + ((size_t)s << (P.clog2 + 8));
     uint32_t tot = 0;
-    if (copies >= 8) {
-      for (uint32_t q = 0; q < copies; q += 8) {
-        uint32_t x[8];
+    for (uint32_t tries = 0;; ++tries) {
+      // read the copies eight at a time (all eight agent-scope loads in flight)
+      tot = 0;
+      if (copies >= 8) {
+        for (uint32_t q = 0; q < copies; q += 8) {
+          uint32_t x[8];
 #pragma unroll
-        for (uint32_t u = 0; u < 8; ++u) x[u] = ld_agent(&part[((q + u) << 8) | t]);
+          for (uint32_t u = 0; u < 8; ++u) x[u] = ld_agent(&part[((q + u) << 8) | t]);
 #pragma unroll
-        for (uint32_t u = 0; u < 8; ++u) tot += x[u];
+          for (uint32_t u = 0; u < 8; ++u) tot += x[u];
+        }
+      } else {
+        for (uint32_t q = 0; q < copies; ++q) tot += ld_agent(&part[(q << 8) | t]);
       }
-    } else {
-      for (uint32_t q = 0; q < copies; ++q) tot += ld_agent(&part[(q << 8) | t]);
+      if (block_sum_u64(tot, c) == sd.size) break;
+      if (tries == (1u << 20)) {   // never expected: contributions that do not land
+        if (t == 0) atomicAdd(&P.diag[2], 1u);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
     }
     for (uint32_t q = 0; q < copies; ++q) st_agent(&part[(q << 8) | t], 0u);
     if (sd.out) sd.out[t] = tot;
@@ -693,11 +762,23 @@ __global__ void __launch_bounds__(kBlock) hist_main(const Params P) {
   uint32_t cur = kNone, kind = KIND_WAVE, lg = 0, nt = 0;
   SegDesc sd;
   sd.ntiles = 0;
-  while (tile < tile_end) {
-    const uint32_t s = P.single ? 0u : P.tile_seg[tile];
-    if (s != cur) {
-      if (cur != kNone) flush_segment(lds, P, c, cur, sd, kind, lg, nt);
-      sd = load_seg(P, s);
+  // one flush site (the exit flush included), so the flush and epilogue code is inlined
+  // once: an out-of-line call taking P by reference would copy the kernel arguments to
+  // per-lane scratch
+  for (;;) {
+    const bool more = tile < tile_end;
+    const uint32_t s = !more ? kNone : (P.single ? 0u : P.tile_seg[tile]);
+    // no tiles left: flush the open segment if there is one, then leave (a workgroup whose
+    // range is empty has no open segment and leaves at once)
+    if (s != cur || !more) {
+      SegDesc next;
+      if (more) next = load_seg(P, s);                // overlaps the ticket's round trip
+      if (cur != kNone) {
+        const uint32_t before = flush_issue(lds, P, c, cur, kind, lg, nt);
+        flush_resolve(P, c, cur, sd, before, nt);
+      }
+      if (!more) break;
+      sd = next;
       kind = begin_segment(lds, P, c, sd);
       lg = c.lg;
       cur = s;
@@ -728,7 +809,6 @@ __global__ void __launch_bounds__(kBlock) hist_main(const Params P) {
       ++tile;
     }
   }
-  if (cur != kNone) flush_segment(lds, P, c, cur, sd, kind, lg, nt);
   if (P.dynamic) {
     __syncthreads();
     if (t == 0) {

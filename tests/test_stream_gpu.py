@@ -87,7 +87,7 @@ def check(hm, chunks, W=1, theta=45, S=960, rmax=8, lag=0, mode=0, many=True, un
     assert int(snap.next_mode) == O.decide_mode(ref["mw"], theta)
     assert snap.next_pattern.words() == O.rule_p(ref["mw"], S, rmax)
     d = hm.diag()
-    assert d.invalid_patterns == 0 and d.wait_timeouts == 0
+    assert d.invalid_patterns == 0 and d.wait_timeouts == 0 and d.merge_timeouts == 0
     return ref
 
 
