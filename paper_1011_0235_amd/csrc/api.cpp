@@ -295,7 +295,6 @@ hist_status_t run_single(DevCtx *d, Params &P, hipStream_t s) {
   P.nseg = 1;
   P.single = 1;
   P.ntiles = ntiles;
-  P.tile_bytes = tile;
   P.dynamic = 0;
   P.clog2 = log2u(copies);
   P.ctr = sc->ctr;
@@ -306,44 +305,60 @@ hist_status_t run_single(DevCtx *d, Params &P, hipStream_t s) {
   return dev_err(launch_hist(P, sh, s));
 }
 
-hist_status_t plan_multi(std::vector<SegDesc> &segs, uint64_t tile, uint32_t max_grid, bool balanced, MultiPlan *mp) {
+hist_status_t plan_multi(std::vector<SegDesc> &segs, uint64_t tile, uint32_t max_grid, bool balanced, bool guided,
+                         MultiPlan *mp) {
+  constexpr uint64_t kQuantum = 16384;
   const uint32_t n = (uint32_t)segs.size();
-  uint64_t nt = 0;
+  tile = std::max<uint64_t>(kQuantum, std::min<uint64_t>(tile, 1ull << 30));
+  uint64_t total = 0;
   for (uint32_t j = 0; j < n; ++j) {
     if (segs[j].size > kMaxSegBytes) return HIST_EOVERFLOW;
     if (segs[j].size && !segs[j].ptr) return HIST_EINVAL;
-    segs[j].tile0 = (uint32_t)nt;
-    segs[j].ntiles = (uint32_t)std::max<uint64_t>(1, ceil_div(segs[j].size, tile));
-    nt += segs[j].ntiles;
-    if (nt >= 0x7FFFFFFFull) return HIST_EOVERFLOW;
+    total += segs[j].size;
   }
-  const uint32_t ntiles = (uint32_t)nt;
+  std::vector<TileRec> recs;
+  recs.reserve((size_t)n + (size_t)(total / tile) + 1);
+  uint64_t done = 0;   // bytes in the tiles before the current one
+  for (uint32_t j = 0; j < n; ++j) {
+    segs[j].tile0 = (uint32_t)recs.size();
+    const uint64_t sz = segs[j].size;
+    uint64_t off = 0;
+    do {   // an empty segment still gets one (empty) tile, so that it is finalized
+      uint64_t tb = tile;
+      if (guided) {
+        // the last bytes of the launch go in smaller tiles, so that the workgroups run out of
+        // work at about the same time: a tile is at most 1/(2G) of what remains
+        const uint64_t want = ceil_div(ceil_div(total - done, (uint64_t)max_grid * 2), kQuantum) * kQuantum;
+        tb = std::min<uint64_t>(tile, std::max<uint64_t>(kQuantum, want));
+      }
+      const uint64_t len = std::min<uint64_t>(tb, sz - off);
+      recs.push_back(TileRec{reinterpret_cast<uint64_t>(segs[j].ptr) + off, (uint32_t)len, j});
+      off += len;
+      done += len;
+      if (recs.size() >= 0x7FFFFFFFull) return HIST_EOVERFLOW;
+    } while (off < sz);
+    segs[j].ntiles = (uint32_t)recs.size() - segs[j].tile0;
+  }
+  const uint32_t ntiles = (uint32_t)recs.size();
   const uint32_t G = std::max<uint32_t>(1, std::min<uint32_t>(max_grid, ntiles));
   mp->nseg = n;
   mp->ntiles = ntiles;
   mp->grid = G;
-  mp->tile = tile;
   mp->seg_bytes = ((size_t)n * sizeof(SegDesc) + 15) & ~(size_t)15;
-  mp->blob.assign(mp->seg_bytes + ((size_t)ntiles + G + 1) * 4, 0);
+  mp->rec_bytes = (size_t)ntiles * sizeof(TileRec);
+  mp->blob.assign(mp->seg_bytes + mp->rec_bytes + ((size_t)G + 1) * 4, 0);
   std::memcpy(mp->blob.data(), segs.data(), (size_t)n * sizeof(SegDesc));
-  uint32_t *map = reinterpret_cast<uint32_t *>(mp->blob.data() + mp->seg_bytes);
-  uint32_t *bounds = map + ntiles;
-  std::vector<uint64_t> wcum((size_t)ntiles + 1, 0);
-  uint32_t ti = 0;
-  for (uint32_t j = 0; j < n; ++j) {
-    for (uint32_t k = 0; k < segs[j].ntiles; ++k, ++ti) {
-      map[ti] = j;
-      const uint64_t off = (uint64_t)k * tile;
-      const uint64_t bytes = off < segs[j].size ? std::min<uint64_t>(tile, segs[j].size - off) : 0;
-      wcum[ti + 1] = wcum[ti] + bytes + 8192;   // a tile also costs its staging and merge
-    }
-  }
+  std::memcpy(mp->blob.data() + mp->seg_bytes, recs.data(), mp->rec_bytes);
+  uint32_t *bounds = reinterpret_cast<uint32_t *>(mp->blob.data() + mp->seg_bytes + mp->rec_bytes);
   if (balanced) {
-    // contiguous tile ranges of about equal cost, one per workgroup
-    const uint64_t total = wcum[ntiles];
+    // contiguous tile ranges of about equal cost, one per workgroup (a tile also costs its
+    // staging and merge)
+    std::vector<uint64_t> wcum((size_t)ntiles + 1, 0);
+    for (uint32_t i = 0; i < ntiles; ++i) wcum[i + 1] = wcum[i] + recs[i].len + 8192;
+    const uint64_t cost = wcum[ntiles];
     uint32_t k = 0;
     for (uint32_t g = 0; g <= G; ++g) {
-      const uint64_t target = (g == G) ? total : (total * g) / G;
+      const uint64_t target = (g == G) ? cost : (cost * g) / G;
       while (k < ntiles && wcum[k] < target) ++k;
       bounds[g] = (g == G) ? ntiles : k;
     }
@@ -358,11 +373,11 @@ hist_status_t run_multi(DevCtx *d, Params &P, const MultiPlan &mp, uint32_t copi
   else TRY(alloc_scratch(sc, mp.nseg, copies, upload ? 0 : mp.blob.size(), s));
   if (upload) TRY(upload_desc(sc, mp.blob.data(), mp.blob.size(), s));
   P.segs = reinterpret_cast<const SegDesc *>(sc->desc);
-  P.tile_seg = reinterpret_cast<const uint32_t *>(sc->desc + mp.seg_bytes);
+  P.recs = reinterpret_cast<const TileRec *>(sc->desc + mp.seg_bytes);
+  P.bounds = reinterpret_cast<const uint32_t *>(sc->desc + mp.seg_bytes + mp.rec_bytes);
   P.nseg = mp.nseg;
   P.single = 0;
   P.ntiles = mp.ntiles;
-  P.tile_bytes = mp.tile;
   P.dynamic = dynamic ? 1u : 0u;
   P.clog2 = log2u(copies);
   P.ctr = sc->ctr;
@@ -586,7 +601,7 @@ static hist_status_t batch_prepare(const void *const *h_ptrs, const uint64_t *h_
     segs[j].out = d_out + (size_t)j * 256;
     segs[j].chunk = -1;
   }
-  TRY(plan_multi(segs, tile, maxg, true, mp));
+  TRY(plan_multi(segs, tile, maxg, true, false, mp));
   *copies = std::min<uint32_t>(64, pow2ceil32(std::max<uint32_t>(1, g_tune[fam].copies)));
   return HIST_OK;
 }
@@ -680,6 +695,21 @@ hist_status_t hist_stream_create(hist_stream_t **out, const hist_stream_config_t
   return HIST_OK;
 }
 
+// The stream's state and the constants a chunk needs before it can start (copied into the
+// launch's parameters so that the device reads only the decision's tag).
+static void stream_params(const hist_stream *st, Params *P) {
+  P->st = st->sa.d_st;
+  P->ordered = 1;
+  P->slots = st->sa.d_slots;
+  P->lag = st->cfg.lag;
+  P->nslot = st->nslot;
+  P->W = st->cfg.W;
+  P->theta = st->cfg.theta_pct;
+  P->S = st->cfg.S;
+  P->rmax = st->cfg.rmax;
+  P->trace_cap = st->cfg.trace_cap;
+}
+
 hist_status_t hist_stream_push(hist_stream_t *st, const void *d_chunk, size_t n, hist_mode_t mode, uint32_t *d_out_k,
                                void *stream) {
   if (!st || (n && !d_chunk) || !mode_ok(mode)) return HIST_EINVAL;
@@ -689,7 +719,7 @@ hist_status_t hist_stream_push(hist_stream_t *st, const void *d_chunk, size_t n,
   Params P;
   init_params(&P);
   stream_layout(st->cfg.S, st->cfg.rmax, mode, &P);
-  P.st = st->sa.d_st;
+  stream_params(st, &P);
   P.seg0.ptr = static_cast<const uint8_t *>(d_chunk);
   P.seg0.size = n;
   P.seg0.out = d_out_k;
@@ -718,7 +748,7 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
     Params P;
     init_params(&P);
     stream_layout(st->cfg.S, st->cfg.rmax, mode, &P);
-    P.st = st->sa.d_st;
+    stream_params(st, &P);
     P.chunk_base = st->pushed;
     const uint32_t fam = KIND_UNIFORM;
     const uint32_t maxg = (uint32_t)d->cus * blocks_per_cu(fam, lds_bytes(P));
@@ -741,7 +771,7 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
       segs[j].stream_idx = 0;
     }
     MultiPlan mp;
-    TRY(plan_multi(segs, tile, maxg, false, &mp));
+    TRY(plan_multi(segs, tile, maxg, false, false, &mp));
     const uint32_t copies = std::min<uint32_t>(64, pow2ceil32(std::max<uint32_t>(1, g_tune[fam].copies)));
     // tiles are handed out in chunk order, so a chunk waiting for an earlier chunk's decision
     // never waits on a workgroup that has not started
@@ -765,7 +795,7 @@ hist_status_t hist_stream_read(hist_stream_t *st, hist_stream_snapshot_t *snap, 
     if (h.done > 0) {
       Decision dec;
       TRY_HIP(hipMemcpy(&dec, st->sa.d_slots + (h.done - 1) % st->nslot, sizeof(dec), hipMemcpyDeviceToHost));
-      snap->next_mode = dec.mode;
+      snap->next_mode = tag_mode(dec.tag);
       if (st->cfg.W == 1)
         for (int v = 0; v < 256; ++v) snap->mw[v] = dec.hist[v];
       std::memcpy(snap->next_pattern.word, dec.words, sizeof(dec.words));

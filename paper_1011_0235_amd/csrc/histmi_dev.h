@@ -26,10 +26,18 @@ struct Decision {
   uint32_t words[256];   // binning pattern words (hist_pattern_t encoding)
   uint32_t hist[256];    // histogram of the producing chunk (the moving window when W = 1)
   uint32_t S, rmax;
-  uint32_t mode;         // HIST_MODE_AHIST or HIST_MODE_WAVEHIST
-  uint32_t kind_lg;      // table kind of the pattern (KIND_UNIFORM or KIND_LOOKUP) << 8 | log2 r if uniform
-  uint32_t gen;          // index of the producing chunk + 1; stored last
+  // stored last, in one 64-bit store, so that one load both says whether the decision is
+  // there and carries what a uniform table needs:
+  //   bits [32,64) producing chunk index + 1 (0: none yet), [16,24) mode (HIST_MODE_*),
+  //   [0,16) table kind of the pattern (KIND_UNIFORM or KIND_LOOKUP) << 8 | log2 r if uniform
+  uint64_t tag;
 };
+__host__ __device__ constexpr uint64_t make_tag(uint64_t gen, uint32_t mode, uint32_t kind_lg) {
+  return (gen << 32) | ((uint64_t)(mode & 0xFFu) << 16) | (kind_lg & 0xFFFFu);
+}
+__host__ __device__ constexpr uint32_t tag_gen(uint64_t tag) { return (uint32_t)(tag >> 32); }
+__host__ __device__ constexpr uint32_t tag_mode(uint64_t tag) { return (uint32_t)(tag >> 16) & 0xFFu; }
+__host__ __device__ constexpr uint32_t tag_kind_lg(uint64_t tag) { return (uint32_t)tag & 0xFFFFu; }
 
 // Device-resident state of one stream (Accumulator, moving window, decisions, traces).
 struct StreamDev {
@@ -58,13 +66,22 @@ struct SegDesc {
 
 constexpr int64_t kServerChunk = -2;
 
+// One tile of a multi-segment launch, written by the host: its bytes and its segment.
+// Tiles never span segments; their sizes may differ (smaller tiles near the end of a
+// launch shorten the tail).
+struct TileRec {
+  uint64_t addr;         // first byte
+  uint32_t len;          // bytes (0 for the single tile of an empty segment)
+  uint32_t seg;          // index into Params::segs
+};
+
 struct Params {
   const SegDesc *segs;       // device array of nseg descriptors (unused when single)
   SegDesc seg0;              // the descriptor when single
-  const uint32_t *tile_seg;  // device map tile -> segment, then per-workgroup tile bounds (unused when single)
+  const TileRec *recs;       // [ntiles] tiles in launch order (unused when single)
+  const uint32_t *bounds;    // [grid + 1] static launches: workgroup g takes tiles [bounds[g], bounds[g+1])
   uint32_t nseg;
   uint32_t ntiles;
-  uint64_t tile_bytes;
   uint32_t single;           // 1: one buffer described by seg0, spread over the whole grid
   uint32_t dynamic;          // 1: tiles handed out in order by an atomic counter; 0: static
   uint32_t clog2;            // log2 of the partial copies per segment
@@ -82,7 +99,18 @@ struct Params {
   StreamDev *st;             // array of stream states
   uint64_t chunk_base;       // absolute index of relative chunk 0
   uint32_t forced;           // 0 = decided per chunk, else HIST_MODE_AHIST / HIST_MODE_WAVEHIST
+  // ordered stream launches (one stream, segment j is chunk chunk_base + j): copies of the
+  // stream's constants, so that starting a chunk reads nothing but its decision's tag
+  uint32_t ordered;          // 1 for an ordered stream launch
+  uint32_t lag;
+  uint32_t nslot;
+  uint32_t W;                // moving-window length in chunks
+  uint32_t theta;            // critical degeneracy, percent
+  uint32_t S;                // sub-bin budget of rule P
+  uint32_t rmax;             // sub-bin cap of rule P
   uint32_t pad;
+  uint64_t trace_cap;
+  Decision *slots;           // the stream's decision ring
   // LDS layout (in 32-bit words)
   uint32_t table_words;      // counting table at word 0
   uint32_t look_off;         // lane-replicated lookup table (byte addresses into the counting table)

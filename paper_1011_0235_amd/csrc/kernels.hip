@@ -52,6 +52,9 @@ struct Ctl {
   uint32_t lg;
   uint32_t used_mode;
   uint32_t tmp;
+  uint64_t tag;            // decision tag of the current segment's stream chunk
+  SegDesc sd;              // the current segment (multi-segment launches)
+  TileRec nrec;            // the next tile's record (multi-segment launches)
   uint32_t red32[kWaves];
   uint64_t red64[kWaves];
   uint32_t cls_cnt[kWaves][8];
@@ -174,6 +177,24 @@ __device__ bool spin_until_u64(const uint64_t *p, uint64_t want, uint32_t *diag)
   return false;
 }
 
+// Bounded spin by thread 0 until the decision tag at p carries generation `gen`.  Returns
+// the tag, or 0 on timeout (counted in diag[1]): the caller then runs the per-wavefront
+// kernel, which needs no pattern, so a timeout costs speed and a trace entry, never counts.
+__device__ uint64_t spin_for_tag(const uint64_t *p, uint32_t gen, uint32_t *diag) {
+  for (uint32_t i = 0; i < (1u << 22); ++i) {
+    const uint64_t tag = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tag_gen(tag) == gen) {
+#ifdef HISTMI_STRICT_FENCES
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+#endif
+      return tag;
+    }
+    __builtin_amdgcn_s_sleep(8);
+  }
+  atomicAdd(&diag[1], 1u);
+  return 0;
+}
+
 // ------------------------------------------------------------------ rule P on the device
 //
 // Pattern from a past histogram (the paper recomputes the indices from the past stream's
@@ -283,16 +304,12 @@ __device__ uint32_t classify_pattern(Ctl &c, uint32_t S, uint32_t rmax, uint32_t
   return have_lookup ? KIND_LOOKUP : KIND_WAVE;
 }
 
-// Zero the counting table for `kind` and (KIND_LOOKUP) build the lane-replicated lookup:
+// KIND_LOOKUP: build the lane-replicated lookup table,
 // look[v * RR + j] = byte address of sub-bin base(v) + (j mod r(v)), j = lane mod RR.
-__device__ __forceinline__ void stage_table(uint32_t *lds, const Params &P, Ctl &c, uint32_t kind, uint32_t lg, uint32_t S) {
+// (The counting table itself is already zero: see table_bin.)  Other kinds need nothing.
+__device__ __forceinline__ void stage_table(uint32_t *lds, const Params &P, Ctl &c, uint32_t kind) {
   const uint32_t t = threadIdx.x;
-  if (kind == KIND_WAVE || kind == KIND_WAVE_AGG) {
-    zero_words(lds, kWaves * 256);
-  } else if (kind == KIND_UNIFORM) {
-    zero_words(lds, 256u << lg);
-  } else {
-    zero_words(lds, (S + 3u) & ~3u);
+  if (kind == KIND_LOOKUP) {
     const uint32_t w = c.words[t];
     const uint32_t base = w & 0xFFFFu, rmask = (1u << ((w >> 16) & 0xFFu)) - 1u;
     const uint32_t rr_lg = P.look_rr_lg, rr = 1u << rr_lg;
@@ -302,8 +319,8 @@ __device__ __forceinline__ void stage_table(uint32_t *lds, const Params &P, Ctl 
       const uint32_t jj = (j + t) & (rr - 1u);     // rotate so a wavefront's stores hit distinct banks
       look[jj] = tb + ((base + (jj & rmask)) << 2);
     }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
 // ------------------------------------------------------------------ the hot loop
@@ -348,10 +365,10 @@ struct Adder {
   }
 };
 
-// Count U 16-byte vectors per lane while the next U are already in flight: the loads of
-// step q + 1 are issued before the bytes of step q go into the table, so every wave keeps
-// U x 1 KiB of HBM reads outstanding while it works on the LDS.
-template <int KIND, int U>
+// U 16-byte vectors per lane (U x 1 KiB per wavefront): the unit of the load pipeline.  The
+// loads of step q + 1 are issued before the bytes of step q go into the table, so every wave
+// keeps U x 1 KiB of HBM reads outstanding while it works on the LDS.
+template <int U>
 struct Pipe {
   u32x4 cur[U];
   __device__ __forceinline__ void load(gu32x4 *v, uint64_t i, uint64_t stride) {
@@ -360,44 +377,75 @@ struct Pipe {
   }
 };
 
-// Add bytes [p, p + len) into the table.  The 16-byte aligned middle goes through wide
-// loads (1 KiB per wavefront per load, U loads per step, next step prefetched); the
-// unaligned head and tail (< 16 bytes each) through single-byte loads.  `rot` rotates where
-// in the range the workgroup starts, so that workgroups working on equal-sized tiles at the
-// same time do not all address the same HBM channels.
-template <int KIND, int U>
-__device__ void run_range(uint32_t *lds, const Adder<KIND> &ad, const uint8_t *p, uint64_t len, uint32_t rot) {
+// A tile's bytes [a0, a0 + len) as the wide loads see them: nv 16-byte vectors from the
+// aligned address b0, in nfull whole steps of U x 4 KiB (the workgroup starts at step r0 and
+// wraps, so that workgroups working on equal-sized tiles at the same time do not all address
+// the same HBM channels), then the remaining vectors; the unaligned head and tail (< 16
+// bytes each) go through single-byte loads.  Only a0 and len are kept between priming and
+// counting; the rest is recomputed (a few scalar operations) to save registers.
+struct Range {
+  uint64_t a0, len;
+};
+template <int U>
+struct RangeLayout {
+  static constexpr uint64_t step = (uint64_t)U * kBlock;
+  uint64_t b0, nv, nfull, r0;
+  __device__ __forceinline__ RangeLayout(const Range &r, uint32_t rot) {
+    const uint64_t a1 = r.a0 + r.len;
+    b0 = (r.a0 + 15u) & ~(uint64_t)15u;
+    const uint64_t b1 = a1 & ~(uint64_t)15u;
+    nv = b0 < b1 ? (b1 - b0) >> 4 : 0u;
+    nfull = nv / step;
+    r0 = nfull ? (uint64_t)rot % nfull : 0u;
+  }
+};
+
+// Issue the tile's first step of loads.  The loads carry no table state, so a tile can be
+// primed before the workgroup knows which table its segment will count into.
+template <int U>
+__device__ __forceinline__ Range prime_range(Pipe<U> &a, uint64_t a0, uint64_t len, uint32_t rot) {
+  const Range r{a0, len};
+  const RangeLayout<U> L(r, rot);
+  if (L.nfull) a.load((gu32x4 *)L.b0, L.r0 * L.step + threadIdx.x, kBlock);
+  return r;
+}
+
+// Count a primed tile.  mid() runs once, halfway through the tile's steps (at the start when
+// the tile has fewer than two steps): it gives the workgroup's control thread a point at
+// which earlier requests have long returned, to read them and issue follow-up loads.
+template <int KIND, int U, typename Mid>
+__device__ __forceinline__ void run_primed(const Adder<KIND> &ad, const Range &r, uint32_t rot, Pipe<U> &a,
+                                           Mid &&mid) {
+  const RangeLayout<U> L(r, rot);
+  const uint64_t step = L.step;
   const uint32_t t = threadIdx.x;
-  const uintptr_t a0 = reinterpret_cast<uintptr_t>(p), a1 = a0 + len;
-  const uintptr_t b0 = (a0 + 15u) & ~static_cast<uintptr_t>(15u), b1 = a1 & ~static_cast<uintptr_t>(15u);
-  gu8 *pg = (gu8 *)p;
-  if (b0 >= b1) {
-    for (uint64_t i = t; i < len; i += kBlock) ad.add(pg[i]);
+  gu8 *pg = (gu8 *)r.a0;
+  if (L.nfull < 2) mid();
+  if (L.nv == 0) {
+    for (uint64_t i = t; i < r.len; i += kBlock) ad.add(pg[i]);
     return;
   }
-  if (t < b0 - a0) ad.add(pg[t]);
+  const uint64_t b1 = L.b0 + (L.nv << 4), a1 = r.a0 + r.len;
+  if (t < L.b0 - r.a0) ad.add(pg[t]);
   if (t < a1 - b1) ad.add(((gu8 *)b1)[t]);
-  gu32x4 *v = (gu32x4 *)b0;
-  const uint64_t nv = (b1 - b0) >> 4;
-  constexpr uint64_t step = (uint64_t)U * kBlock;
-  const uint64_t nfull = nv / step;                  // whole steps of U x 4 KiB
-  if (nfull) {
-    const uint64_t r0 = (uint64_t)rot % nfull;
-    Pipe<KIND, U> a, b;
-    a.load(v, r0 * step + t, kBlock);
-    for (uint64_t q = 0; q < nfull; ++q) {
-      const bool more = q + 1 < nfull;
+  gu32x4 *v = (gu32x4 *)L.b0;
+  if (L.nfull) {
+    Pipe<U> b;
+    const uint64_t half = L.nfull >> 1;
+    for (uint64_t q = 0; q < L.nfull; ++q) {
+      const bool more = q + 1 < L.nfull;
       if (more) {
-        uint64_t s1 = q + 1 + r0;
-        if (s1 >= nfull) s1 -= nfull;
+        uint64_t s1 = q + 1 + L.r0;
+        if (s1 >= L.nfull) s1 -= L.nfull;
         b.load(v, s1 * step + t, kBlock);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) ad.add16(a.cur[u]);
       if (more) a = b;
+      if (q + 1 == half) mid();
     }
   }
-  for (uint64_t i = nfull * step + t; i < nv; i += kBlock) ad.add16(__builtin_nontemporal_load(v + i));
+  for (uint64_t i = L.nfull * step + t; i < L.nv; i += kBlock) ad.add16(__builtin_nontemporal_load(v + i));
 }
 
 // One buffer spread over the whole grid: workgroup g takes the 4 KiB blocks g, g + G,
@@ -426,7 +474,7 @@ __device__ void run_strided(uint32_t *lds, const Adder<KIND> &ad, const uint8_t 
   uint64_t base = (uint64_t)g * kBlock;
   const uint64_t span = (uint64_t)(U - 1) * stride + (kBlock - 1);
   if (base + span < nv) {
-    Pipe<KIND, U> a, b;
+    Pipe<U> a, b;
     a.load(v, base + t, stride);
     for (;;) {
       const uint64_t nb = base + (uint64_t)U * stride;
@@ -442,20 +490,33 @@ __device__ void run_strided(uint32_t *lds, const Adder<KIND> &ad, const uint8_t 
   for (uint64_t i = base + t; i < nv; i += stride) ad.add16(__builtin_nontemporal_load(v + i));
 }
 
-// Sum this thread's bin (value t) out of the table.
-__device__ uint32_t table_bin(const uint32_t *lds, const Ctl &c, uint32_t kind, uint32_t lg) {
+// Sum this thread's bin (value t) out of the table, clearing each sub-bin as it is read.
+// Every sub-bin the adds can touch belongs to exactly one value, so after all threads have
+// done this the whole counting table is zero again and the next segment needs no clearing
+// pass (the table is cleared once when the workgroup starts).
+__device__ uint32_t table_bin(uint32_t *lds, const Ctl &c, uint32_t kind, uint32_t lg) {
   const uint32_t t = threadIdx.x;
   uint32_t h = 0;
   if (kind == KIND_WAVE || kind == KIND_WAVE_AGG) {
 #pragma unroll
-    for (uint32_t w = 0; w < kWaves; ++w) h += lds[(w << 8) | t];
+    for (uint32_t w = 0; w < kWaves; ++w) {
+      h += lds[(w << 8) | t];
+      lds[(w << 8) | t] = 0u;
+    }
   } else if (kind == KIND_UNIFORM) {
     const uint32_t r = 1u << lg;
-    for (uint32_t j = 0; j < r; ++j) h += lds[(t << lg) | ((j + t) & (r - 1u))];   // rotated: distinct banks
+    for (uint32_t j = 0; j < r; ++j) {
+      const uint32_t i = (t << lg) | ((j + t) & (r - 1u));   // rotated: distinct banks
+      h += lds[i];
+      lds[i] = 0u;
+    }
   } else {
     const uint32_t w = c.words[t];
     const uint32_t base = w & 0xFFFFu, r = 1u << ((w >> 16) & 0xFFu);
-    for (uint32_t j = 0; j < r; ++j) h += lds[base + j];
+    for (uint32_t j = 0; j < r; ++j) {
+      h += lds[base + j];
+      lds[base + j] = 0u;
+    }
   }
   return h;
 }
@@ -468,7 +529,8 @@ __device__ __forceinline__ SegDesc load_seg(const Params &P, uint32_t s) {
 
 // Stage segment `sd`: pick the table kind (from the launch, or from the stream's decision)
 // and prepare the LDS.  Returns the kind; sets c.lg / c.used_mode / c.words.
-__device__ __forceinline__ uint32_t begin_segment(uint32_t *lds, const Params &P, Ctl &c, const SegDesc &sd) {
+__device__ __forceinline__ uint32_t begin_segment(uint32_t *lds, const Params &P, Ctl &c, const SegDesc &sd,
+                                                  uint64_t hint) {
   const uint32_t t = threadIdx.x;
   uint32_t kind;
   uint32_t S = P.pat_S;
@@ -482,59 +544,64 @@ __device__ __forceinline__ uint32_t begin_segment(uint32_t *lds, const Params &P
   } else {
     StreamDev *st = P.st + sd.stream_idx;
     const int64_t k = (int64_t)P.chunk_base + sd.chunk;
-    const int64_t j = (sd.chunk == kServerChunk) ? -2 : k - 1 - (int64_t)st->lag;
     uint32_t dmode;
     if (sd.chunk == kServerChunk) {
       // served request: the stream's latest decision, whatever has been published (no wait)
       const Decision *d = &st->slots[0];
-      const uint32_t gen = ld_agent(&d->gen);
-      if (gen == 0) {
+      const uint64_t tag = ld_agent(&d->tag);
+      if (tag_gen(tag) == 0) {
         c.words[t] = t;
         dmode = HIST_MODE_WAVEHIST;
         S = 256;
       } else {
         c.words[t] = ld_agent(&d->words[t]);
-        dmode = ld_agent(&d->mode);
+        dmode = tag_mode(tag);
         S = ld_agent(&d->S);
       }
     } else {
-      // an ordered stream's decision was made by this library's own epilogue: its table kind
-      // comes with it, and the pattern words are read only when the lookup table or the
-      // trace needs them
-      uint32_t kind_lg = ((uint32_t)KIND_UNIFORM << 8);   // no history: identity pattern
-      dmode = HIST_MODE_WAVEHIST;
-      const bool traced = (uint64_t)k < st->trace_cap;
-      if (j >= 0) {
-        const Decision *d = &st->slots[(uint64_t)j % st->nslot];
-        if (t == 0) spin_until_u32(&d->gen, (uint32_t)(j + 1), P.diag);
-        __syncthreads();
-        dmode = ld_agent(&d->mode);
-        kind_lg = ld_agent(&d->kind_lg);
-        if (traced || (kind_lg >> 8) == KIND_LOOKUP) {
-          c.words[t] = ld_agent(&d->words[t]);
-          S = ld_agent(&d->S);
+      // an ordered stream's decision was made by this library's own epilogue: thread 0 takes
+      // its tag (one load, usually already done at the switch: see tag_prefetch), decides the
+      // table from it and publishes the choice with one barrier; the pattern words are read
+      // only when the lookup table or the trace needs them
+      const int64_t j = k - 1 - (int64_t)P.lag;
+      const bool traced = (uint64_t)k < P.trace_cap;
+      const Decision *d = &P.slots[(uint64_t)(j >= 0 ? j : 0) % P.nslot];
+      if (t == 0) {
+        // no history, or (never expected) a wait that timed out: the per-wavefront kernel
+        // with the identity pattern
+        uint64_t tag = make_tag(0, HIST_MODE_WAVEHIST, (uint32_t)KIND_UNIFORM << 8);
+        if (j >= 0) {
+          const uint32_t want = (uint32_t)(j + 1);
+          const uint64_t got = (tag_gen(hint) == want) ? hint : spin_for_tag(&d->tag, want, P.diag);
+          if (got) tag = got;
         }
-      } else {
-        c.words[t] = t;
-        S = 256;
-      }
-      const uint32_t mode = P.forced ? P.forced : dmode;
-      if (mode == HIST_MODE_AHIST) {
-        kind = kind_lg >> 8;
-        c.lg = kind_lg & 0xFFu;
-        if ((kind == KIND_LOOKUP && (P.look_words == 0 || S > P.pat_S)) ||
-            (kind == KIND_UNIFORM && (256u << c.lg) > P.table_words) || kind > KIND_LOOKUP) {
-          kind = KIND_WAVE;   // no room for this pattern's tables (cannot happen with rule P)
-          if (t == 0) atomicAdd(&P.diag[0], 1u);
+        const uint32_t mode = P.forced ? P.forced : tag_mode(tag);
+        const uint32_t kind_lg = tag_kind_lg(tag);
+        uint32_t kd, lg = 0;
+        if (mode == HIST_MODE_AHIST) {
+          kd = kind_lg >> 8;
+          lg = kind_lg & 0xFFu;
+          const uint32_t Sd = (kd == KIND_LOOKUP && tag_gen(tag) != 0) ? ld_agent(&d->S) : 256u;
+          if ((kd == KIND_LOOKUP && (P.look_words == 0 || Sd > P.pat_S)) ||
+              (kd == KIND_UNIFORM && (256u << lg) > P.table_words) || kd > KIND_LOOKUP) {
+            kd = KIND_WAVE;   // no room for this pattern's tables (cannot happen with rule P)
+            atomicAdd(&P.diag[0], 1u);
+          }
+        } else {
+          kd = (mode == HIST_MODE_WAVEAGG) ? KIND_WAVE_AGG : KIND_WAVE;
         }
-      } else {
-        kind = (mode == HIST_MODE_WAVEAGG) ? KIND_WAVE_AGG : KIND_WAVE;
+        c.tag = tag;
+        c.kind = kd;
+        c.lg = lg;
+        c.used_mode = (kd == KIND_WAVE) ? HIST_MODE_WAVEHIST : (kd == KIND_WAVE_AGG) ? HIST_MODE_WAVEAGG
+                                                                                     : HIST_MODE_AHIST;
       }
-      if (t == 0)
-        c.used_mode = (kind == KIND_WAVE) ? HIST_MODE_WAVEHIST : (kind == KIND_WAVE_AGG) ? HIST_MODE_WAVEAGG
-                                                                                         : HIST_MODE_AHIST;
       __syncthreads();
-      stage_table(lds, P, c, kind, c.lg, S);
+      kind = c.kind;
+      // each thread writes and later reads only its own value's word (lookup staging, table
+      // sums, trace), so no barrier is needed after this
+      if (kind == KIND_LOOKUP || traced) c.words[t] = (tag_gen(c.tag) != 0) ? ld_agent(&d->words[t]) : t;
+      stage_table(lds, P, c, kind);
       return kind;
     }
     const uint32_t mode = P.forced ? P.forced : dmode;
@@ -552,7 +619,7 @@ __device__ __forceinline__ uint32_t begin_segment(uint32_t *lds, const Params &P
                                                                                        : HIST_MODE_AHIST;
     __syncthreads();
   }
-  stage_table(lds, P, c, kind, c.lg, S);
+  stage_table(lds, P, c, kind);
   return kind;
 }
 
@@ -576,12 +643,10 @@ __device__ __forceinline__ void server_epilogue(const Params &P, Ctl &c, uint32_
   if (t == 0) {
     st_agent(&d->S, st->S);
     st_agent(&d->rmax, st->rmax);
-    st_agent(&d->mode, mode);
-    st_agent(&d->kind_lg, kind_lg);
   }
   order_global();
   __syncthreads();
-  if (t == 0) __hip_atomic_fetch_add(&d->gen, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (t == 0) st_agent(&d->tag, make_tag(1, mode, kind_lg));   // generation 1: "a decision exists"
 }
 
 // Stream epilogue for chunk k with histogram h (thread t holds bin t): Accumulator, moving
@@ -592,7 +657,7 @@ __device__ __forceinline__ void server_epilogue(const Params &P, Ctl &c, uint32_
 __device__ __forceinline__ void stream_epilogue(const Params &P, Ctl &c, uint32_t sidx, int64_t k, uint32_t h) {
   const uint32_t t = threadIdx.x;
   StreamDev *st = P.st + sidx;
-  const uint32_t W = st->W;
+  const uint32_t W = P.W;
   atomicAdd(reinterpret_cast<unsigned long long *>(&st->acc[t]), (unsigned long long)h);
   uint64_t mw;
   if (W == 1) {
@@ -609,26 +674,31 @@ __device__ __forceinline__ void stream_epilogue(const Params &P, Ctl &c, uint32_
   // degeneracy of the window: AHist iff some bin exceeds theta percent (strict)
   const uint64_t N = block_sum_u64(mw, c);
   const uint64_t mx = block_max_u64(mw, c);
-  const uint32_t mode = (100ull * mx > (uint64_t)st->theta * N) ? HIST_MODE_AHIST : HIST_MODE_WAVEHIST;
-  const uint32_t word = rule_p_word(mw, N, st->S, st->rmax, c);
+  const uint32_t mode = (100ull * mx > (uint64_t)P.theta * N) ? HIST_MODE_AHIST : HIST_MODE_WAVEHIST;
+  const uint32_t word = rule_p_word(mw, N, P.S, P.rmax, c);
   const uint32_t kind_lg = pattern_kind_lg(word, c);
-  Decision *d = &st->slots[(uint64_t)k % st->nslot];
+  Decision *d = &P.slots[(uint64_t)k % P.nslot];
+  // The chunk that runs with this decision (k + 1 + lag) reads the pattern words only for a
+  // lookup table or for its trace.  Otherwise the tag alone carries the decision, and it is
+  // published at once instead of after the other stores are acknowledged: that shortens the
+  // path from this chunk's last tile to the chunks that wait for it.
+  const uint64_t tag = make_tag((uint64_t)(k + 1), mode, kind_lg);
+  const bool words_needed = (kind_lg >> 8) == KIND_LOOKUP || (uint64_t)k + 1 + P.lag < P.trace_cap;
+  if (!words_needed && t == 0) st_agent(&d->tag, tag);
   st_agent(&d->words[t], word);
   st_agent(&d->hist[t], h);
   if (t == 0) {
-    st_agent(&d->S, st->S);
-    st_agent(&d->rmax, st->rmax);
-    st_agent(&d->mode, mode);
-    st_agent(&d->kind_lg, kind_lg);
+    st_agent(&d->S, P.S);
+    st_agent(&d->rmax, P.rmax);
   }
-  if ((uint64_t)k < st->trace_cap) {
+  if ((uint64_t)k < P.trace_cap) {
     st_agent(&st->pat_trace[(size_t)k * 256u + t], c.words[t]);
     if (t == 0) st->mode_trace[k] = (uint8_t)c.used_mode;
   }
   order_global();
   __syncthreads();
   if (t == 0) {
-    __hip_atomic_store(&d->gen, (uint32_t)(k + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (words_needed) st_agent(&d->tag, tag);
     if (W == 1) __hip_atomic_fetch_add(&st->done, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     else __hip_atomic_store(&st->done, (uint64_t)(k + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
@@ -726,88 +796,124 @@ __device__ __forceinline__ Adder<KIND> make_adder(const uint32_t *lds, const Par
   return ad;
 }
 
-template <int KIND, int U>
-__device__ __forceinline__ void run_tile(uint32_t *lds, const Params &P, const Ctl &c, const uint8_t *p, uint64_t len,
-                                         bool strided, uint32_t rot) {
-  const Adder<KIND> ad = make_adder<KIND>(lds, P, c);
-  if (strided) run_strided<KIND, U>(lds, ad, p, len);
-  else run_range<KIND, U>(lds, ad, p, len, rot);
+// Decision tag of segment s's chunk in an ordered stream launch, loaded by thread 0 without
+// waiting, so that its round trip overlaps the other loads of a segment switch (0: nothing
+// to load, or another thread).
+__device__ __forceinline__ uint64_t tag_prefetch(const Params &P, uint32_t s) {
+  if (!P.ordered || threadIdx.x != 0) return 0;
+  const int64_t j = (int64_t)P.chunk_base + (int64_t)s - 1 - (int64_t)P.lag;
+  if (j < 0) return 0;
+  return ld_agent(&P.slots[(uint64_t)j % P.nslot].tag);
 }
 
+// One buffer spread over the whole grid (single launches): every workgroup strides over the
+// buffer and flushes once.
 template <int U>
-__global__ void __launch_bounds__(kBlock) hist_main(const Params P) {
-  // one dynamic LDS block: the counting table at address 0 (so table addresses need no
-  // base offset), the lookup table after it, the control block at the end
-  extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
-  Ctl &c = *reinterpret_cast<Ctl *>(lds + P.table_words + P.look_words);
-  const uint32_t t = threadIdx.x;
+__device__ __forceinline__ void single_path(uint32_t *lds, const Params &P, Ctl &c) {
+  if (blockIdx.x >= P.ntiles) return;
+  const SegDesc sd = P.seg0;
+  const uint32_t kind = begin_segment(lds, P, c, sd, tag_prefetch(P, 0));
+  const uint32_t lg = c.lg;
+  if (kind == KIND_WAVE) run_strided<KIND_WAVE, U>(lds, make_adder<KIND_WAVE>(lds, P, c), sd.ptr, sd.size);
+  else if (kind == KIND_WAVE_AGG) run_strided<KIND_WAVE_AGG, U>(lds, make_adder<KIND_WAVE_AGG>(lds, P, c), sd.ptr, sd.size);
+  else if (kind == KIND_UNIFORM) run_strided<KIND_UNIFORM, U>(lds, make_adder<KIND_UNIFORM>(lds, P, c), sd.ptr, sd.size);
+  else run_strided<KIND_LOOKUP, U>(lds, make_adder<KIND_LOOKUP>(lds, P, c), sd.ptr, sd.size);
+  const uint32_t before = flush_issue(lds, P, c, 0, kind, lg, 1);
+  flush_resolve(P, c, 0, sd, before, 1);
+}
 
-  uint32_t tile;
-  uint32_t tile_end = P.ntiles;
+// The segment descriptor is staged through LDS (c.sd) rather than held in registers: lanes
+// 0..kSegWords-1 each load one word of it, so the load can be in flight across the flush of
+// the previous segment without tying up scalar registers.
+constexpr uint32_t kSegWords = sizeof(SegDesc) / 4;
+__device__ __forceinline__ uint32_t seg_word(const Params &P, uint32_t s) {
+  const uint32_t t = threadIdx.x;
+  return t < kSegWords ? reinterpret_cast<const uint32_t *>(P.segs + s)[t] : 0u;
+}
+__device__ __forceinline__ void seg_commit(Ctl &c, uint32_t w) {
+  if (threadIdx.x < kSegWords) reinterpret_cast<uint32_t *>(&c.sd)[threadIdx.x] = w;
+  __syncthreads();
+}
+
+// Many segments cut into tiles (batches, stream pushes, server batches).  A workgroup takes
+// its next tile when it starts a tile (dynamic: from an atomic counter, in launch order, so a
+// workgroup waiting for an earlier chunk's decision only waits for tiles that running
+// workgroups hold; static: the next tile of its contiguous range).  Halfway through the tile
+// its control thread reads that tile's index and loads its record.  At the end of the tile
+// the next tile's first loads are issued, and -- when the segment changes -- the next
+// descriptor and decision tag are loaded while the workgroup flushes and takes its ticket,
+// so a segment switch waits for about one memory round trip, with the data on its way.
+template <int U>
+__device__ __forceinline__ void multi_path(uint32_t *lds, const Params &P, Ctl &c) {
+  const uint32_t t = threadIdx.x;
+  uint32_t tile, tile_end = P.ntiles;
   if (P.dynamic) {
     if (t == 0) c.next_tile = atomicAdd(&P.ctr[0], 1u);
     __syncthreads();
     tile = c.next_tile;
     __syncthreads();
-  } else if (P.single) {
-    tile = blockIdx.x;               // one tile per workgroup
-    tile_end = tile < P.ntiles ? tile + 1 : tile;
   } else {
-    // contiguous, byte-balanced tile range per workgroup: bounds stored after the tile map
-    const uint32_t *bounds = P.tile_seg + P.ntiles;
-    tile = bounds[blockIdx.x];
-    tile_end = bounds[blockIdx.x + 1];
+    tile = P.bounds[blockIdx.x];
+    tile_end = P.bounds[blockIdx.x + 1];
   }
-
+  const uint32_t rot = blockIdx.x * 7u;
+  Pipe<U> a;
+  Range rg;
   uint32_t cur = kNone, kind = KIND_WAVE, lg = 0, nt = 0;
-  SegDesc sd;
-  sd.ntiles = 0;
-  // one flush site (the exit flush included), so the flush and epilogue code is inlined
-  // once: an out-of-line call taking P by reference would copy the kernel arguments to
-  // per-lane scratch
-  for (;;) {
-    const bool more = tile < tile_end;
-    const uint32_t s = !more ? kNone : (P.single ? 0u : P.tile_seg[tile]);
-    // no tiles left: flush the open segment if there is one, then leave (a workgroup whose
-    // range is empty has no open segment and leaves at once)
-    if (s != cur || !more) {
-      SegDesc next;
-      if (more) next = load_seg(P, s);                // overlaps the ticket's round trip
-      if (cur != kNone) {
-        const uint32_t before = flush_issue(lds, P, c, cur, kind, lg, nt);
-        flush_resolve(P, c, cur, sd, before, nt);
-      }
-      if (!more) break;
-      sd = next;
-      kind = begin_segment(lds, P, c, sd);
-      lg = c.lg;
-      cur = s;
-      nt = 0;
-    }
-    uint32_t next_req = 0;
-    if (P.dynamic && t == 0) next_req = atomicAdd(&P.ctr[0], 1u);   // hide the grab behind this tile
-    // a one-buffer static launch spreads the whole buffer over the grid; otherwise the
-    // workgroup takes its tile, starting at a rotated position
-    const bool strided = P.single && !P.dynamic;
-    uint64_t off = 0, len = sd.size;
-    if (!strided) {
-      off = (uint64_t)(tile - sd.tile0) * P.tile_bytes;
-      len = off < sd.size ? (sd.size - off < P.tile_bytes ? sd.size - off : P.tile_bytes) : 0u;
-    }
-    const uint32_t rot = blockIdx.x * 7u;
-    if (kind == KIND_WAVE) run_tile<KIND_WAVE, U>(lds, P, c, sd.ptr + off, len, strided, rot);
-    else if (kind == KIND_WAVE_AGG) run_tile<KIND_WAVE_AGG, U>(lds, P, c, sd.ptr + off, len, strided, rot);
-    else if (kind == KIND_UNIFORM) run_tile<KIND_UNIFORM, U>(lds, P, c, sd.ptr + off, len, strided, rot);
-    else run_tile<KIND_LOOKUP, U>(lds, P, c, sd.ptr + off, len, strided, rot);
+  if (tile < tile_end) {
+    const TileRec r0 = P.recs[tile];
+    const uint32_t w = seg_word(P, r0.seg);
+    const uint64_t hint = tag_prefetch(P, r0.seg);
+    rg = prime_range<U>(a, r0.addr, r0.len, rot);
+    cur = r0.seg;
+    seg_commit(c, w);
+    kind = begin_segment(lds, P, c, c.sd, hint);
+    lg = c.lg;
+  }
+  while (tile < tile_end) {
+    uint32_t req = tile + 1;
+    if (P.dynamic && t == 0) req = atomicAdd(&P.ctr[0], 1u);
+    TileRec rn;
+    rn.addr = 0;
+    rn.len = 0;
+    rn.seg = kNone;
+    auto mid = [&]() {
+      if (t == 0 && req < tile_end) rn = P.recs[req];
+    };
+    if (kind == KIND_WAVE) run_primed<KIND_WAVE, U>(make_adder<KIND_WAVE>(lds, P, c), rg, rot, a, mid);
+    else if (kind == KIND_WAVE_AGG) run_primed<KIND_WAVE_AGG, U>(make_adder<KIND_WAVE_AGG>(lds, P, c), rg, rot, a, mid);
+    else if (kind == KIND_UNIFORM) run_primed<KIND_UNIFORM, U>(make_adder<KIND_UNIFORM>(lds, P, c), rg, rot, a, mid);
+    else run_primed<KIND_LOOKUP, U>(make_adder<KIND_LOOKUP>(lds, P, c), rg, rot, a, mid);
     ++nt;
-    if (P.dynamic) {
-      __syncthreads();
-      if (t == 0) c.next_tile = next_req;
-      __syncthreads();
-      tile = c.next_tile;
-    } else {
-      ++tile;
+    __syncthreads();
+    if (t == 0) {
+      c.next_tile = req;
+      c.nrec = rn;
     }
+    __syncthreads();
+    const uint32_t nxt = c.next_tile;
+    const bool has_nxt = nxt < tile_end;
+    const TileRec r = c.nrec;
+    if (has_nxt) rg = prime_range<U>(a, r.addr, r.len, rot);   // in flight during the switch
+    const uint32_t ns = has_nxt ? r.seg : kNone;
+    if (ns != cur) {
+      uint32_t w = 0;
+      uint64_t hint = 0;
+      if (has_nxt) {
+        w = seg_word(P, ns);
+        hint = tag_prefetch(P, ns);
+      }
+      const uint32_t before = flush_issue(lds, P, c, cur, kind, lg, nt);
+      flush_resolve(P, c, cur, c.sd, before, nt);
+      if (has_nxt) {
+        cur = ns;
+        nt = 0;
+        seg_commit(c, w);
+        kind = begin_segment(lds, P, c, c.sd, hint);
+        lg = c.lg;
+      }
+    }
+    tile = nxt;
   }
   if (P.dynamic) {
     __syncthreads();
@@ -819,6 +925,18 @@ __global__ void __launch_bounds__(kBlock) hist_main(const Params P) {
       }
     }
   }
+}
+
+template <int U>
+__global__ void __launch_bounds__(kBlock) hist_main(const Params P) {
+  // one dynamic LDS block: the counting table at address 0 (so table addresses need no
+  // base offset), the lookup table after it, the control block at the end
+  extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+  Ctl &c = *reinterpret_cast<Ctl *>(lds + P.table_words + P.look_words);
+  zero_words(lds, P.table_words);   // from here on table_bin leaves the table zero
+  __syncthreads();
+  if (P.single) single_path<U>(lds, P, c);
+  else multi_path<U>(lds, P, c);
 }
 
 // Rule P as a stand-alone call: one workgroup reads a uint64[256] histogram and writes a

@@ -123,15 +123,18 @@ hist_status_t run_single(DevCtx *d, Params &P, hipStream_t s);
 
 // Segments + tile map + per-workgroup bounds in one host buffer.
 struct MultiPlan {
-  std::vector<uint8_t> blob;   // SegDesc[n] | uint32 tile_seg[ntiles] | uint32 bounds[grid + 1]
+  std::vector<uint8_t> blob;   // SegDesc[n] | TileRec[ntiles] | uint32 bounds[grid + 1]
   uint32_t nseg = 0;
   uint32_t ntiles = 0;
   uint32_t grid = 0;
   size_t seg_bytes = 0;
-  uint64_t tile = 0;
+  size_t rec_bytes = 0;
 };
-// segs: ptr/size/out/acc/chunk/stream_idx filled; tile0/ntiles are filled here.
-hist_status_t plan_multi(std::vector<SegDesc> &segs, uint64_t tile, uint32_t max_grid, bool balanced, MultiPlan *mp);
+// segs: ptr/size/out/acc/chunk/stream_idx filled; tile0/ntiles are filled here.  Tiles are
+// at most `tile` bytes; `guided` shrinks them towards the end of the launch (for dynamic
+// launches); `balanced` writes contiguous per-workgroup tile ranges (for static launches).
+hist_status_t plan_multi(std::vector<SegDesc> &segs, uint64_t tile, uint32_t max_grid, bool balanced, bool guided,
+                         MultiPlan *mp);
 // own: a dedicated scratch (already sized, descriptors already on the device) or nullptr.
 hist_status_t run_multi(DevCtx *d, Params &P, const MultiPlan &mp, uint32_t copies, hipStream_t s, Scratch *own,
                         bool dynamic, bool upload);
