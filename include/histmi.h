@@ -161,6 +161,12 @@ typedef struct {
  * Chunk k runs with D_{k-1-lag}; chunks with k-1-lag < 0 run WAVEHIST with the identity
  * pattern.  A forced mode in push replaces the decided kernel but not the pattern.  All
  * state lives on the device; no host round trip happens between chunks.
+ *
+ * Pushes of one stream must be issued from one host thread at a time, in chunk order, but
+ * may go to different HIP streams: a chunk waits on the device for the decision it runs
+ * with, so consecutive launches may overlap (the tail of one filling the device while the
+ * next starts) and the results do not depend on timing.  At most two launches of one stream
+ * are in flight: a push makes its HIP stream wait for the launch two before it.
  */
 hist_status_t hist_stream_create(hist_stream_t **st, const hist_stream_config_t *cfg);
 
@@ -182,7 +188,8 @@ typedef struct {
     hist_pattern_t next_pattern;  /* rule P of the current moving window */
 } hist_stream_snapshot_t;
 
-/* Synchronous: waits for `stream`, then copies the state.  h_mode_trace (uint8[trace_len])
+/* Synchronous: waits for `stream` and for this stream's launches on any HIP stream, then
+ * copies the state.  h_mode_trace (uint8[trace_len])
  * and h_pattern_trace (uint32[trace_len][256]) may be NULL; entry k holds the mode / pattern
  * words chunk k ran with (k < trace_cap). */
 hist_status_t hist_stream_read(hist_stream_t *st, hist_stream_snapshot_t *snap, uint8_t *h_mode_trace,
@@ -297,10 +304,15 @@ hist_status_t hist_diag_read(hist_diag_t *d);
 /* Launch shape of one kernel family.  Zero fields keep the built-in default. */
 typedef struct {
     uint32_t blocks_per_cu;   /* persistent workgroups per compute unit */
-    uint32_t tile_kib;        /* batch/stream tile size in KiB (multiple of 16) */
+    uint32_t tile_kib;        /* largest tile of a multi-buffer launch in KiB (multiple of 16) */
     uint32_t merge_copies;    /* partial-histogram copies a segment spreads its merge over (power of 2) */
+    uint32_t tiles_per_wg;    /* multi-buffer launches: tiles are made small enough that every
+                                 workgroup gets about this many (1..64) */
 } hist_tune_t;
-/* family: 0 = per-wavefront, 1 = lane-cyclic uniform sub-bins, 2 = pattern lookup. */
+/* family: 0 = per-wavefront, 1 = lane-cyclic uniform sub-bins, 2 = pattern lookup,
+ * 3 = wavefront aggregation (these four for hist_u8 / hist_batch / the server, by kernel),
+ * 4 = ordered stream pushes (hist_stream_push / hist_stream_push_many). */
+#define HIST_TUNE_STREAM 4u
 hist_status_t hist_tune_set(uint32_t family, const hist_tune_t *t);
 hist_status_t hist_tune_get(uint32_t family, hist_tune_t *t);
 

@@ -72,7 +72,8 @@ class Diag(ctypes.Structure):
 
 
 class Tune(ctypes.Structure):
-    _fields_ = [("blocks_per_cu", ctypes.c_uint32), ("tile_kib", ctypes.c_uint32), ("merge_copies", ctypes.c_uint32)]
+    _fields_ = [("blocks_per_cu", ctypes.c_uint32), ("tile_kib", ctypes.c_uint32), ("merge_copies", ctypes.c_uint32),
+                ("tiles_per_wg", ctypes.c_uint32)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -135,7 +136,8 @@ def declared_symbols():
 
 
 TUNING_PATH = os.path.join(HERE, "tuning.json")
-_FAMILIES = {"wavehist": 0, "uniform": 1, "lookup": 2, "waveagg": 3}
+_FAMILIES = {"wavehist": 0, "uniform": 1, "lookup": 2, "waveagg": 3, "stream": 4}
+TUNE_STREAM = 4
 
 
 def apply_tuning(path: str = TUNING_PATH):
@@ -148,7 +150,7 @@ def apply_tuning(path: str = TUNING_PATH):
     for name, fam in t.get("families", {}).items():
         if name in _FAMILIES:
             tune_set(_FAMILIES[name], int(fam.get("blocks_per_cu", 0)), int(fam.get("tile_kib", 0)),
-                     int(fam.get("merge_copies", 0)))
+                     int(fam.get("merge_copies", 0)), int(fam.get("tiles_per_wg", 0)))
 
 
 def load(path: Optional[str] = None, apply_tuning: bool = True):
@@ -345,8 +347,8 @@ def tune_get(family: int) -> Tune:
     return t
 
 
-def tune_set(family: int, blocks_per_cu: int = 0, tile_kib: int = 0, merge_copies: int = 0):
-    t = Tune(blocks_per_cu, tile_kib, merge_copies)
+def tune_set(family: int, blocks_per_cu: int = 0, tile_kib: int = 0, merge_copies: int = 0, tiles_per_wg: int = 0):
+    t = Tune(blocks_per_cu, tile_kib, merge_copies, tiles_per_wg)
     _check(load().hist_tune_set(int(family), ctypes.byref(t)), "hist_tune_set")
 
 

@@ -29,22 +29,30 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 MIB = 1 << 20
-FAMILY = {"wavehist": 0, "uniform": 1, "lookup": 2, "waveagg": 3}
+FAMILY = {"wavehist": 0, "uniform": 1, "lookup": 2, "waveagg": 3, "stream": 4}
 
 
 def log(*a):
     print(*a, flush=True)
 
 
-def timed(torch, fn, reps):
+def timed(torch, fn, reps, streams=()):
+    """Mean ms per call of fn; `streams` are further HIP streams fn launches on (forked from
+    and joined back into the current stream around the timed calls)."""
     s = torch.cuda.current_stream()
     fn()
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(s)
+    for h in streams:
+        h.wait_event(e0)
     for _ in range(reps):
         fn()
+    for h in streams:
+        ev = torch.cuda.Event()
+        ev.record(h)
+        s.wait_event(ev)
     e1.record(s)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
@@ -130,7 +138,8 @@ def main():
     a0 = torch.from_numpy(np.concatenate(chunks)).to(dev)
     arenas = [a0, a0.clone()]
     sbufs = [[(int(a.data_ptr()) + k * 4 * MIB, 4 * MIB) for k in range(len(chunks))] for a in arenas]
-    souts = torch.zeros((len(chunks), 256), dtype=torch.int32, device=dev)
+    souts = [torch.zeros((len(chunks), 256), dtype=torch.int32, device=dev) for _ in range(2)]
+    hip_streams = [torch.cuda.Stream(), torch.cuda.Stream()]
     nb = a0.numel()
     rows, cfgs = {}, {}
     for S, rmax, theta in ((8192, 32, 0), (16384, 64, 0), (960, 8, 45), (960, 8, 0)):
@@ -139,9 +148,11 @@ def main():
             i = [0]
 
             def f():
-                st.push_many(sbufs[i[0] & 1], d_out=souts)
+                # consecutive pushes on two HIP streams, as the bench runs them
+                k = i[0] & 1
+                st.push_many(sbufs[k], d_out=souts[k], stream=hip_streams[k])
                 i[0] += 1
-            ms = timed(torch, f, 6)
+            ms = timed(torch, f, 6, hip_streams)
             st.close()
             key = "S%d_r%d_t%d_lag%d" % (S, rmax, theta, lag)
             rows[key] = round(nb / ms / 1e6, 1)
@@ -152,6 +163,31 @@ def main():
     result["sweeps"]["stream"] = rows
     result["stream"] = cfgs[best]
     log("stream ->", cfgs[best])
+    # launch shape of stream pushes at that configuration: workgroups per CU x tiles per
+    # workgroup (each measured twice, in two interleaved passes, to damp run-to-run noise)
+    c = cfgs[best]
+    shape = {}
+    for rep in range(2):
+        for bpc in (2, 3, 4):
+            for tpw in (2, 3, 4, 6):
+                hm.tune_set(FAMILY["stream"], blocks_per_cu=bpc, tiles_per_wg=tpw)
+                st = hm.Stream(W=1, theta_pct=c["theta_pct"], S=c["S"], rmax=c["rmax"], lag=c["lag"], trace_cap=0)
+                i = [0]
+
+                def f():
+                    k = i[0] & 1
+                    st.push_many(sbufs[k], d_out=souts[k], stream=hip_streams[k])
+                    i[0] += 1
+                ms = timed(torch, f, 10, hip_streams)
+                st.close()
+                shape.setdefault("bpc%d_tpw%d" % (bpc, tpw), []).append(nb / ms / 1e6)
+    rows = {k: round(float(np.mean(v)), 1) for k, v in shape.items()}
+    bk = max(rows, key=lambda k: rows[k])
+    bpc, tpw = int(bk[3]), int(bk.split("tpw")[1])
+    hm.tune_set(FAMILY["stream"], blocks_per_cu=bpc, tiles_per_wg=tpw)
+    result["families"]["stream"] = {"blocks_per_cu": bpc, "tiles_per_wg": tpw}
+    result["sweeps"]["stream_shape"] = rows
+    log("stream shape", rows, "->", bk)
     del arenas, a0
 
     # ---- Figure 5: degenerate + uniform mixture, d = 0..100 %

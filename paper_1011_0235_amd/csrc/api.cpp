@@ -19,7 +19,7 @@ namespace rt {
 
 // Defaults from the gfx950 probes: the lane-cyclic table streams best with 2 workgroups of
 // 4 wavefronts per CU and 4 loads in flight per lane.
-Tune g_tune[kFamilies] = {{4, 256, 4}, {2, 256, 4}, {2, 256, 4}, {4, 256, 4}};
+Tune g_tune[kFamilies] = {{4, 256, 4, 6}, {2, 256, 4, 6}, {2, 256, 4, 6}, {4, 256, 4, 6}, {3, 1024, 4, 4}};
 uint32_t g_single_copies = 16;   // partial copies for a launch with one large segment
 
 static std::mutex g_mu;
@@ -450,7 +450,24 @@ struct hist_stream {
   uint32_t nslot = 0;
   uint64_t pushed = 0;
   StreamAlloc sa;
+  // Launches of one stream may run on different HIP streams and overlap; the device makes
+  // each chunk wait for its decision.  At most two launches are in flight: before a launch,
+  // the HIP stream waits for the launch two before it (events recorded after each launch).
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  bool ev_used[2] = {false, false};
+  uint32_t evi = 0;
 };
+
+static hist_status_t stream_launch_begin(hist_stream *st, hipStream_t s) {
+  if (st->ev_used[st->evi]) TRY_HIP(hipStreamWaitEvent(s, st->ev[st->evi], 0));
+  return HIST_OK;
+}
+static hist_status_t stream_launch_end(hist_stream *st, hipStream_t s) {
+  TRY_HIP(hipEventRecord(st->ev[st->evi], s));
+  st->ev_used[st->evi] = true;
+  st->evi ^= 1u;
+  return HIST_OK;
+}
 
 struct hist_batch_graph {
   hipGraph_t graph = nullptr;
@@ -591,7 +608,7 @@ static hist_status_t batch_prepare(const void *const *h_ptrs, const uint64_t *h_
   // tiles: at most the tuned size, and small enough that every workgroup gets several
   uint64_t total = 0;
   for (uint32_t j = 0; j < n; ++j) total += h_sizes[j];
-  const uint64_t want = ceil_div(ceil_div(total, (uint64_t)maxg * 6), 16384) * 16384;
+  const uint64_t want = ceil_div(ceil_div(total, (uint64_t)maxg * g_tune[fam].tpw), 16384) * 16384;
   const uint64_t tile = std::max<uint64_t>(16384, std::min<uint64_t>((uint64_t)g_tune[fam].tile_kib * 1024, want));
   std::vector<SegDesc> segs(n);
   for (uint32_t j = 0; j < n; ++j) {
@@ -683,11 +700,17 @@ hist_status_t hist_stream_create(hist_stream_t **out, const hist_stream_config_t
   TRY(get_dev(&d));
   hist_stream *st = new hist_stream();
   st->cfg = c;
-  // one launch never reuses a decision slot: a launch spans at most kMaxChunksPerLaunch chunks
-  // plus the lag + 1 decisions made before it
-  st->nslot = c.lag + 2 + kMaxChunksPerLaunch;
-  const hist_status_t r = stream_state_alloc(1, c.W, c.theta_pct, c.S, c.rmax, c.lag, st->nslot, c.trace_cap, &st->sa);
+  // no decision slot is reused while a chunk may still read it: the two launches that can be
+  // in flight span at most 2 * kMaxChunksPerLaunch chunks, plus the lag + 1 decisions made
+  // before them
+  st->nslot = c.lag + 2 + 2 * kMaxChunksPerLaunch;
+  hist_status_t r = stream_state_alloc(1, c.W, c.theta_pct, c.S, c.rmax, c.lag, st->nslot, c.trace_cap, &st->sa);
+  for (int i = 0; i < 2 && r == HIST_OK; ++i)
+    if (hipEventCreateWithFlags(&st->ev[i], hipEventDisableTiming) != hipSuccess) r = HIST_EDEVICE;
   if (r != HIST_OK) {
+    for (int i = 0; i < 2; ++i)
+      if (st->ev[i]) (void)hipEventDestroy(st->ev[i]);
+    stream_state_free(&st->sa);
     delete st;
     return r;
   }
@@ -712,23 +735,14 @@ static void stream_params(const hist_stream *st, Params *P) {
 
 hist_status_t hist_stream_push(hist_stream_t *st, const void *d_chunk, size_t n, hist_mode_t mode, uint32_t *d_out_k,
                                void *stream) {
+  // one chunk is a one-segment launch of the tiled kernel: every launch of an ordered
+  // stream hands its tiles out dynamically, so it completes with however many of its
+  // workgroups are resident -- which overlapping launches on other HIP streams rely on
   if (!st || (n && !d_chunk) || !mode_ok(mode)) return HIST_EINVAL;
   if ((uint64_t)n > kMaxSegBytes) return HIST_EOVERFLOW;
-  DevCtx *d;
-  TRY(get_dev(&d));
-  Params P;
-  init_params(&P);
-  stream_layout(st->cfg.S, st->cfg.rmax, mode, &P);
-  stream_params(st, &P);
-  P.seg0.ptr = static_cast<const uint8_t *>(d_chunk);
-  P.seg0.size = n;
-  P.seg0.out = d_out_k;
-  P.chunk_base = st->pushed;
-  P.seg0.chunk = 0;
-  P.seg0.stream_idx = 0;
-  TRY(run_single(d, P, static_cast<hipStream_t>(stream)));
-  st->pushed += 1;
-  return HIST_OK;
+  const void *p = d_chunk;
+  const uint64_t size = n;
+  return hist_stream_push_many(st, &p, &size, 1, mode, d_out_k, stream);
 }
 
 hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs, const uint64_t *h_sizes,
@@ -750,7 +764,7 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
     stream_layout(st->cfg.S, st->cfg.rmax, mode, &P);
     stream_params(st, &P);
     P.chunk_base = st->pushed;
-    const uint32_t fam = KIND_UNIFORM;
+    const uint32_t fam = kFamStream;
     const uint32_t maxg = (uint32_t)d->cus * blocks_per_cu(fam, lds_bytes(P));
     // tiles small enough that the lag + 1 chunks which may run at once still fill the grid
     uint64_t total = 0;
@@ -759,7 +773,7 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
     const uint64_t inflight = (uint64_t)std::min<uint32_t>(st->cfg.lag + 1, m);
     uint64_t tile = (uint64_t)g_tune[fam].tile_kib * 1024;
     const uint64_t fill = ceil_div(per_chunk * inflight, maxg);     // lag + 1 chunks cover the grid
-    const uint64_t several = ceil_div(total, (uint64_t)maxg * 4);  // every workgroup gets several tiles
+    const uint64_t several = ceil_div(total, (uint64_t)maxg * g_tune[fam].tpw);   // tiles per workgroup
     tile = std::min<uint64_t>(tile, std::max<uint64_t>(16384, ceil_div(std::min(fill, several), 16384) * 16384));
     std::vector<SegDesc> segs(m);
     for (uint32_t j = 0; j < m; ++j) {
@@ -775,7 +789,9 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
     const uint32_t copies = std::min<uint32_t>(64, pow2ceil32(std::max<uint32_t>(1, g_tune[fam].copies)));
     // tiles are handed out in chunk order, so a chunk waiting for an earlier chunk's decision
     // never waits on a workgroup that has not started
+    TRY(stream_launch_begin(st, s));
     TRY(run_multi(d, P, mp, copies, s, nullptr, true, true));
+    TRY(stream_launch_end(st, s));
     st->pushed += m;
   }
   return HIST_OK;
@@ -785,6 +801,8 @@ hist_status_t hist_stream_read(hist_stream_t *st, hist_stream_snapshot_t *snap, 
                                uint32_t *h_pattern_trace, uint32_t trace_len, void *stream) {
   if (!st) return HIST_EINVAL;
   TRY_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+  for (int i = 0; i < 2; ++i)   // launches of this stream on other HIP streams
+    if (st->ev_used[i]) TRY_HIP(hipEventSynchronize(st->ev[i]));
   if (snap) {
     StreamDev h;
     TRY_HIP(hipMemcpy(&h, st->sa.d_st, sizeof(h), hipMemcpyDeviceToHost));
@@ -817,6 +835,8 @@ hist_status_t hist_stream_destroy(hist_stream_t *st) {
   if (!st) return HIST_EINVAL;
   (void)hipDeviceSynchronize();
   stream_state_free(&st->sa);
+  for (int i = 0; i < 2; ++i)
+    if (st->ev[i]) (void)hipEventDestroy(st->ev[i]);
   delete st;
   return HIST_OK;
 }
@@ -840,10 +860,12 @@ hist_status_t hist_tune_set(uint32_t family, const hist_tune_t *t) {
   if (t->tile_kib && (t->tile_kib % 16 || t->tile_kib > (1u << 20))) return HIST_EINVAL;
   if (t->merge_copies && (!is_pow2(t->merge_copies) || t->merge_copies > 64)) return HIST_EINVAL;
   if (t->blocks_per_cu > 8) return HIST_EINVAL;
+  if (t->tiles_per_wg > 64) return HIST_EINVAL;
   std::lock_guard<std::mutex> lk(g_mu);
   if (t->blocks_per_cu) g_tune[family].bpc = t->blocks_per_cu;
   if (t->tile_kib) g_tune[family].tile_kib = t->tile_kib;
   if (t->merge_copies) g_tune[family].copies = t->merge_copies;
+  if (t->tiles_per_wg) g_tune[family].tpw = t->tiles_per_wg;
   return HIST_OK;
 }
 
@@ -853,6 +875,7 @@ hist_status_t hist_tune_get(uint32_t family, hist_tune_t *t) {
   t->blocks_per_cu = g_tune[family].bpc;
   t->tile_kib = g_tune[family].tile_kib;
   t->merge_copies = g_tune[family].copies;
+  t->tiles_per_wg = g_tune[family].tpw;
   return HIST_OK;
 }
 

@@ -24,7 +24,8 @@ namespace rt {
 
 constexpr uint32_t kStaticLdsReserve = 8192;       // static LDS of the kernel (control block), with margin
 constexpr uint64_t kMaxSegBytes = 0xFFFFFFFFull;   // per-segment counts must fit the 32-bit partials
-constexpr uint32_t kFamilies = 4;                  // one tuning entry per Kind
+constexpr uint32_t kFamilies = 5;                  // one tuning entry per Kind, then ordered streams
+constexpr uint32_t kFamStream = HIST_TUNE_STREAM;
 constexpr uint32_t kMaxChunksPerLaunch = 1024;     // stream chunks in one persistent launch, at most
 
 #define TRY_HIP(x)                               \
@@ -57,8 +58,9 @@ inline bool mode_ok(hist_mode_t m) {
 
 struct Tune {
   uint32_t bpc;        // workgroups per CU
-  uint32_t tile_kib;   // multi-segment tile size
+  uint32_t tile_kib;   // largest multi-segment tile
   uint32_t copies;     // partial copies per segment (multi-segment launches)
+  uint32_t tpw;        // multi-segment launches: about this many tiles per workgroup
 };
 extern Tune g_tune[kFamilies];
 extern uint32_t g_single_copies;

@@ -117,14 +117,17 @@ def test_stream_and_server_config_errors(hm):
 
 
 def test_tuning_table(hm):
-    old = hm.tune_get(1)
-    hm.tune_set(1, blocks_per_cu=3, tile_kib=128, merge_copies=8)
-    t = hm.tune_get(1)
-    assert (t.blocks_per_cu, t.tile_kib, t.merge_copies) == (3, 128, 8)
+    for fam in (1, hm.TUNE_STREAM):
+        old = hm.tune_get(fam)
+        hm.tune_set(fam, blocks_per_cu=3, tile_kib=128, merge_copies=8, tiles_per_wg=5)
+        t = hm.tune_get(fam)
+        assert (t.blocks_per_cu, t.tile_kib, t.merge_copies, t.tiles_per_wg) == (3, 128, 8, 5)
+        hm.tune_set(fam, old.blocks_per_cu, old.tile_kib, old.merge_copies, old.tiles_per_wg)
     with pytest.raises(hm.HistError):
         hm.tune_set(1, tile_kib=17)
     with pytest.raises(hm.HistError):
         hm.tune_set(1, merge_copies=3)
     with pytest.raises(hm.HistError):
+        hm.tune_set(1, tiles_per_wg=65)
+    with pytest.raises(hm.HistError):
         hm.tune_set(5, blocks_per_cu=1)
-    hm.tune_set(1, old.blocks_per_cu, old.tile_kib, old.merge_copies)

@@ -185,3 +185,66 @@ def test_push_many_single_chunk(hm):
     assert [list(map(int, p)) for p in pats] == ref["patterns"]
     assert [int(x) for x in snap.acc] == ref["acc"]
     st.close()
+
+
+@pytest.mark.parametrize("W,lag,S,rmax,theta", [(1, 0, 960, 8, 45), (1, 3, 960, 8, 45), (3, 2, 8192, 32, 45),
+                                                (1, 5, 8192, 32, 0), (2, 1, 300, 64, 30)])
+def test_pushes_on_alternating_hip_streams(hm, W, lag, S, rmax, theta):
+    # consecutive launches of one stream on two HIP streams may overlap on the device; every
+    # chunk waits for its own decision, so the results equal the sequential ones exactly
+    chunks = mixed_chunks(300 + lag, 48, 200_000)
+    ref = O.stream_reference(chunks, W=W, theta_pct=theta, S=S, rmax=rmax, lag=lag)
+    st = hm.Stream(W=W, theta_pct=theta, S=S, rmax=rmax, lag=lag, trace_cap=len(chunks))
+    ds = [dev(c) if c.size else None for c in chunks]
+    outs = torch.full((len(chunks), 256), -1, dtype=torch.int32, device="cuda")
+    bufs = [(int(x.data_ptr()) if x is not None else 0, c.size) for x, c in zip(ds, chunks)]
+    torch.cuda.synchronize()
+    hs = [torch.cuda.Stream(), torch.cuda.Stream()]
+    k, call = 0, 0
+    for n in (5, 1, 7, 3, 1, 9, 2, 6, 4, 10):
+        if call % 3 == 1:
+            for j in range(k, k + n):
+                st.push(bufs[j][0], d_out=outs[j], n=bufs[j][1], stream=hs[call & 1])
+        else:
+            st.push_many(bufs[k:k + n], d_out=outs[k:k + n], stream=hs[call & 1])
+        k += n
+        call += 1
+    assert k == len(chunks)
+    snap, modes, pats = st.read(len(chunks), stream=hs[0])
+    torch.cuda.synchronize()
+    assert np.array_equal(outs.cpu().numpy().astype(np.int64) & 0xFFFFFFFF, ref["hists"].astype(np.int64))
+    assert [int(x) for x in snap.acc] == ref["acc"]
+    assert [int(x) for x in snap.mw] == ref["mw"]
+    assert int(snap.chunks) == len(chunks)
+    assert [int(m) for m in modes] == ref["modes"]
+    assert [list(map(int, p)) for p in pats] == ref["patterns"]
+    d = hm.diag()
+    assert d.invalid_patterns == 0 and d.wait_timeouts == 0 and d.merge_timeouts == 0
+    st.close()
+
+
+def test_full_size_pushes_overlapping(hm):
+    # the full 66 x 4 MiB stream pushed three times over two HIP streams at the bench's lag
+    chunks = config2_like(4 << 20)
+    hists = [O.hist(c) for c in chunks] * 3
+    lag, S, rmax, theta = 31, 8192, 32, 0
+    ref = O.stream_reference(None, W=1, theta_pct=theta, S=S, rmax=rmax, lag=lag, hists=hists)
+    d = dev(np.concatenate(chunks))
+    base = int(d.data_ptr())
+    bufs = [(base + k * (4 << 20), 4 << 20) for k in range(len(chunks))]
+    outs = [torch.full((len(chunks), 256), -1, dtype=torch.int32, device="cuda") for _ in range(3)]
+    st = hm.Stream(W=1, theta_pct=theta, S=S, rmax=rmax, lag=lag, trace_cap=len(hists))
+    torch.cuda.synchronize()
+    hs = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for r in range(3):
+        st.push_many(bufs, d_out=outs[r], stream=hs[r & 1])
+    snap, modes, pats = st.read(len(hists), stream=hs[0])
+    torch.cuda.synchronize()
+    got = np.concatenate([o.cpu().numpy().astype(np.int64) & 0xFFFFFFFF for o in outs])
+    assert np.array_equal(got, ref["hists"].astype(np.int64))
+    assert [int(x) for x in snap.acc] == ref["acc"]
+    assert [int(m) for m in modes] == ref["modes"]
+    assert [list(map(int, p)) for p in pats] == ref["patterns"]
+    dg = hm.diag()
+    assert dg.invalid_patterns == 0 and dg.wait_timeouts == 0 and dg.merge_timeouts == 0
+    st.close()
