@@ -10,8 +10,8 @@ go to two HIP streams in turn: the next launch fills the device while the previo
 (the paper pipelines its stream over several CUDA streams the same way).
 
 Prints ONE JSON line.  Extra fields: a roofline of the dominant kernel (algorithmic bytes
-per launch over the launch's share of the device: the interval between its completion and
-the previous launch's, from HIP events recorded on the launching HIP streams), the CPU
+per launch over the launch's share of the device: the mean interval between successive
+launch completions, from HIP events recorded on the launching HIP streams), the CPU
 oracle timed on the host's cores, the same stream at pipeline lag 0 and with the paper's
 960-entry sub-histogram, a 1 MiB single image, and the 8192 x 8192 input matrix of the
 paper's Table 2.
@@ -274,10 +274,13 @@ def main():
         t_end.record(stream)
         torch.cuda.synchronize()
         total_ms = t_start.elapsed_time(t_end)
-        # a launch's share of the device: the interval between its completion and the one
-        # before it (launches overlap, so start-to-end spans would count the overlap twice)
-        launch_ms = [(ends[i - 1].elapsed_time(ends[i]) if i else t_start.elapsed_time(ends[0]))
-                     for i in range(len(ends))]
+        # a launch's share of the device in steady state: the interval between its completion
+        # and the previous launch's (launches overlap, so start-to-end spans would count the
+        # overlap twice; the first timed launch, which starts alone, is left out)
+        if len(ends) > 1:
+            launch_ms = [ends[i - 1].elapsed_time(ends[i]) for i in range(1, len(ends))]
+        else:
+            launch_ms = [t_start.elapsed_time(e) for e in ends]
         return total_ms, launch_ms
 
     # ---- headline
