@@ -53,8 +53,10 @@ struct Ctl {
   uint32_t used_mode;
   uint32_t tmp;
   uint64_t tag;            // decision tag of the current segment's stream chunk
-  SegDesc sd;              // the current segment (multi-segment launches)
-  TileRec nrec;            // the next tile's record (multi-segment launches)
+  // multi-segment launches, double-buffered so that one barrier per step suffices:
+  SegDesc sd[2];           // the current segment's descriptor (and the next one's, being staged)
+  TileRec nrec[2];         // the next tile's record, by tile parity
+  uint32_t ntile[2];       // the next tile's index, by tile parity
   uint32_t red32[kWaves];
   uint64_t red64[kWaves];
   uint32_t cls_cnt[kWaves][8];
@@ -704,22 +706,22 @@ __device__ __forceinline__ void stream_epilogue(const Params &P, Ctl &c, uint32_
   }
 }
 
-// Merge of a segment, in two halves so the ticket's round trip overlaps other work.
+// Merge of a segment.
 //
 // flush_issue: sum the LDS table down to this thread's bin and add it, with no-return
 // agent-scope atomics, into one of the segment's partial copies; thread 0 then takes a
-// ticket (tiles done so far) without waiting for its value.
+// ticket (tiles done so far).  The caller reads the ticket when it next needs thread 0's
+// results anyway; the workgroup that completed the segment's last tile runs
+// finalize_segment.
 //
-// flush_resolve (later, after the next segment's descriptor loads): thread 0 reads the
-// ticket; the workgroup that completed the segment's last tile finalizes it.  The
-// finalizer does not rely on the other workgroups' atomics having landed before their
+// finalize_segment does not rely on the other workgroups' atomics having landed before their
 // tickets: it re-reads the copies until the 256 totals add up to the segment's byte count.
 // Counts only grow and the exact total is known, so a matching sum means every
 // contribution is in -- no per-flush acknowledgement wait is needed.
 __device__ __forceinline__ uint32_t flush_issue(uint32_t *lds, const Params &P, Ctl &c, uint32_t s, uint32_t kind,
-                                                uint32_t lg, uint32_t nt) {
+                                                uint32_t lg, uint32_t nt, bool synced) {
   const uint32_t t = threadIdx.x;
-  __syncthreads();
+  if (!synced) __syncthreads();   // the caller's barrier already ended every add otherwise
   const uint32_t h = table_bin(lds, c, kind, lg);
   const uint32_t copies = 1u << P.clog2;
   uint32_t *part = P.partial + ((size_t)s << (P.clog2 + 8));
@@ -733,12 +735,9 @@ __device__ __forceinline__ uint32_t flush_issue(uint32_t *lds, const Params &P, 
   return before;
 }
 
-__device__ __forceinline__ void flush_resolve(const Params &P, Ctl &c, uint32_t s, const SegDesc &sd, uint32_t before,
-                                              uint32_t nt) {
+__device__ __forceinline__ void finalize_segment(const Params &P, Ctl &c, uint32_t s, const SegDesc &sd) {
   const uint32_t t = threadIdx.x;
-  if (t == 0) c.flag = (before + nt == sd.ntiles) ? 1u : 0u;
-  __syncthreads();
-  if (c.flag) {
+  {
 #ifdef HISTMI_STRICT_FENCES
     __threadfence();
 #endif
@@ -773,7 +772,6 @@ __device__ __forceinline__ void flush_resolve(const Params &P, Ctl &c, uint32_t 
     else if (sd.chunk == kServerChunk) server_epilogue(P, c, sd.stream_idx, tot);
     if (t == 0) st_agent(&P.seg_done[s], 0u);
   }
-  __syncthreads();
 }
 
 template <int KIND>
@@ -811,6 +809,7 @@ __device__ __forceinline__ uint64_t tag_prefetch(const Params &P, uint32_t s) {
 template <int U>
 __device__ __forceinline__ void single_path(uint32_t *lds, const Params &P, Ctl &c) {
   if (blockIdx.x >= P.ntiles) return;
+  const uint32_t t = threadIdx.x;
   const SegDesc sd = P.seg0;
   const uint32_t kind = begin_segment(lds, P, c, sd, tag_prefetch(P, 0));
   const uint32_t lg = c.lg;
@@ -818,11 +817,13 @@ __device__ __forceinline__ void single_path(uint32_t *lds, const Params &P, Ctl 
   else if (kind == KIND_WAVE_AGG) run_strided<KIND_WAVE_AGG, U>(lds, make_adder<KIND_WAVE_AGG>(lds, P, c), sd.ptr, sd.size);
   else if (kind == KIND_UNIFORM) run_strided<KIND_UNIFORM, U>(lds, make_adder<KIND_UNIFORM>(lds, P, c), sd.ptr, sd.size);
   else run_strided<KIND_LOOKUP, U>(lds, make_adder<KIND_LOOKUP>(lds, P, c), sd.ptr, sd.size);
-  const uint32_t before = flush_issue(lds, P, c, 0, kind, lg, 1);
-  flush_resolve(P, c, 0, sd, before, 1);
+  const uint32_t before = flush_issue(lds, P, c, 0, kind, lg, 1, false);
+  if (t == 0) c.flag = (before + 1 == sd.ntiles) ? 1u : 0u;
+  __syncthreads();
+  if (c.flag) finalize_segment(P, c, 0, sd);
 }
 
-// The segment descriptor is staged through LDS (c.sd) rather than held in registers: lanes
+// The segment descriptor is staged through LDS (c.sd[]) rather than held in registers: lanes
 // 0..kSegWords-1 each load one word of it, so the load can be in flight across the flush of
 // the previous segment without tying up scalar registers.
 constexpr uint32_t kSegWords = sizeof(SegDesc) / 4;
@@ -830,9 +831,8 @@ __device__ __forceinline__ uint32_t seg_word(const Params &P, uint32_t s) {
   const uint32_t t = threadIdx.x;
   return t < kSegWords ? reinterpret_cast<const uint32_t *>(P.segs + s)[t] : 0u;
 }
-__device__ __forceinline__ void seg_commit(Ctl &c, uint32_t w) {
-  if (threadIdx.x < kSegWords) reinterpret_cast<uint32_t *>(&c.sd)[threadIdx.x] = w;
-  __syncthreads();
+__device__ __forceinline__ void seg_stage(Ctl &c, uint32_t slot, uint32_t w) {
+  if (threadIdx.x < kSegWords) reinterpret_cast<uint32_t *>(&c.sd[slot])[threadIdx.x] = w;
 }
 
 // Many segments cut into tiles (batches, stream pushes, server batches).  A workgroup takes
@@ -860,14 +860,17 @@ __device__ __forceinline__ void multi_path(uint32_t *lds, const Params &P, Ctl &
   Pipe<U> a;
   Range rg;
   uint32_t cur = kNone, kind = KIND_WAVE, lg = 0, nt = 0;
+  uint32_t sp = 0;    // c.sd[sp] describes the current segment
+  uint32_t par = 0;   // parity of the tile step (c.ntile / c.nrec slot)
   if (tile < tile_end) {
     const TileRec r0 = P.recs[tile];
     const uint32_t w = seg_word(P, r0.seg);
     const uint64_t hint = tag_prefetch(P, r0.seg);
     rg = prime_range<U>(a, r0.addr, r0.len, rot);
     cur = r0.seg;
-    seg_commit(c, w);
-    kind = begin_segment(lds, P, c, c.sd, hint);
+    seg_stage(c, sp, w);
+    __syncthreads();
+    kind = begin_segment(lds, P, c, c.sd[sp], hint);
     lg = c.lg;
   }
   while (tile < tile_end) {
@@ -885,15 +888,17 @@ __device__ __forceinline__ void multi_path(uint32_t *lds, const Params &P, Ctl &
     else if (kind == KIND_UNIFORM) run_primed<KIND_UNIFORM, U>(make_adder<KIND_UNIFORM>(lds, P, c), rg, rot, a, mid);
     else run_primed<KIND_LOOKUP, U>(make_adder<KIND_LOOKUP>(lds, P, c), rg, rot, a, mid);
     ++nt;
-    __syncthreads();
+    // one barrier ends the tile: every add is done and the next tile is published (slot by
+    // parity, so a wave still reading the previous step's slot is never overwritten)
     if (t == 0) {
-      c.next_tile = req;
-      c.nrec = rn;
+      c.ntile[par] = req;
+      c.nrec[par] = rn;
     }
     __syncthreads();
-    const uint32_t nxt = c.next_tile;
+    const uint32_t nxt = c.ntile[par];
+    const TileRec r = c.nrec[par];
+    par ^= 1u;
     const bool has_nxt = nxt < tile_end;
-    const TileRec r = c.nrec;
     if (has_nxt) rg = prime_range<U>(a, r.addr, r.len, rot);   // in flight during the switch
     const uint32_t ns = has_nxt ? r.seg : kNone;
     if (ns != cur) {
@@ -903,13 +908,18 @@ __device__ __forceinline__ void multi_path(uint32_t *lds, const Params &P, Ctl &
         w = seg_word(P, ns);
         hint = tag_prefetch(P, ns);
       }
-      const uint32_t before = flush_issue(lds, P, c, cur, kind, lg, nt);
-      flush_resolve(P, c, cur, c.sd, before, nt);
+      const uint32_t before = flush_issue(lds, P, c, cur, kind, lg, nt, true);
+      // a second barrier publishes the ticket's verdict together with the next descriptor
+      // (staged in the other slot, so a finalizer still reading c.sd[sp] is unaffected)
+      if (t == 0) c.flag = (before + nt == c.sd[sp].ntiles) ? 1u : 0u;
+      if (has_nxt) seg_stage(c, sp ^ 1u, w);
+      __syncthreads();
+      if (c.flag) finalize_segment(P, c, cur, c.sd[sp]);
       if (has_nxt) {
+        sp ^= 1u;
         cur = ns;
         nt = 0;
-        seg_commit(c, w);
-        kind = begin_segment(lds, P, c, c.sd, hint);
+        kind = begin_segment(lds, P, c, c.sd[sp], hint);   // ends with the third barrier
         lg = c.lg;
       }
     }
