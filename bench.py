@@ -30,6 +30,7 @@ import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 MIB = 1 << 20
+N_ARENAS = 4
 
 
 def parse():
@@ -235,12 +236,13 @@ def main():
     S = tune["S"] if args.S is None else args.S
     rmax = tune["rmax"] if args.rmax is None else args.rmax
 
-    # ---- inputs: the config-2 stream, twice, resident in HBM
+    # ---- inputs: the config-2 stream, four copies resident in HBM (1.03 GiB), used in turn so
+    # that no step reads bytes read in the last 792 MiB (the device cache is 256 MB)
     chunks = G.stream_chunks(4 * MIB)
     host = np.concatenate(chunks)
     nbytes = host.size
-    arenas = [torch.from_numpy(host).to(dev), None]
-    arenas[1] = arenas[0].clone()
+    arenas = [torch.from_numpy(host).to(dev)]
+    arenas += [arenas[0].clone() for _ in range(N_ARENAS - 1)]
     nchunk = len(chunks)
     bufs = [[(int(a.data_ptr()) + k * 4 * MIB, 4 * MIB) for k in range(nchunk)] for a in arenas]
     outs = [torch.zeros((nchunk, 256), dtype=torch.int32, device=dev) for _ in range(2)]
@@ -250,9 +252,9 @@ def main():
     # once; each chunk waits on the device for the decision it runs with).
     hip_streams = [torch.cuda.Stream(), torch.cuda.Stream()]
 
-    def run_stream(st, steps, warmup, per_launch_events=True):
+    def run_stream(st, steps, warmup, per_launch_events=True, n_hip=2):
         for i in range(warmup):
-            st.push_many(bufs[i & 1], d_out=outs[i & 1], stream=hip_streams[i & 1])
+            st.push_many(bufs[i % N_ARENAS], d_out=outs[i & 1], stream=hip_streams[(i & 1) % n_hip])
         torch.cuda.synchronize()
         ends = []
         t_start = torch.cuda.Event(enable_timing=True)
@@ -261,11 +263,12 @@ def main():
         for h in hip_streams:
             h.wait_event(t_start)
         for i in range(steps):
-            j = warmup + i
-            st.push_many(bufs[j & 1], d_out=outs[j & 1], stream=hip_streams[i & 1])
+            j = warmup + i   # arenas, outputs and HIP streams rotate as in the warm-up
+            hs = hip_streams[(j & 1) % n_hip]
+            st.push_many(bufs[j % N_ARENAS], d_out=outs[j & 1], stream=hs)
             if per_launch_events:
                 e = torch.cuda.Event(enable_timing=True)
-                e.record(hip_streams[i & 1])   # on the stream the launch went to
+                e.record(hs)   # on the stream the launch went to
                 ends.append(e)
         for h in hip_streams:
             ev = torch.cuda.Event()
@@ -306,10 +309,25 @@ def main():
     avg_launch_ms = float(np.mean(launch_ms)) if launch_ms else ms_per_step
     alg_bytes = nbytes + nchunk * 1024 + nchunk * 4096   # input + u32 outputs + u64 Accumulator read/write
     achieved = alg_bytes / (avg_launch_ms * 1e-3) / 1e9
+    p10, p50, p90 = (float(x) for x in np.percentile(launch_ms, [10, 50, 90])) if launch_ms else (ms_per_step,) * 3
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(),
                 "kernel": "histmi::hist_main<4>", "avg_launch_ms": round(avg_launch_ms, 5),
+                "launch_ms_p10_p50_p90": [round(p10, 5), round(p50, 5), round(p90, 5)],
                 "alg_bytes_per_launch": alg_bytes}
+    # the measured read roofline: a plain streaming read of 2 x 1 GiB (used in turn), best over
+    # grid sizes (streaming reads on this GPU are sensitive to the grid)
+    probe = [torch.randint(0, 256, (1 << 30,), dtype=torch.uint8, device=dev) for _ in range(2)]
+    psum = torch.zeros(1, dtype=torch.int64, device=dev)
+    k = [0]
+    read_sweep = {}
+    for wg in (256, 512, 768, 1024, 2048):
+        def probe_once():
+            hm.read_probe(probe[k[0] & 1], psum, workgroups=wg, stream=stream)
+            k[0] += 1
+        read_sweep[wg] = round((1 << 30) / (timed(torch, stream, probe_once, 10) * 1e-3) / 1e9, 1)
+    read_roof = max(read_sweep.values())
+    del probe
 
     res = {
         "metric": "input GB/s and % of HBM peak (bit-exact); batched/served GB/s + p50/p99 latency",
@@ -330,6 +348,9 @@ def main():
                    "chunk_bytes": 4 * MIB, "chunks": nchunk, "mode": "auto", "W": 1, "theta_pct": theta,
                    "S": S, "rmax": rmax, "lag": lag},
         "pct_of_hbm_peak": round(100.0 * value / HBM_PEAK_GBS, 2),
+        "read_roofline_GBps": round(read_roof, 1),
+        "read_probe_GBps_by_workgroups": read_sweep,
+        "pct_of_read_roofline": round(100.0 * value / read_roof, 2),
         "parity_exact": parity and acc_ok,
         "roofline": roofline,
         "device": {"arch": info.arch.decode(), "cus": info.cu_count, "clock_khz": info.clock_khz},
@@ -353,13 +374,18 @@ def main():
     if not args.no_extras:
         extras = {}
         # the same stream, sequential semantics (pattern for chunk k+1 from chunk k) and paper sizes
-        for name, (l, th, s_, r_) in {"stream_lag0_auto": (0, theta, S, rmax),
-                                      "stream_paper960_theta45_lag0": (0, 45, 960, 8),
-                                      "stream_paper960_theta45_lag%d" % lag: (lag, 45, 960, 8)}.items():
+        # (the switch exercised: theta 45 sends peaked chunks to AHist and wide ones to the
+        # per-wavefront kernel; one HIP stream: no overlap between consecutive launches)
+        for name, (l, th, s_, r_, nh) in {"stream_lag0_auto": (0, theta, S, rmax, 2),
+                                          "stream_theta45_lag0": (0, 45, S, rmax, 2),
+                                          "stream_theta45_lag%d" % lag: (lag, 45, S, rmax, 2),
+                                          "stream_paper960_theta45_lag0": (0, 45, 960, 8, 2),
+                                          "stream_paper960_theta45_lag%d" % lag: (lag, 45, 960, 8, 2),
+                                          "stream_lag%d_one_hip_stream" % lag: (lag, theta, S, rmax, 1)}.items():
             st = hm.Stream(W=1, theta_pct=th, S=s_, rmax=r_, lag=l, trace_cap=0)
-            tms, _ = run_stream(st, 5, 2, per_launch_events=False)
+            tms, _ = run_stream(st, 8, 3, per_launch_events=False, n_hip=nh)
             st.close()
-            extras[name] = {"GB/s": round(nbytes * 5 / (tms * 1e-3) / 1e9, 1), "ms_per_step": round(tms / 5, 4)}
+            extras[name] = {"GB/s": round(nbytes * 8 / (tms * 1e-3) / 1e9, 1), "ms_per_step": round(tms / 8, 4)}
         # one 1 MiB image (config 1): latency of one call, back to back
         x = torch.from_numpy(G.image_1mib()).to(dev)
         o1 = torch.zeros(256, dtype=torch.int32, device=dev)

@@ -301,6 +301,18 @@ typedef struct {
 /* Synchronous read of the current device's counters. */
 hist_status_t hist_diag_read(hist_diag_t *d);
 
+/*
+ * hist_read_probe -- the HBM read roofline the histogram kernels are measured against: a
+ * plain streaming read of n_bytes at d_in (16-byte vector loads, grid-stride, each byte read
+ * once) whose little-endian uint32 words are summed and ADDED to *d_sum (device uint64).
+ *   d_in: device pointer, 16-byte aligned; n_bytes: a multiple of 16 (0 is a no-op).
+ *   workgroups: grid size (256 threads each), 1..65536; 0 = two per compute unit.
+ * Errors (synchronous): HIST_EINVAL for NULL pointers, misaligned/ragged sizes or a grid
+ * out of range.  Asynchronous on `stream`.  Not part of the histogram path: a measurement aid.
+ */
+hist_status_t hist_read_probe(const void *d_in, size_t n_bytes, uint64_t *d_sum, uint32_t workgroups,
+                              void *stream);
+
 /* Launch shape of one kernel family.  Zero fields keep the built-in default. */
 typedef struct {
     uint32_t blocks_per_cu;   /* persistent workgroups per compute unit */

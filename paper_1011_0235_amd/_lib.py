@@ -116,6 +116,7 @@ _SIGS = [
     ("hist_batch_graph_launch", ctypes.c_int, [_VP, _VP]),
     ("hist_batch_graph_destroy", ctypes.c_int, [_VP]),
     ("hist_diag_read", ctypes.c_int, [ctypes.POINTER(Diag)]),
+    ("hist_read_probe", ctypes.c_int, [_VP, ctypes.c_size_t, _VP, ctypes.c_uint32, _VP]),
     ("hist_tune_set", ctypes.c_int, [ctypes.c_uint32, ctypes.POINTER(Tune)]),
     ("hist_tune_get", ctypes.c_int, [ctypes.c_uint32, ctypes.POINTER(Tune)]),
     ("hist_server_create", ctypes.c_int, [ctypes.POINTER(_VP), ctypes.POINTER(ServerConfig)]),
@@ -241,6 +242,13 @@ def hist_u8_u64(d_in, d_acc, mode: int = MODE_AUTO, pattern: Optional[Pattern] =
     st = load().hist_u8_u64(_ptr(d_in), nb, _ptr(d_acc), int(mode),
                             ctypes.byref(pattern) if pattern is not None else None, _stream(stream))
     _check(st, "hist_u8_u64")
+
+
+def read_probe(d_in, d_sum, workgroups: int = 0, stream=None, n: Optional[int] = None):
+    """Streaming read of d_in (HBM read roofline); adds its uint32 words to d_sum[0] (uint64)."""
+    nb = _nbytes(d_in) if n is None else int(n)
+    _check(load().hist_read_probe(_ptr(d_in), nb, _ptr(d_sum), int(workgroups), _stream(stream)),
+           "hist_read_probe")
 
 
 def _ptr_arrays(bufs) -> Tuple[ctypes.Array, np.ndarray]:

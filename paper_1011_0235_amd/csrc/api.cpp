@@ -855,6 +855,20 @@ hist_status_t hist_diag_read(hist_diag_t *out) {
   return HIST_OK;
 }
 
+hist_status_t hist_read_probe(const void *d_in, size_t n_bytes, uint64_t *d_sum, uint32_t workgroups,
+                              void *stream) {
+  if (n_bytes == 0) return HIST_OK;
+  if (!d_in || !d_sum || (n_bytes & 15u) || (reinterpret_cast<uintptr_t>(d_in) & 15u) || workgroups > 65536)
+    return HIST_EINVAL;
+  DevCtx *d;
+  TRY(get_dev(&d));
+  const uint64_t nvec = (uint64_t)n_bytes >> 4;
+  // no more workgroups than the vectors need
+  const uint64_t want = std::max<uint64_t>(1, ceil_div(nvec, (uint64_t)kBlock * 4));
+  const uint32_t grid = (uint32_t)std::min<uint64_t>(workgroups ? workgroups : (uint64_t)d->cus * 2, want);
+  return dev_err(launch_read_probe(d_in, nvec, d_sum, grid, static_cast<hipStream_t>(stream)));
+}
+
 hist_status_t hist_tune_set(uint32_t family, const hist_tune_t *t) {
   if (!t || family >= kFamilies) return HIST_EINVAL;
   if (t->tile_kib && (t->tile_kib % 16 || t->tile_kib > (1u << 20))) return HIST_EINVAL;

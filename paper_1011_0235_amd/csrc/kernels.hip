@@ -964,6 +964,31 @@ __global__ void __launch_bounds__(kBlock) pattern_update_kernel(const uint64_t *
   }
 }
 
+// ------------------------------------------------------------------ read-bandwidth probe
+//
+// The HBM read roofline the counting kernels are measured against: every 16-byte vector of
+// a buffer is loaded once (global_load_dwordx4, four per lane in flight, grid-stride) and its
+// four 32-bit words are summed, so the loads cannot be dropped.  One u64 atomic per wavefront.
+__global__ void __launch_bounds__(kBlock) read_probe_kernel(gu32x4 *v, uint64_t nvec, uint64_t *sum) {
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  uint64_t acc = 0;
+  for (; i + 3 * stride < nvec; i += 4 * stride) {
+    u32x4 x[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) x[u] = __builtin_nontemporal_load(v + i + u * stride);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc += (uint64_t)x[u][0] + x[u][1] + x[u][2] + x[u][3];
+  }
+  for (; i < nvec; i += stride) {
+    const u32x4 x = __builtin_nontemporal_load(v + i);
+    acc += (uint64_t)x[0] + x[1] + x[2] + x[3];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += shfl_xor_u64(acc, o);
+  if (lane_id() == 0 && acc) atomicAdd(reinterpret_cast<unsigned long long *>(sum), (unsigned long long)acc);
+}
+
 // ------------------------------------------------------------------ host-side launchers
 
 uint32_t ctl_bytes() { return (uint32_t)((sizeof(Ctl) + 15) & ~(size_t)15); }
@@ -975,6 +1000,11 @@ hipError_t launch_hist(const Params &P, const LaunchShape &sh, hipStream_t s) {
 
 hipError_t launch_pattern_update(const uint64_t *h, uint32_t S, uint32_t rmax, hist_pattern_t *out, hipStream_t s) {
   hipLaunchKernelGGL(pattern_update_kernel, dim3(1), dim3(kBlock), 0, s, h, S, rmax, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_read_probe(const void *d_in, uint64_t nvec, uint64_t *d_sum, uint32_t grid, hipStream_t s) {
+  hipLaunchKernelGGL(read_probe_kernel, dim3(grid), dim3(kBlock), 0, s, (gu32x4 *)d_in, nvec, d_sum);
   return hipGetLastError();
 }
 

@@ -99,6 +99,11 @@ def test_synchronous_argument_errors(hm):
     assert lib.hist_pattern_update(None, 960, 8, out, None) == hm.EINVAL
     assert lib.hist_pattern_update(out, 255, 8, out, None) == hm.EINVAL
     assert lib.hist_pattern_update(out, 960, 3, out, None) == hm.EINVAL
+    assert lib.hist_read_probe(None, 16, out, 0, None) == hm.EINVAL
+    assert lib.hist_read_probe(ctypes.c_void_p(0x1000), 17, out, 0, None) == hm.EINVAL
+    assert lib.hist_read_probe(ctypes.c_void_p(0x1008), 16, out, 0, None) == hm.EINVAL
+    assert lib.hist_read_probe(ctypes.c_void_p(0x1000), 16, out, 70000, None) == hm.EINVAL
+    assert lib.hist_read_probe(ctypes.c_void_p(0x1000), 0, None, 0, None) == hm.OK
 
 
 def test_stream_and_server_config_errors(hm):

@@ -153,3 +153,19 @@ def test_pattern_update_matches_oracle_rule(hm):
             words = (dp.cpu().numpy().astype(np.int64) & 0xFFFFFFFF).tolist()
             assert words[:256] == O.rule_p(h.tolist(), S, rmax), (S, rmax)
             assert words[256] == S and words[257] == rmax
+
+
+def test_read_probe_sums_every_word(hm):
+    # the read-roofline probe reads each 16-byte vector once: its sum of uint32 words is exact
+    g = np.random.default_rng(15)
+    for n in (16, 4096, (1 << 20) + 16 * 7, 3 << 22):
+        host = g.integers(0, 256, size=n, dtype=np.uint8)
+        d = dev(host)
+        acc = torch.zeros(1, dtype=torch.int64, device="cuda")
+        hm.read_probe(d, acc)
+        hm.read_probe(d, acc, workgroups=3)
+        torch.cuda.synchronize()
+        exp = 2 * int(host.view(np.uint32).astype(np.uint64).sum())
+        assert int(acc.item()) == exp, n
+    with pytest.raises(hm.HistError):
+        hm.read_probe(d, acc, n=15)
