@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (calibrates HBM byte counters)")
+    ap.add_argument("--lds-probe", action="store_true",
+                    help="only run each counting kernel once on the 64 MiB Table 2 inputs (for LDS counters)")
     return ap.parse_args()
 
 
@@ -61,6 +63,34 @@ def copy_probe():
     torch.cuda.synchronize()
     print(json.dumps({"copy_probe_bytes_read_per_dispatch": n, "copy_probe_bytes_written_per_dispatch": n,
                       "dispatches": 3}), flush=True)
+
+
+def lds_probe():
+    """One launch per (input, kernel) on the paper's 8192 x 8192 matrix (Table 2), in a fixed
+    order that the printed JSON lists, for per-dispatch LDS counters (bank and address
+    conflicts, LDS busy and wait cycles)."""
+    import torch
+
+    import paper_1011_0235_amd as hm
+    import synthgen as G
+    from oracle import oracle as O
+    hm.load()
+    kernels = [("uniform_r32", hm.MODE_AUTO, None), ("wavehist", hm.MODE_WAVEHIST, None),
+               ("waveagg", hm.MODE_WAVEAGG, None), ("paper960", hm.MODE_AHIST, hm.pattern_init(hm.PAT_PAPER960))]
+    out = torch.zeros(256, dtype=torch.int32, device="cuda")
+    order, ok = [], True
+    for kind in ("random", "all127", "xray"):
+        host = G.table2_input(kind)
+        d = torch.from_numpy(host).cuda()
+        exp = O.hist(host).astype(np.int64)
+        for name, mode, pat in kernels:
+            hm.hist_u8(d, out, mode=mode, pattern=pat)
+            torch.cuda.synchronize()
+            ok = ok and bool(np.array_equal(out.cpu().numpy().astype(np.int64), exp))
+            order.append("%s/%s" % (kind, name))
+        del d
+    print(json.dumps({"lds_probe_dispatch_order": order, "bytes_per_dispatch": 64 * MIB, "parity_exact": ok}),
+          flush=True)
 
 
 def profiled_traffic():
@@ -215,6 +245,9 @@ def main():
     args = parse()
     if args.copy_probe:
         copy_probe()
+        return
+    if args.lds_probe:
+        lds_probe()
         return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
