@@ -171,6 +171,69 @@ def bench_batched(hm, G, O, torch, dev, stream):
             "speedup_vs_sequential": round(ms_seq / ms_graph, 2), "parity_sampled_exact": ok}
 
 
+def bench_xray(hm, G, O, torch, dev, hip_streams, S, rmax, lag, theta, frames=512):
+    """The X-ray-like frame stream (512 frames of 2048 x 2048, 2 GiB): the mean of each frame's
+    clipped Normal walks (step sigma 4), its sigma is U[6, 40], 1 % of its pixels are saturated.
+    Generated on the device under the root seed; all frames are pushed in one launch, the
+    pattern carried on the device.  The mode and pattern traces of one pass are checked
+    exactly against the oracle's stream reference (per-frame histograms of the bytes read
+    back); then the pass is timed, alternating two HIP streams."""
+    n = 2048 * 2048
+    specs = G.xray_specs(frames)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(G.ROOT_SEED + 3)
+    arena = torch.empty(frames * n, dtype=torch.uint8, device=dev)
+    k_sat = int(round(0.01 * n))
+    for t, sp in enumerate(specs):
+        z = torch.randn(n, device=dev, generator=gen) * sp.sigma + sp.mu
+        fr = arena[t * n:(t + 1) * n]
+        fr.copy_(z.round_().clamp_(0, 255).to(torch.uint8))
+        fr[torch.randperm(n, device=dev, generator=gen)[:k_sat]] = 255
+    torch.cuda.synchronize()
+    host = arena.cpu().numpy()
+    hists = [O.hist(host[t * n:(t + 1) * n]) for t in range(frames)]
+    del host
+    base = int(arena.data_ptr())
+    bufs = [(base + t * n, n) for t in range(frames)]
+    outs = [torch.zeros((frames, 256), dtype=torch.int32, device=dev) for _ in range(2)]
+    exp = np.stack(hists).astype(np.int64)
+    res = {"frames": frames, "bytes": frames * n}
+    for name, (th, lg, mode) in {"auto": (theta, lag, hm.MODE_AUTO), "auto_theta45": (45, lag, hm.MODE_AUTO),
+                                 "auto_theta4": (4, lag, hm.MODE_AUTO), "ahist": (theta, lag, hm.MODE_AHIST),
+                                 "wavehist": (theta, lag, hm.MODE_WAVEHIST), "auto_lag0": (theta, 0, hm.MODE_AUTO)}.items():
+        ref = O.stream_reference(None, W=1, theta_pct=th, S=S, rmax=rmax, lag=lg, hists=hists, mode=mode)
+        st = hm.Stream(W=1, theta_pct=th, S=S, rmax=rmax, lag=lg, trace_cap=frames)
+        st.push_many(bufs, mode=mode, d_out=outs[0], stream=hip_streams[0])
+        _, modes, pats = st.read(frames, stream=hip_streams[0])
+        ok = (bool(np.array_equal(outs[0].cpu().numpy().astype(np.int64), exp))
+              and [int(m) for m in modes] == ref["modes"]
+              and [list(map(int, p)) for p in pats] == ref["patterns"])
+        reps = 4
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        cur = torch.cuda.current_stream()
+        torch.cuda.synchronize()
+        e0.record(cur)
+        for h in hip_streams:
+            h.wait_event(e0)
+        for r in range(reps):
+            st.push_many(bufs, mode=mode, d_out=outs[r & 1], stream=hip_streams[r & 1])
+        for h in hip_streams:
+            ev = torch.cuda.Event()
+            ev.record(h)
+            cur.wait_event(ev)
+        e1.record(cur)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        st.close()
+        n_ahist = sum(1 for m in ref["modes"] if m == hm.MODE_AHIST)
+        switches = sum(1 for a, b in zip(ref["modes"], ref["modes"][1:]) if a != b)
+        res[name] = {"GB/s": round(frames * n / (ms * 1e-3) / 1e9, 1), "ms": round(ms, 3), "theta_pct": th,
+                     "lag": lg, "frames_ahist": n_ahist, "mode_switches": switches, "parity_exact": ok}
+    del arena
+    return res
+
+
 def bench_served(hm, G, O, torch, dev, stream, rates=(1000, 10000, 50000), duration=2.0):
     """Open-loop Poisson arrivals (sizes log-uniform 4 KiB..64 MiB, 64 stream ids) into the
     continuous-batching server; latency from scheduled arrival to host-observed completion."""
@@ -456,6 +519,7 @@ def main():
             t2[kind] = row
             del xs
         extras["table2_64mib_GBps"] = t2
+        extras["xray_config3"] = bench_xray(hm, G, O, torch, dev, hip_streams, S, rmax, lag, theta)
         extras["batched_config4"] = bench_batched(hm, G, O, torch, dev, stream)
         extras["served_config5"] = bench_served(hm, G, O, torch, dev, stream)
         res["extras"] = extras

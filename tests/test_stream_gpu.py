@@ -248,3 +248,32 @@ def test_full_size_pushes_overlapping(hm):
     dg = hm.diag()
     assert dg.invalid_patterns == 0 and dg.wait_timeouts == 0 and dg.merge_timeouts == 0
     st.close()
+
+
+@pytest.mark.parametrize("frame_bytes,count", [(1 << 18, 512), (2048 * 2048, 48)])
+def test_xray_frame_stream(hm, frame_bytes, count):
+    # the X-ray-like frame stream (drifting mean, random width, 1 % saturated pixels): every
+    # frame's histogram and the exact mode / pattern traces at the paper's theta, with the
+    # pattern carried on the device, sequential (lag 0) and pipelined
+    specs = G.xray_specs(count)
+    frames = [G.xray_frame(t, specs[t], frame_bytes) for t in range(count)]
+    hists = [O.hist(f) for f in frames]
+    d = dev(np.concatenate(frames))
+    base = int(d.data_ptr())
+    bufs = [(base + t * frame_bytes, frame_bytes) for t in range(count)]
+    # the mean's walk stays inside 57..183 and the peak bin holds 1-7 % of a frame, so the
+    # paper's theta = 45 never fires on these frames; theta = 4 and 3 make the stream cross
+    for lag, S, rmax, theta in ((0, 960, 8, 45), (31, 8192, 32, 4), (7, 4096, 32, 3)):
+        ref = O.stream_reference(None, W=1, theta_pct=theta, S=S, rmax=rmax, lag=lag, hists=hists)
+        st = hm.Stream(W=1, theta_pct=theta, S=S, rmax=rmax, lag=lag, trace_cap=count)
+        outs = torch.full((count, 256), -1, dtype=torch.int32, device="cuda")
+        st.push_many(bufs, d_out=outs)
+        snap, modes, pats = st.read(count)
+        st.close()
+        assert np.array_equal(outs.cpu().numpy().astype(np.int64), ref["hists"].astype(np.int64)), lag
+        assert [int(m) for m in modes] == ref["modes"], lag
+        assert [list(map(int, p)) for p in pats] == ref["patterns"], lag
+        assert [int(x) for x in snap.acc] == ref["acc"], lag
+        n_ahist = sum(1 for m in ref["modes"] if m == O.MODE_AHIST)
+        if theta <= 4:   # narrow frames cross theta: both kernels run
+            assert 0 < n_ahist < count, (theta, n_ahist)
