@@ -234,6 +234,91 @@ def bench_xray(hm, G, O, torch, dev, hip_streams, S, rmax, lag, theta, frames=51
     return res
 
 
+def bench_ingest(hm, G, O, torch, dev):
+    """The stream fed from HOST memory (the paper's Sec. III.B setting): the 66 x 4 MiB stream in
+    pinned host memory, copied chunk by chunk to the device and histogrammed, with the paper's
+    pattern budget (S 960, rmax 8, theta 45) and the pattern of chunk k+1 from chunk k (lag 0).
+    Sequential: one HIP stream and a host synchronisation after every chunk, with its time
+    broken down (Tables 3-4): the copies alone, the kernels alone, and the rest (host launch
+    and synchronisation; the paper's CPU pattern recomputation is zero here, it runs on the
+    device).  Pipelined: the chunks spread over 1..256 HIP streams, as % of the sequential time
+    (Fig. 3: W = 1, the Accumulator; Fig. 4: moving windows W = 32 / 128 / 256)."""
+    chunks = G.stream_chunks(4 * MIB)
+    n = 4 * MIB
+    host = torch.empty(len(chunks) * n, dtype=torch.uint8, pin_memory=True)
+    hv = host.numpy()
+    for k, c in enumerate(chunks):
+        hv[k * n:(k + 1) * n] = c
+    base = int(host.data_ptr())
+    exp = np.stack([O.hist(c) for c in chunks]).astype(np.int64)
+    nb = len(chunks) * n
+    outs = torch.zeros((len(chunks), 256), dtype=torch.int32, device=dev)
+    dcopy = torch.empty(len(chunks) * n, dtype=torch.uint8, device=dev)
+    cur = torch.cuda.current_stream()
+    S, rmax, theta = 960, 8, 45
+
+    def wall(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    def ingest_pass(ing, W, sequential):
+        st = hm.Stream(W=W, theta_pct=theta, S=S, rmax=rmax, lag=0, trace_cap=0)
+
+        def go():
+            for k in range(len(chunks)):
+                ing.push(st, base + k * n, d_out=outs[k], n=n)
+                if sequential:
+                    ing.sync()
+            ing.sync()
+        go()                       # warm
+        t = min(wall(go) for _ in range(3))
+        ok = bool(np.array_equal(outs.cpu().numpy().astype(np.int64), exp))
+        st.close()
+        return t, ok
+
+    res = {"bytes": nb, "chunks": len(chunks), "S": S, "rmax": rmax, "theta_pct": theta, "lag": 0}
+    ing1 = hm.Ingest(n_hip_streams=1, slot_bytes=n)
+    t_seq, ok_seq = ingest_pass(ing1, 1, True)
+    ing1.close()
+
+    def copies():
+        for k in range(len(chunks)):
+            dcopy[k * n:(k + 1) * n].copy_(host[k * n:(k + 1) * n], non_blocking=True)
+            cur.synchronize()
+    t_copy = min(wall(copies) for _ in range(2))
+    st = hm.Stream(W=1, theta_pct=theta, S=S, rmax=rmax, lag=0, trace_cap=0)
+    dbase = int(dcopy.data_ptr())
+
+    def kernels():
+        for k in range(len(chunks)):
+            st.push(dbase + k * n, d_out=outs[k], n=n, stream=cur)
+            cur.synchronize()
+    kernels()
+    t_kern = min(wall(kernels) for _ in range(2))
+    st.close()
+    res["sequential"] = {"ms": round(t_seq * 1e3, 3), "GB/s": round(nb / t_seq / 1e9, 2), "parity_exact": ok_seq,
+                         "pct_copy": round(100 * t_copy / t_seq, 1), "pct_kernel": round(100 * t_kern / t_seq, 1),
+                         "pct_host_other": round(100 * max(0.0, t_seq - t_copy - t_kern) / t_seq, 1),
+                         "pct_cpu_pattern": 0.0}
+    fig = {}
+    for W in (1, 32, 128, 256):
+        row = {}
+        for K in ((1, 2, 4, 8, 16, 32, 64, 128, 256) if W == 1 else (1, 16, 256)):
+            ing = hm.Ingest(n_hip_streams=K, slot_bytes=n)
+            t, ok = ingest_pass(ing, W, False)
+            ing.close()
+            row[K] = {"pct_of_sequential": round(100 * t / t_seq, 1), "GB/s": round(nb / t / 1e9, 2),
+                      "parity_exact": ok}
+        fig["W%d" % W] = row
+    res["pipelined"] = fig
+    res["wait_timeouts"] = int(hm.diag().wait_timeouts)   # in-kernel decision waits that gave up (0 expected)
+    del host, dcopy
+    return res
+
+
 def bench_served(hm, G, O, torch, dev, stream, rates=(1000, 10000, 50000), duration=2.0):
     """Open-loop Poisson arrivals (sizes log-uniform 4 KiB..64 MiB, 64 stream ids) into the
     continuous-batching server; latency from scheduled arrival to host-observed completion."""
@@ -520,6 +605,7 @@ def main():
             del xs
         extras["table2_64mib_GBps"] = t2
         extras["xray_config3"] = bench_xray(hm, G, O, torch, dev, hip_streams, S, rmax, lag, theta)
+        extras["host_ingest_config2"] = bench_ingest(hm, G, O, torch, dev)
         extras["batched_config4"] = bench_batched(hm, G, O, torch, dev, stream)
         extras["served_config5"] = bench_served(hm, G, O, torch, dev, stream)
         res["extras"] = extras

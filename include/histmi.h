@@ -198,6 +198,40 @@ hist_status_t hist_stream_read(hist_stream_t *st, hist_stream_snapshot_t *snap, 
 /* Synchronous; waits for the device before freeing. */
 hist_status_t hist_stream_destroy(hist_stream_t *st);
 
+/* ---------------------------------------------------------------- host ingest (Sec. III.B) */
+
+/*
+ * Streams whose chunks live in HOST memory: each chunk is copied to the device and pushed
+ * through a stream, with the copies of some chunks overlapping the counting of others across
+ * n_hip_streams HIP streams -- the paper's pipelined stream (Sec. III.B, Fig. 2), whose
+ * benefit it measures against 1..256 CUDA streams (Figs. 3-4).  The decisions stay on the
+ * device, so no host round trip is needed between chunks.  Calling hist_ingest_sync after
+ * every push gives the sequential variant the paper compares against.
+ */
+typedef struct hist_ingest hist_ingest_t;
+
+typedef struct {
+    uint32_t n_hip_streams;   /* 1..256 HIP streams used in turn */
+    uint64_t slot_bytes;      /* largest chunk (< 2^32); one device staging buffer of this size per HIP stream */
+} hist_ingest_config_t;
+
+hist_status_t hist_ingest_create(hist_ingest_t **ing, const hist_ingest_config_t *cfg);
+
+/* Copies h_chunk[0, n) (host memory; pinned memory, e.g. from hipHostMalloc, copies at full
+ * speed and asynchronously) into the next HIP stream's staging buffer and pushes it as one
+ * chunk of `st` (the semantics of hist_stream_push).  Returns once the copy and the launch
+ * are queued: h_chunk must stay valid and unchanged until hist_ingest_sync returns.
+ * d_out_k: device uint32[256] overwritten with the chunk's histogram, or NULL.
+ * Errors: HIST_EINVAL (NULL handles, NULL h_chunk with n > 0, n > slot_bytes, bad mode). */
+hist_status_t hist_ingest_push(hist_ingest_t *ing, hist_stream_t *st, const void *h_chunk, size_t n,
+                               hist_mode_t mode, uint32_t *d_out_k);
+
+/* Waits for every queued copy and launch of this ingest. */
+hist_status_t hist_ingest_sync(hist_ingest_t *ing);
+
+/* Synchronous; waits before freeing. */
+hist_status_t hist_ingest_destroy(hist_ingest_t *ing);
+
 /* ---------------------------------------------------------------- batches (Sec. III.B) */
 
 /*

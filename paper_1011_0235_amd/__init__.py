@@ -7,7 +7,7 @@ is its thin binding.  There is no CPU fallback: calls fail if the library is not
 from ._lib import (  # noqa: F401
     AUTO_FLAT_R, EBUSY, ECANCELED, EDEVICE, EINVAL, ENOMEM, ENOTSUP, EOVERFLOW, ETIMEDOUT, OK,
     MODE_AHIST, MODE_AUTO, MODE_WAVEAGG, MODE_WAVEHIST, PAT_FLAT, PAT_IDENTITY, PAT_PAPER960, RMAX_MAX, S_MAX,
-    BatchGraph, HistError, Pattern, Server, Stream, declared_symbols, device_info, diag, hist_batch, hist_u8,
+    BatchGraph, HistError, Ingest, Pattern, Server, Stream, declared_symbols, device_info, diag, hist_batch, hist_u8,
     hist_u8_u64, load, pattern_init, pattern_update, pattern_validate, strerror, tune_get, tune_set,
     TUNE_STREAM, read_probe,
 )

@@ -61,6 +61,10 @@ class StreamConfig(ctypes.Structure):
                 ("rmax", ctypes.c_uint32), ("lag", ctypes.c_uint32), ("trace_cap", ctypes.c_uint32)]
 
 
+class IngestConfig(ctypes.Structure):
+    _fields_ = [("n_hip_streams", ctypes.c_uint32), ("slot_bytes", ctypes.c_uint64)]
+
+
 class StreamSnapshot(ctypes.Structure):
     _fields_ = [("chunks", ctypes.c_uint64), ("acc", ctypes.c_uint64 * 256), ("mw", ctypes.c_uint64 * 256),
                 ("next_mode", ctypes.c_uint32), ("next_pattern", Pattern)]
@@ -119,6 +123,10 @@ _SIGS = [
     ("hist_read_probe", ctypes.c_int, [_VP, ctypes.c_size_t, _VP, ctypes.c_uint32, _VP]),
     ("hist_tune_set", ctypes.c_int, [ctypes.c_uint32, ctypes.POINTER(Tune)]),
     ("hist_tune_get", ctypes.c_int, [ctypes.c_uint32, ctypes.POINTER(Tune)]),
+    ("hist_ingest_create", ctypes.c_int, [ctypes.POINTER(_VP), ctypes.POINTER(IngestConfig)]),
+    ("hist_ingest_push", ctypes.c_int, [_VP, _VP, _VP, ctypes.c_size_t, ctypes.c_int, _VP]),
+    ("hist_ingest_sync", ctypes.c_int, [_VP]),
+    ("hist_ingest_destroy", ctypes.c_int, [_VP]),
     ("hist_server_create", ctypes.c_int, [ctypes.POINTER(_VP), ctypes.POINTER(ServerConfig)]),
     ("hist_server_submit", ctypes.c_int, [_VP, ctypes.c_uint32, _VP, ctypes.c_size_t, _VP, c_u64p]),
     ("hist_server_poll", ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.POINTER(ServerResult)]),
@@ -332,6 +340,40 @@ class Stream:
     def close(self):
         if self._h:
             load().hist_stream_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Ingest:
+    """Host-ingest pipeline: pushes chunks that live in host memory (pinned for asynchronous
+    copies) through device streams, copies overlapping counting over n_hip_streams HIP streams."""
+
+    def __init__(self, n_hip_streams: int = 4, slot_bytes: int = 4 << 20):
+        cfg = IngestConfig(n_hip_streams, slot_bytes)
+        self.cfg = cfg
+        self._h = ctypes.c_void_p()
+        _check(load().hist_ingest_create(ctypes.byref(self._h), ctypes.byref(cfg)), "hist_ingest_create")
+
+    def push(self, stream: "Stream", h_chunk, mode: int = MODE_AUTO, d_out=None, n: Optional[int] = None):
+        """h_chunk: a host tensor / numpy array / host address (must stay valid until sync)."""
+        if isinstance(h_chunk, np.ndarray):
+            ptr, nb = int(h_chunk.ctypes.data), int(h_chunk.nbytes)
+        else:
+            ptr, nb = _ptr(h_chunk), (_nbytes(h_chunk) if not isinstance(h_chunk, int) else 0)
+        nb = nb if n is None else int(n)
+        _check(load().hist_ingest_push(self._h, stream._h, ptr, nb, int(mode), _ptr(d_out)), "hist_ingest_push")
+
+    def sync(self):
+        _check(load().hist_ingest_sync(self._h), "hist_ingest_sync")
+
+    def close(self):
+        if self._h:
+            load().hist_ingest_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

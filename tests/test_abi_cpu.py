@@ -117,6 +117,11 @@ def test_stream_and_server_config_errors(hm):
                 hm._lib.ServerConfig(1 << 20, 4, 4, 17, 4, 0, 45, 960, 8),
                 hm._lib.ServerConfig(1 << 20, 4, 4, 1, 4, 5, 45, 960, 8)):
         assert lib.hist_server_create(ctypes.byref(h), ctypes.byref(cfg)) == hm.EINVAL
+    for cfg in (hm._lib.IngestConfig(0, 1 << 20), hm._lib.IngestConfig(257, 1 << 20), hm._lib.IngestConfig(4, 0),
+                hm._lib.IngestConfig(4, 1 << 33)):
+        assert lib.hist_ingest_create(ctypes.byref(h), ctypes.byref(cfg)) == hm.EINVAL
+    assert lib.hist_ingest_push(None, None, None, 0, 0, None) == hm.EINVAL
+    assert lib.hist_ingest_sync(None) == hm.EINVAL
     assert lib.hist_stream_push(None, None, 0, 0, None, None) == hm.EINVAL
     assert lib.hist_server_submit(None, 0, None, 0, None, None) == hm.EINVAL
 
