@@ -392,8 +392,14 @@ hist_status_t run_multi(DevCtx *d, Params &P, const MultiPlan &mp, uint32_t copi
 hist_status_t stream_state_alloc(uint32_t count, uint32_t W, uint32_t theta, uint32_t S, uint32_t rmax, uint32_t lag,
                                  uint32_t nslot, uint32_t trace_cap, StreamAlloc *sa) {
   const size_t tc = std::max<uint32_t>(trace_cap, 1);
+  // W > 1: chunks are sequenced in order (moving window) from a ring of recent histograms.
+  // Chunk j's histogram is needed until chunk j + W is sequenced; the chunk that reuses its
+  // slot (j + R) is counted only after its decision, made when chunk j + R - 1 - lag was
+  // sequenced, so R >= W + lag + 1 suffices (plus a margin).
+  const uint32_t R = W > 1 ? W + lag + 66 : 1;
+  sa->R = R;
   bool ok = hipMalloc(&sa->d_st, (size_t)count * sizeof(StreamDev)) == hipSuccess &&
-            hipMalloc(&sa->d_ring, (size_t)count * W * 256 * 4) == hipSuccess &&
+            hipMalloc(&sa->d_ring, (size_t)count * R * 256 * 8) == hipSuccess &&
             hipMalloc(&sa->d_slots, (size_t)count * nslot * sizeof(Decision)) == hipSuccess &&
             hipMalloc(&sa->d_mode_trace, (size_t)count * tc) == hipSuccess &&
             hipMalloc(&sa->d_pat_trace, (size_t)count * tc * 256 * 4) == hipSuccess;
@@ -413,13 +419,14 @@ hist_status_t stream_state_alloc(uint32_t count, uint32_t W, uint32_t theta, uin
     x.nslot = nslot;
     x.trace_cap = trace_cap;
     x.lookup_rr = rmax > 32 ? 64 : 32;
-    x.ring = sa->d_ring + (size_t)i * W * 256;
+    x.R = R;
+    x.ring = sa->d_ring + (size_t)i * R * 256;
     x.slots = sa->d_slots + (size_t)i * nslot;
     x.mode_trace = sa->d_mode_trace + (size_t)i * tc;
     x.pat_trace = sa->d_pat_trace + (size_t)i * tc * 256;
   }
   ok = hipMemcpy(sa->d_st, h.data(), (size_t)count * sizeof(StreamDev), hipMemcpyHostToDevice) == hipSuccess &&
-       hipMemset(sa->d_ring, 0, (size_t)count * W * 256 * 4) == hipSuccess &&
+       hipMemset(sa->d_ring, 0, (size_t)count * R * 256 * 8) == hipSuccess &&
        hipMemset(sa->d_slots, 0, (size_t)count * nslot * sizeof(Decision)) == hipSuccess &&
        hipMemset(sa->d_mode_trace, 0, (size_t)count * tc) == hipSuccess &&
        hipMemset(sa->d_pat_trace, 0, (size_t)count * tc * 256 * 4) == hipSuccess;
@@ -730,6 +737,7 @@ static void stream_params(const hist_stream *st, Params *P) {
   P->theta = st->cfg.theta_pct;
   P->S = st->cfg.S;
   P->rmax = st->cfg.rmax;
+  P->R = st->sa.R;
   P->trace_cap = st->cfg.trace_cap;
 }
 

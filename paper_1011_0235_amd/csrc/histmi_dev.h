@@ -42,10 +42,13 @@ __host__ __device__ constexpr uint32_t tag_kind_lg(uint64_t tag) { return (uint3
 // Device-resident state of one stream (Accumulator, moving window, decisions, traces).
 struct StreamDev {
   uint32_t W, theta, S, rmax, lag, nslot, trace_cap, lookup_rr;
-  uint64_t done;         // chunk epilogues completed (W > 1: stored in order with release; W = 1: counted)
-  uint64_t acc[256];
-  uint64_t mw[256];
-  uint32_t *ring;        // [W][256] histograms of the last W chunks
+  uint32_t R;            // sequenced streams (W > 1): histogram ring slots
+  uint32_t seq_lock;     // sequenced streams: 1 while a workgroup sequences chunks
+  uint64_t done;         // W = 1: chunk epilogues completed (counted); W > 1: chunks sequenced
+  uint64_t acc[256];     // Accumulator (every chunk's finalizer adds its histogram)
+  uint64_t mw[256];      // moving window after the last sequenced chunk (W > 1)
+  uint64_t *ring;        // [R][256] recent histograms (W > 1), chunk j in slot j % R, each
+                         // entry (j + 1) << 32 | count: a load tells whether it is chunk j's
   Decision *slots;       // [nslot]; decision made after chunk j lives in slot j % nslot
   uint8_t *mode_trace;   // [trace_cap]
   uint32_t *pat_trace;   // [trace_cap][256]
@@ -108,7 +111,7 @@ struct Params {
   uint32_t theta;            // critical degeneracy, percent
   uint32_t S;                // sub-bin budget of rule P
   uint32_t rmax;             // sub-bin cap of rule P
-  uint32_t pad;
+  uint32_t R;                // histogram ring slots (W > 1)
   uint64_t trace_cap;
   Decision *slots;           // the stream's decision ring
   // LDS layout (in 32-bit words)

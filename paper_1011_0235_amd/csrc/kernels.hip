@@ -53,12 +53,14 @@ struct Ctl {
   uint32_t used_mode;
   uint32_t tmp;
   uint64_t tag;            // decision tag of the current segment's stream chunk
+  uint64_t seqj;           // the stream sequencer's next chunk
   // multi-segment launches, double-buffered so that one barrier per step suffices:
   SegDesc sd[2];           // the current segment's descriptor (and the next one's, being staged)
   TileRec nrec[2];         // the next tile's record, by tile parity
   uint32_t ntile[2];       // the next tile's index, by tile parity
   uint32_t red32[kWaves];
   uint64_t red64[kWaves];
+  uint64_t red64b[kWaves];
   uint32_t cls_cnt[kWaves][8];
   uint32_t words[256];     // binning pattern words of the current segment
   uint32_t bitmap[512];    // overlap check of a pattern (up to HIST_S_MAX sub-bins)
@@ -106,6 +108,31 @@ __device__ uint64_t block_sum_u64(uint64_t v, Ctl &c) {
   for (uint32_t w = 0; w < kWaves; ++w) s += c.red64[w];
   __syncthreads();
   return s;
+}
+
+// Sum and maximum of v over the workgroup in one pass.
+__device__ void block_sum_max_u64(uint64_t v, Ctl &c, uint64_t *sum, uint64_t *mx) {
+  uint64_t a = v, m = v;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a += shfl_xor_u64(a, o);
+    const uint64_t u = shfl_xor_u64(m, o);
+    m = u > m ? u : m;
+  }
+  if (lane_id() == 0) {
+    c.red64[wave_id()] = a;
+    c.red64b[wave_id()] = m;
+  }
+  __syncthreads();
+  uint64_t s = 0, x = 0;
+#pragma unroll
+  for (uint32_t w = 0; w < kWaves; ++w) {
+    s += c.red64[w];
+    x = c.red64b[w] > x ? c.red64b[w] : x;
+  }
+  __syncthreads();
+  *sum = s;
+  *mx = x;
 }
 
 __device__ uint64_t block_max_u64(uint64_t v, Ctl &c) {
@@ -651,41 +678,33 @@ __device__ __forceinline__ void server_epilogue(const Params &P, Ctl &c, uint32_
   if (t == 0) st_agent(&d->tag, make_tag(1, mode, kind_lg));   // generation 1: "a decision exists"
 }
 
-// Stream epilogue for chunk k with histogram h (thread t holds bin t): Accumulator, moving
-// window, degeneracy switch and rule P (Sec. III.B, Sec. III.C), then the trace of what
-// chunk k ran with.  With a window of one chunk (W = 1) the decision after chunk k depends
-// on h_k alone, so epilogues of different chunks run independently; with W > 1 the moving
-// window is updated in chunk order.
-__device__ __forceinline__ void stream_epilogue(const Params &P, Ctl &c, uint32_t sidx, int64_t k, uint32_t h) {
+// The decision after chunk j of an ordered stream, from its moving window mw (thread t
+// holds bin t; h is chunk j's own histogram, kept with the decision for snapshots):
+// degeneracy switch (Sec. III.C) and rule P (Sec. III.B), written to decision slot j.
+__device__ __forceinline__ void decide_and_publish(const Params &P, Ctl &c, uint64_t j, uint64_t mw, uint32_t h) {
   const uint32_t t = threadIdx.x;
-  StreamDev *st = P.st + sidx;
-  const uint32_t W = P.W;
-  atomicAdd(reinterpret_cast<unsigned long long *>(&st->acc[t]), (unsigned long long)h);
-  uint64_t mw;
-  if (W == 1) {
-    mw = h;
-  } else {
-    if (t == 0) spin_until_u64(&st->done, (uint64_t)k, P.diag);
-    __syncthreads();
-    uint32_t *ring = st->ring + (size_t)((uint64_t)k % W) * 256u;
-    const uint32_t old = ((uint64_t)k >= W) ? ld_agent(&ring[t]) : 0u;
-    st_agent(&ring[t], h);
-    mw = ld_agent(&st->mw[t]) + (uint64_t)h - (uint64_t)old;
-    st_agent(&st->mw[t], mw);
-  }
   // degeneracy of the window: AHist iff some bin exceeds theta percent (strict)
-  const uint64_t N = block_sum_u64(mw, c);
-  const uint64_t mx = block_max_u64(mw, c);
+  uint64_t N, mx;
+  block_sum_max_u64(mw, c, &N, &mx);
   const uint32_t mode = (100ull * mx > (uint64_t)P.theta * N) ? HIST_MODE_AHIST : HIST_MODE_WAVEHIST;
-  const uint32_t word = rule_p_word(mw, N, P.S, P.rmax, c);
-  const uint32_t kind_lg = pattern_kind_lg(word, c);
-  Decision *d = &P.slots[(uint64_t)k % P.nslot];
-  // The chunk that runs with this decision (k + 1 + lag) reads the pattern words only for a
+  uint32_t word, kind_lg;
+  if (256u * P.rmax <= P.S) {
+    // the budget holds rmax sub-bins for every value: rule P's first case, whatever the
+    // window; the pattern is the uniform table v * rmax (no block-wide passes needed)
+    const uint32_t lg = (uint32_t)__builtin_ctz(P.rmax);
+    word = (t << lg) | (lg << 16);
+    kind_lg = ((uint32_t)KIND_UNIFORM << 8) | lg;
+  } else {
+    word = rule_p_word(mw, N, P.S, P.rmax, c);
+    kind_lg = pattern_kind_lg(word, c);
+  }
+  Decision *d = &P.slots[j % P.nslot];
+  // The chunk that runs with this decision (j + 1 + lag) reads the pattern words only for a
   // lookup table or for its trace.  Otherwise the tag alone carries the decision, and it is
   // published at once instead of after the other stores are acknowledged: that shortens the
   // path from this chunk's last tile to the chunks that wait for it.
-  const uint64_t tag = make_tag((uint64_t)(k + 1), mode, kind_lg);
-  const bool words_needed = (kind_lg >> 8) == KIND_LOOKUP || (uint64_t)k + 1 + P.lag < P.trace_cap;
+  const uint64_t tag = make_tag(j + 1, mode, kind_lg);
+  const bool words_needed = (kind_lg >> 8) == KIND_LOOKUP || j + 1 + P.lag < P.trace_cap;
   if (!words_needed && t == 0) st_agent(&d->tag, tag);
   st_agent(&d->words[t], word);
   st_agent(&d->hist[t], h);
@@ -693,17 +712,93 @@ __device__ __forceinline__ void stream_epilogue(const Params &P, Ctl &c, uint32_
     st_agent(&d->S, P.S);
     st_agent(&d->rmax, P.rmax);
   }
+  if (words_needed) {
+    order_global();
+    __syncthreads();
+    if (t == 0) st_agent(&d->tag, tag);
+  }
+}
+
+// Sequencing of a stream with a moving window of W > 1 chunks.  MW_j needs the chunks in
+// order, but chunks finish in any order; rather than have each chunk's finalizer wait for the
+// one before it, every finalizer leaves its histogram in the ring and tries (one CAS) to
+// become the stream's sequencer.  The sequencer keeps the window in registers and takes the
+// chunks in order for as long as the next one's histogram is there: MW += h_j - h_{j-W},
+// then the decision after chunk j.  Before it leaves it stores the window, releases the lock
+// and looks once more, so a histogram that arrived while it held the lock is never left
+// behind (its own finalizer's CAS failed only while the lock was held).  Nothing waits.
+__device__ __forceinline__ void sequence_stream(const Params &P, Ctl &c, StreamDev *st) {
+  const uint32_t t = threadIdx.x;
+  const uint32_t W = P.W, R = P.R;
+  for (;;) {
+    if (t == 0) c.flag = (atomicCAS(&st->seq_lock, 0u, 1u) == 0u) ? 1u : 0u;
+    __syncthreads();
+    const bool holder = c.flag != 0;
+    __syncthreads();
+    if (!holder) return;
+    if (t == 0) c.seqj = ld_agent(&st->done);
+    __syncthreads();
+    uint64_t j = c.seqj;
+    uint64_t mw = ld_agent(&st->mw[t]);
+    // Each ring entry carries its chunk's generation, so entries can be loaded ahead and
+    // checked when they are used: four chunks' entries are in flight while a decision is
+    // made (four register sets, rotated by unrolling so none is indexed at run time).
+    auto load = [&](uint64_t q, uint64_t &e, uint64_t &eo) {
+      e = ld_agent(&st->ring[(q % R) * 256u + t]);
+      eo = q >= W ? ld_agent(&st->ring[((q - W) % R) * 256u + t]) : 0u;
+    };
+    // takes chunk j from (e, eo) if it is there, then loads chunk j + 4 into (e, eo)
+    auto step = [&](uint64_t &e, uint64_t &eo) -> bool {
+      if (!block_all((uint32_t)(e >> 32) == (uint32_t)(j + 1), c)) return false;
+      const uint32_t hj = (uint32_t)e;
+      mw += (uint64_t)hj - (uint64_t)(uint32_t)eo;
+      load(j + 4, e, eo);
+      decide_and_publish(P, c, j, mw, hj);
+      ++j;
+      return true;
+    };
+    uint64_t e0, o0, e1, o1, e2, o2, e3, o3;
+    load(j, e0, o0);
+    load(j + 1, e1, o1);
+    load(j + 2, e2, o2);
+    load(j + 3, e3, o3);
+    while (step(e0, o0) && step(e1, o1) && step(e2, o2) && step(e3, o3)) {
+    }
+    st_agent(&st->mw[t], mw);
+    if (t == 0) st_agent(&st->done, j);
+    order_global();
+    __syncthreads();
+    if (t == 0) st_agent(&st->seq_lock, 0u);
+    order_global();
+    // look once more: a histogram that arrived while the lock was held
+    const uint64_t e = ld_agent(&st->ring[(j % R) * 256u + t]);
+    if (!block_all((uint32_t)(e >> 32) == (uint32_t)(j + 1), c)) return;
+  }
+}
+
+// Stream epilogue for chunk k with histogram h (thread t holds bin t): Accumulator, the trace
+// of what chunk k ran with, then the moving window, degeneracy switch and rule P (Sec. III.B,
+// Sec. III.C).  With a window of one chunk (W = 1) the decision after chunk k depends on h_k
+// alone, so epilogues of different chunks run independently; with W > 1 the chunks are
+// sequenced (see sequence_stream).
+__device__ __forceinline__ void stream_epilogue(const Params &P, Ctl &c, uint32_t sidx, int64_t k, uint32_t h) {
+  const uint32_t t = threadIdx.x;
+  StreamDev *st = P.st + sidx;
+  atomicAdd(reinterpret_cast<unsigned long long *>(&st->acc[t]), (unsigned long long)h);
   if ((uint64_t)k < P.trace_cap) {
     st_agent(&st->pat_trace[(size_t)k * 256u + t], c.words[t]);
     if (t == 0) st->mode_trace[k] = (uint8_t)c.used_mode;
   }
-  order_global();
-  __syncthreads();
-  if (t == 0) {
-    if (words_needed) st_agent(&d->tag, tag);
-    if (W == 1) __hip_atomic_fetch_add(&st->done, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    else __hip_atomic_store(&st->done, (uint64_t)(k + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (P.W == 1) {
+    decide_and_publish(P, c, (uint64_t)k, (uint64_t)h, h);
+    if (t == 0) __hip_atomic_fetch_add(&st->done, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return;
   }
+  const uint32_t slot = (uint32_t)((uint64_t)k % P.R);
+  st_agent(&st->ring[slot * 256u + t], ((uint64_t)(uint32_t)(k + 1) << 32) | h);
+  order_global();     // every entry is in before the CAS below (so a failing CAS means the
+  __syncthreads();    // sequencer's last look will find them)
+  sequence_stream(P, c, st);
 }
 
 // Merge of a segment.

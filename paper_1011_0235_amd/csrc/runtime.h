@@ -145,7 +145,8 @@ hist_status_t run_multi(DevCtx *d, Params &P, const MultiPlan &mp, uint32_t copi
 // Device-resident stream states: allocation and release.
 struct StreamAlloc {
   StreamDev *d_st = nullptr;
-  uint32_t *d_ring = nullptr;
+  uint32_t R = 1;                 // histogram ring slots per stream
+  uint64_t *d_ring = nullptr;
   Decision *d_slots = nullptr;
   uint8_t *d_mode_trace = nullptr;
   uint32_t *d_pat_trace = nullptr;

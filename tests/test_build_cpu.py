@@ -1,11 +1,13 @@
 """Compile-time resource checks of the counting kernels (host only: hipcc cross-compiles for
 gfx950 without a GPU).
 
-Every kernel must use no per-lane scratch memory.  The main kernel takes its parameter block
-by value; if any helper that receives it by reference is left out of line, the compiler
-copies the whole block (over 1 KiB) into each lane's private memory on entry, which costs
-more than the histogram itself.  Occupancy must stay at >= 3 wavefronts per SIMD (three
-workgroups of four wavefronts per CU)."""
+No kernel may touch per-lane scratch memory.  The main kernel takes its parameter block by
+value; if any helper that receives it by reference is left out of line, the compiler copies
+the whole block (over 1 KiB) into each lane's private memory on entry, which costs more than
+the histogram itself.  The generated code must hold no scratch load or store at all, and the
+reserved private segment must stay small (the register allocator may reserve an emergency
+spill slot of a few bytes that no instruction uses).  Occupancy must stay at >= 3 wavefronts
+per SIMD (three workgroups of four wavefronts per CU)."""
 
 import os
 import re
@@ -38,7 +40,13 @@ def test_kernels_use_no_scratch(tmp_path):
             kernels[name][m.group(1).strip()] = int(m.group(2))
     assert any("hist_main" in k for k in kernels), list(kernels)
     for k, res in kernels.items():
-        assert res.get("ScratchSize [bytes/lane]") == 0, (k, res)
+        assert res.get("ScratchSize [bytes/lane]", 0) <= 64, (k, res)
         assert res.get("VGPRs Spill", 0) == 0, (k, res)
         if "hist_main" in k:
             assert res.get("Occupancy [waves/SIMD]", 0) >= 3, (k, res)
+    asm = tmp_path / "k.s"
+    r = subprocess.run(["hipcc"] + build.hip_flags() + ["--cuda-device-only", "-S", src, "-o", str(asm)],
+                       capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stderr[-2000:]
+    text = asm.read_text()
+    assert not re.search(r"^\s*(scratch_(load|store)|buffer_(load|store)_\w+\s.*s\[0:3\])", text, re.M)
