@@ -399,7 +399,7 @@ hist_status_t stream_state_alloc(uint32_t count, uint32_t W, uint32_t theta, uin
   const uint32_t R = W > 1 ? W + lag + 66 : 1;
   sa->R = R;
   bool ok = hipMalloc(&sa->d_st, (size_t)count * sizeof(StreamDev)) == hipSuccess &&
-            hipMalloc(&sa->d_ring, (size_t)count * R * 256 * 8) == hipSuccess &&
+            hipMalloc(&sa->d_ring, (size_t)count * R * 257 * 8) == hipSuccess &&
             hipMalloc(&sa->d_slots, (size_t)count * nslot * sizeof(Decision)) == hipSuccess &&
             hipMalloc(&sa->d_mode_trace, (size_t)count * tc) == hipSuccess &&
             hipMalloc(&sa->d_pat_trace, (size_t)count * tc * 256 * 4) == hipSuccess;
@@ -421,12 +421,13 @@ hist_status_t stream_state_alloc(uint32_t count, uint32_t W, uint32_t theta, uin
     x.lookup_rr = rmax > 32 ? 64 : 32;
     x.R = R;
     x.ring = sa->d_ring + (size_t)i * R * 256;
+    x.ring_n = sa->d_ring + (size_t)count * R * 256 + (size_t)i * R;
     x.slots = sa->d_slots + (size_t)i * nslot;
     x.mode_trace = sa->d_mode_trace + (size_t)i * tc;
     x.pat_trace = sa->d_pat_trace + (size_t)i * tc * 256;
   }
   ok = hipMemcpy(sa->d_st, h.data(), (size_t)count * sizeof(StreamDev), hipMemcpyHostToDevice) == hipSuccess &&
-       hipMemset(sa->d_ring, 0, (size_t)count * R * 256 * 8) == hipSuccess &&
+       hipMemset(sa->d_ring, 0, (size_t)count * R * 257 * 8) == hipSuccess &&
        hipMemset(sa->d_slots, 0, (size_t)count * nslot * sizeof(Decision)) == hipSuccess &&
        hipMemset(sa->d_mode_trace, 0, (size_t)count * tc) == hipSuccess &&
        hipMemset(sa->d_pat_trace, 0, (size_t)count * tc * 256 * 4) == hipSuccess;
@@ -824,9 +825,15 @@ hist_status_t hist_stream_read(hist_stream_t *st, hist_stream_snapshot_t *snap, 
       snap->next_mode = tag_mode(dec.tag);
       if (st->cfg.W == 1)
         for (int v = 0; v < 256; ++v) snap->mw[v] = dec.hist[v];
-      std::memcpy(snap->next_pattern.word, dec.words, sizeof(dec.words));
-      snap->next_pattern.total_S = dec.S;
-      snap->next_pattern.rmax = dec.rmax;
+      const uint32_t kl = tag_kind_lg(dec.tag);
+      if ((kl >> 8) == KIND_UNIFORM) {   // the words of a uniform pattern are not stored
+        const uint32_t lg = kl & 0xFFu;
+        for (uint32_t v = 0; v < 256; ++v) snap->next_pattern.word[v] = (v << lg) | (lg << 16);
+      } else {
+        std::memcpy(snap->next_pattern.word, dec.words, sizeof(dec.words));
+      }
+      snap->next_pattern.total_S = st->cfg.S;
+      snap->next_pattern.rmax = st->cfg.rmax;
     } else {
       snap->next_mode = HIST_MODE_WAVEHIST;
       TRY(hist_pattern_init(&snap->next_pattern, HIST_PAT_IDENTITY, 0, 0));

@@ -23,9 +23,11 @@ enum Kind : uint32_t {
 // A stream's kernel choice for one chunk: written by the epilogue of the chunk it was
 // derived from, read by the chunk that runs with it.
 struct Decision {
-  uint32_t words[256];   // binning pattern words (hist_pattern_t encoding)
-  uint32_t hist[256];    // histogram of the producing chunk (the moving window when W = 1)
-  uint32_t S, rmax;
+  uint32_t words[256];   // binning pattern words (hist_pattern_t encoding); stored only when a
+                         // chunk needs them (a lookup table, or a traced chunk): a uniform
+                         // pattern's words follow from the tag (value v at v << lg)
+  uint32_t hist[256];    // histogram of the producing chunk (W = 1 only: the moving window)
+  uint32_t S, rmax;      // stored with the words
   // stored last, in one 64-bit store, so that one load both says whether the decision is
   // there and carries what a uniform table needs:
   //   bits [32,64) producing chunk index + 1 (0: none yet), [16,24) mode (HIST_MODE_*),
@@ -39,16 +41,25 @@ __host__ __device__ constexpr uint32_t tag_gen(uint64_t tag) { return (uint32_t)
 __host__ __device__ constexpr uint32_t tag_mode(uint64_t tag) { return (uint32_t)(tag >> 16) & 0xFFu; }
 __host__ __device__ constexpr uint32_t tag_kind_lg(uint64_t tag) { return (uint32_t)tag & 0xFFFFu; }
 
+// Size-ring entries: a chunk of a stream is a device buffer, so its size fits in 40 bits
+// (1 TiB); the 24 bits above carry its generation (chunk index + 1, modulo 2^24; ring slots
+// are reused every R < 2^24 chunks, so an old entry never passes for a new one).
+constexpr uint32_t kSizeBits = 40;
+constexpr uint64_t kSizeMask = (1ull << kSizeBits) - 1;
+constexpr uint32_t kSizeGenMask = 0xFFFFFFu;
+
 // Device-resident state of one stream (Accumulator, moving window, decisions, traces).
 struct StreamDev {
   uint32_t W, theta, S, rmax, lag, nslot, trace_cap, lookup_rr;
   uint32_t R;            // sequenced streams (W > 1): histogram ring slots
   uint32_t seq_lock;     // sequenced streams: 1 while a workgroup sequences chunks
   uint64_t done;         // W = 1: chunk epilogues completed (counted); W > 1: chunks sequenced
+  uint64_t win_n;        // W > 1: bytes in the moving window after the last sequenced chunk
   uint64_t acc[256];     // Accumulator (every chunk's finalizer adds its histogram)
   uint64_t mw[256];      // moving window after the last sequenced chunk (W > 1)
   uint64_t *ring;        // [R][256] recent histograms (W > 1), chunk j in slot j % R, each
                          // entry (j + 1) << 32 | count: a load tells whether it is chunk j's
+  uint64_t *ring_n;      // [R] the same chunks' sizes, (j + 1 mod 2^24) << 40 | bytes
   Decision *slots;       // [nslot]; decision made after chunk j lives in slot j % nslot
   uint8_t *mode_trace;   // [trace_cap]
   uint32_t *pat_trace;   // [trace_cap][256]

@@ -54,13 +54,14 @@ struct Ctl {
   uint32_t tmp;
   uint64_t tag;            // decision tag of the current segment's stream chunk
   uint64_t seqj;           // the stream sequencer's next chunk
+  uint64_t seqn;           // and the bytes in its window
+  uint32_t sflag[2][kWaves];  // the sequencer's per-wavefront flags, by chunk parity
   // multi-segment launches, double-buffered so that one barrier per step suffices:
   SegDesc sd[2];           // the current segment's descriptor (and the next one's, being staged)
   TileRec nrec[2];         // the next tile's record, by tile parity
   uint32_t ntile[2];       // the next tile's index, by tile parity
   uint32_t red32[kWaves];
   uint64_t red64[kWaves];
-  uint64_t red64b[kWaves];
   uint32_t cls_cnt[kWaves][8];
   uint32_t words[256];     // binning pattern words of the current segment
   uint32_t bitmap[512];    // overlap check of a pattern (up to HIST_S_MAX sub-bins)
@@ -94,8 +95,17 @@ __device__ uint32_t block_sum_u32(uint32_t v, Ctl &c) {
   return s;
 }
 
+// True iff p holds on every thread: one ballot per wavefront (no cross-lane traffic), the
+// four results meet in LDS.
 __device__ bool block_all(bool p, Ctl &c) {
-  return block_sum_u32(p ? 0u : 1u, c) == 0u;
+  const uint64_t fails = __ballot(!p);
+  if (lane_id() == 0) c.red32[wave_id()] = fails ? 1u : 0u;
+  __syncthreads();
+  uint32_t any = 0;
+#pragma unroll
+  for (uint32_t w = 0; w < kWaves; ++w) any |= c.red32[w];
+  __syncthreads();
+  return any == 0u;
 }
 
 __device__ uint64_t block_sum_u64(uint64_t v, Ctl &c) {
@@ -108,31 +118,6 @@ __device__ uint64_t block_sum_u64(uint64_t v, Ctl &c) {
   for (uint32_t w = 0; w < kWaves; ++w) s += c.red64[w];
   __syncthreads();
   return s;
-}
-
-// Sum and maximum of v over the workgroup in one pass.
-__device__ void block_sum_max_u64(uint64_t v, Ctl &c, uint64_t *sum, uint64_t *mx) {
-  uint64_t a = v, m = v;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    a += shfl_xor_u64(a, o);
-    const uint64_t u = shfl_xor_u64(m, o);
-    m = u > m ? u : m;
-  }
-  if (lane_id() == 0) {
-    c.red64[wave_id()] = a;
-    c.red64b[wave_id()] = m;
-  }
-  __syncthreads();
-  uint64_t s = 0, x = 0;
-#pragma unroll
-  for (uint32_t w = 0; w < kWaves; ++w) {
-    s += c.red64[w];
-    x = c.red64b[w] > x ? c.red64b[w] : x;
-  }
-  __syncthreads();
-  *sum = s;
-  *mx = x;
 }
 
 __device__ uint64_t block_max_u64(uint64_t v, Ctl &c) {
@@ -166,13 +151,24 @@ __device__ __forceinline__ void order_global() {
 #endif
 }
 
+// Device-memory pointer.  Pointers that the kernel loads from memory (the stream state's ring
+// and trace arrays, a segment's buffers) reach it as generic pointers; a generic access is a
+// FLAT instruction, which counts against both the vector-memory and the LDS counters and so
+// makes every later wait a wait for all outstanding memory operations.  Every access below
+// goes to device memory, never LDS, and says so.
+template <typename T> using gptr = __attribute__((address_space(1))) T *;
+template <typename T>
+__device__ __forceinline__ gptr<T> gmem(T *p) {
+  return (gptr<T>)p;
+}
+
 template <typename T>
 __device__ __forceinline__ T ld_agent(const T *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(gmem(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 template <typename T>
 __device__ __forceinline__ void st_agent(T *p, T v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(gmem(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Bounded spin by thread 0 until *p == want.  Polls with relaxed agent-scope loads (no
@@ -678,124 +674,196 @@ __device__ __forceinline__ void server_epilogue(const Params &P, Ctl &c, uint32_
   if (t == 0) st_agent(&d->tag, make_tag(1, mode, kind_lg));   // generation 1: "a decision exists"
 }
 
-// The decision after chunk j of an ordered stream, from its moving window mw (thread t
-// holds bin t; h is chunk j's own histogram, kept with the decision for snapshots):
-// degeneracy switch (Sec. III.C) and rule P (Sec. III.B), written to decision slot j.
-__device__ __forceinline__ void decide_and_publish(const Params &P, Ctl &c, uint64_t j, uint64_t mw, uint32_t h) {
+// Rule P (Sec. III.B) for a window mw of N bytes (thread t holds bin t; all threads call):
+// the pattern word for value t, and the table kind in *kind_lg.  When the budget S holds rmax
+// sub-bins for every value, rule P gives every value rmax whatever the window: the pattern
+// is the uniform table v * rmax and no block-wide pass is needed.
+__device__ __forceinline__ uint32_t decide_pattern(const Params &P, Ctl &c, uint64_t mw, uint64_t N,
+                                                   uint32_t *kind_lg) {
   const uint32_t t = threadIdx.x;
-  // degeneracy of the window: AHist iff some bin exceeds theta percent (strict)
-  uint64_t N, mx;
-  block_sum_max_u64(mw, c, &N, &mx);
-  const uint32_t mode = (100ull * mx > (uint64_t)P.theta * N) ? HIST_MODE_AHIST : HIST_MODE_WAVEHIST;
-  uint32_t word, kind_lg;
   if (256u * P.rmax <= P.S) {
-    // the budget holds rmax sub-bins for every value: rule P's first case, whatever the
-    // window; the pattern is the uniform table v * rmax (no block-wide passes needed)
     const uint32_t lg = (uint32_t)__builtin_ctz(P.rmax);
-    word = (t << lg) | (lg << 16);
-    kind_lg = ((uint32_t)KIND_UNIFORM << 8) | lg;
-  } else {
-    word = rule_p_word(mw, N, P.S, P.rmax, c);
-    kind_lg = pattern_kind_lg(word, c);
+    *kind_lg = ((uint32_t)KIND_UNIFORM << 8) | lg;
+    return (t << lg) | (lg << 16);
   }
-  Decision *d = &P.slots[j % P.nslot];
-  // The chunk that runs with this decision (j + 1 + lag) reads the pattern words only for a
-  // lookup table or for its trace.  Otherwise the tag alone carries the decision, and it is
-  // published at once instead of after the other stores are acknowledged: that shortens the
-  // path from this chunk's last tile to the chunks that wait for it.
+  const uint32_t word = rule_p_word(mw, N, P.S, P.rmax, c);
+  *kind_lg = pattern_kind_lg(word, c);
+  return word;
+}
+
+// Publish the decision made after chunk j into slot d (all threads call).  The chunk that
+// runs with it (j + 1 + lag) reads the pattern words only for a lookup table or for its
+// trace; otherwise the tag alone carries the decision and is stored at once, with nothing to
+// wait for.  When the words are needed they are stored and acknowledged before the tag.
+__device__ __forceinline__ void publish_decision(const Params &P, Decision *d, uint64_t j, uint32_t mode,
+                                                 uint32_t kind_lg, uint32_t word) {
+  const uint32_t t = threadIdx.x;
   const uint64_t tag = make_tag(j + 1, mode, kind_lg);
   const bool words_needed = (kind_lg >> 8) == KIND_LOOKUP || j + 1 + P.lag < P.trace_cap;
-  if (!words_needed && t == 0) st_agent(&d->tag, tag);
+  if (!words_needed) {
+    if (t == 0) st_agent(&d->tag, tag);
+    return;
+  }
   st_agent(&d->words[t], word);
-  st_agent(&d->hist[t], h);
   if (t == 0) {
     st_agent(&d->S, P.S);
     st_agent(&d->rmax, P.rmax);
   }
-  if (words_needed) {
-    order_global();
-    __syncthreads();
-    if (t == 0) st_agent(&d->tag, tag);
-  }
+  order_global();
+  __syncthreads();
+  if (t == 0) st_agent(&d->tag, tag);
 }
 
 // Sequencing of a stream with a moving window of W > 1 chunks.  MW_j needs the chunks in
 // order, but chunks finish in any order; rather than have each chunk's finalizer wait for the
-// one before it, every finalizer leaves its histogram in the ring and tries (one CAS) to
-// become the stream's sequencer.  The sequencer keeps the window in registers and takes the
-// chunks in order for as long as the next one's histogram is there: MW += h_j - h_{j-W},
-// then the decision after chunk j.  Before it leaves it stores the window, releases the lock
-// and looks once more, so a histogram that arrived while it held the lock is never left
-// behind (its own finalizer's CAS failed only while the lock was held).  Nothing waits.
+// one before it, every finalizer leaves its histogram (and size) in the ring and tries (one
+// CAS) to become the stream's sequencer.  The sequencer keeps the window and its byte count in
+// registers and takes the chunks in order for as long as the next one's histogram is there:
+// MW += h_j - h_{j-W}, N += n_j - n_{j-W}, then the decision after chunk j.  Before it leaves
+// it stores the window, releases the lock and looks once more, so a histogram that arrived
+// while it held the lock is never left behind (its own finalizer's CAS failed only while the
+// lock was held).  Nothing waits.
+//
+// The sequencer works in batches of kSeqBatch chunks, one memory round trip each: the ring
+// entries of chunks j .. j + kSeqBatch - 1 (and of the chunks leaving the window) are loaded together;
+// every entry carries its chunk's generation, so each wavefront finds with one ballot per
+// chunk which of them are there, and which windows have a bin above theta percent of their
+// bytes (Sec. III.C); the four wavefronts' results meet in LDS behind one barrier.  The
+// chunks that are there, in order from j, are then decided and published.  An entry of a
+// chunk leaving the window that is itself in the batch may not have been loaded yet; the
+// chunk that needs it then counts as absent and is taken by the next batch.
+constexpr uint32_t kSeqBatch = 6;   // as many as fit beside the tile loop's registers (occupancy 4)
+
+__device__ __forceinline__ uint64_t lane_u64(uint64_t v, uint32_t lane) {
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, lane);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), lane);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ void sequence_stream(const Params &P, Ctl &c, StreamDev *st) {
-  const uint32_t t = threadIdx.x;
-  const uint32_t W = P.W, R = P.R;
+  const uint32_t t = threadIdx.x, lane = lane_id();
+  const uint32_t W = P.W, R = P.R, nslot = P.nslot;
+  const uint64_t *ring = st->ring;
+  const uint64_t *ring_n = st->ring_n;
+  Decision *slots = P.slots;
+  auto wrap = [R](uint32_t s, uint32_t d) -> uint32_t { return s + d >= R ? s + d - R : s + d; };
+  uint32_t par = 0;
   for (;;) {
     if (t == 0) c.flag = (atomicCAS(&st->seq_lock, 0u, 1u) == 0u) ? 1u : 0u;
     __syncthreads();
     const bool holder = c.flag != 0;
     __syncthreads();
     if (!holder) return;
-    if (t == 0) c.seqj = ld_agent(&st->done);
-    __syncthreads();
-    uint64_t j = c.seqj;
+    // the previous holder stored these before it released the lock
+    uint64_t j = ld_agent(&st->done);
+    uint64_t N = ld_agent(&st->win_n);
     uint64_t mw = ld_agent(&st->mw[t]);
-    // Each ring entry carries its chunk's generation, so entries can be loaded ahead and
-    // checked when they are used: four chunks' entries are in flight while a decision is
-    // made (four register sets, rotated by unrolling so none is indexed at run time).
-    auto load = [&](uint64_t q, uint64_t &e, uint64_t &eo) {
-      e = ld_agent(&st->ring[(q % R) * 256u + t]);
-      eo = q >= W ? ld_agent(&st->ring[((q - W) % R) * 256u + t]) : 0u;
-    };
-    // takes chunk j from (e, eo) if it is there, then loads chunk j + 4 into (e, eo)
-    auto step = [&](uint64_t &e, uint64_t &eo) -> bool {
-      if (!block_all((uint32_t)(e >> 32) == (uint32_t)(j + 1), c)) return false;
-      const uint32_t hj = (uint32_t)e;
-      mw += (uint64_t)hj - (uint64_t)(uint32_t)eo;
-      load(j + 4, e, eo);
-      decide_and_publish(P, c, j, mw, hj);
-      ++j;
-      return true;
-    };
-    uint64_t e0, o0, e1, o1, e2, o2, e3, o3;
-    load(j, e0, o0);
-    load(j + 1, e1, o1);
-    load(j + 2, e2, o2);
-    load(j + 3, e3, o3);
-    while (step(e0, o0) && step(e1, o1) && step(e2, o2) && step(e3, o3)) {
+    // ring slots of chunk j and of chunk j - W (meaningful once j >= W), decision slot of j
+    uint32_t sj = (uint32_t)(j % R);
+    uint32_t so = sj >= W ? sj - W : sj + R - W;
+    uint32_t dj = (uint32_t)(j % nslot);
+    for (;;) {
+      // one round trip: this thread's bins of chunks j + b and j + b - W, and in lane b the
+      // sizes of those two chunks
+      uint64_t e[kSeqBatch], eo[kSeqBatch];
+#pragma unroll
+      for (uint32_t b = 0; b < kSeqBatch; ++b) {
+        e[b] = ld_agent(&ring[(size_t)wrap(sj, b) * 256u + t]);
+        eo[b] = ld_agent(&ring[(size_t)wrap(so, b) * 256u + t]);
+      }
+      const uint32_t bl = lane < kSeqBatch ? lane : 0u;
+      const uint64_t nv = ld_agent(&ring_n[wrap(sj, bl)]);
+      const uint64_t nov = ld_agent(&ring_n[wrap(so, bl)]);
+      uint32_t bad = 0, hot = 0;
+      uint64_t m = mw, NN = N;
+#pragma unroll
+      for (uint32_t b = 0; b < kSeqBatch; ++b) {
+        const uint64_t q = j + b;
+        const uint32_t g = (uint32_t)(q + 1), go = (uint32_t)(q + 1 - W);
+        const bool old = q >= W;
+        const uint64_t n = lane_u64(nv, b), no = lane_u64(nov, b);
+        bool ok = (uint32_t)(e[b] >> 32) == g && (uint32_t)(n >> kSizeBits) == (g & kSizeGenMask);
+        if (old)
+          ok = ok && (uint32_t)(eo[b] >> 32) == go && (uint32_t)(no >> kSizeBits) == (go & kSizeGenMask);
+        m += (uint64_t)(uint32_t)e[b] - (old ? (uint64_t)(uint32_t)eo[b] : 0u);
+        NN += (n & kSizeMask) - (old ? (no & kSizeMask) : 0u);
+        if (__ballot(!ok) != 0) bad |= 1u << b;
+        if (__ballot(100ull * m > (uint64_t)P.theta * NN) != 0) hot |= 1u << b;
+      }
+      uint32_t *f = c.sflag[par];
+      par ^= 1u;
+      if (lane == 0) f[wave_id()] = bad | (hot << 16);
+      __syncthreads();
+      uint32_t fl = 0;
+#pragma unroll
+      for (uint32_t w = 0; w < kWaves; ++w) fl |= f[w];
+      // chunks j .. j + cnt - 1 are there (all four wavefronts saw every entry)
+      const uint32_t cnt = (uint32_t)__builtin_ctz((fl & 0xFFFFu) | (1u << kSeqBatch));
+#pragma unroll
+      for (uint32_t b = 0; b < kSeqBatch; ++b) {
+        if (b >= cnt) break;
+        const uint64_t q = j + b;
+        const bool old = q >= W;
+        mw += (uint64_t)(uint32_t)e[b] - (old ? (uint64_t)(uint32_t)eo[b] : 0u);
+        N += (lane_u64(nv, b) & kSizeMask) - (old ? (lane_u64(nov, b) & kSizeMask) : 0u);
+        uint32_t kind_lg;
+        const uint32_t word = decide_pattern(P, c, mw, N, &kind_lg);
+        const uint32_t mode = (fl >> (16 + b)) & 1u ? HIST_MODE_AHIST : HIST_MODE_WAVEHIST;
+        const uint32_t d = dj + b >= nslot ? dj + b - nslot : dj + b;
+        publish_decision(P, &slots[d], q, mode, kind_lg, word);
+      }
+      j += cnt;
+      sj = wrap(sj, cnt);
+      so = wrap(so, cnt);
+      dj = dj + cnt >= nslot ? dj + cnt - nslot : dj + cnt;
+      if (cnt < kSeqBatch) break;
     }
     st_agent(&st->mw[t], mw);
-    if (t == 0) st_agent(&st->done, j);
+    if (t == 0) {
+      st_agent(&st->done, j);
+      st_agent(&st->win_n, N);
+    }
     order_global();
     __syncthreads();
     if (t == 0) st_agent(&st->seq_lock, 0u);
     order_global();
-    // look once more: a histogram that arrived while the lock was held
-    const uint64_t e = ld_agent(&st->ring[(j % R) * 256u + t]);
-    if (!block_all((uint32_t)(e >> 32) == (uint32_t)(j + 1), c)) return;
+    // look once more: a chunk that arrived while the lock was held
+    const uint64_t e = ld_agent(&ring[(size_t)sj * 256u + t]);
+    const uint64_t n = ld_agent(&ring_n[sj]);
+    const uint32_t g = (uint32_t)(j + 1);
+    if (!block_all((uint32_t)(e >> 32) == g && (uint32_t)(n >> kSizeBits) == (g & kSizeGenMask), c)) return;
   }
 }
 
-// Stream epilogue for chunk k with histogram h (thread t holds bin t): Accumulator, the trace
-// of what chunk k ran with, then the moving window, degeneracy switch and rule P (Sec. III.B,
-// Sec. III.C).  With a window of one chunk (W = 1) the decision after chunk k depends on h_k
-// alone, so epilogues of different chunks run independently; with W > 1 the chunks are
-// sequenced (see sequence_stream).
-__device__ __forceinline__ void stream_epilogue(const Params &P, Ctl &c, uint32_t sidx, int64_t k, uint32_t h) {
+// Stream epilogue for chunk k of `bytes` bytes with histogram h (thread t holds bin t):
+// Accumulator, the trace of what chunk k ran with, then the moving window, degeneracy switch
+// and rule P (Sec. III.B, Sec. III.C).  With a window of one chunk (W = 1) the decision after
+// chunk k depends on h_k alone, so epilogues of different chunks run independently; with
+// W > 1 the chunks are sequenced (see sequence_stream).
+__device__ __forceinline__ void stream_epilogue(const Params &P, Ctl &c, uint32_t sidx, int64_t k, uint32_t h,
+                                                uint64_t bytes) {
   const uint32_t t = threadIdx.x;
   StreamDev *st = P.st + sidx;
-  atomicAdd(reinterpret_cast<unsigned long long *>(&st->acc[t]), (unsigned long long)h);
+  __hip_atomic_fetch_add(gmem(&st->acc[t]), (uint64_t)h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if ((uint64_t)k < P.trace_cap) {
     st_agent(&st->pat_trace[(size_t)k * 256u + t], c.words[t]);
-    if (t == 0) st->mode_trace[k] = (uint8_t)c.used_mode;
+    if (t == 0) *gmem(&st->mode_trace[k]) = (uint8_t)c.used_mode;
   }
   if (P.W == 1) {
-    decide_and_publish(P, c, (uint64_t)k, (uint64_t)h, h);
+    // degeneracy of the window (this chunk): AHist iff some bin exceeds theta percent (strict)
+    const bool hot = 100ull * h > (uint64_t)P.theta * bytes;
+    const uint32_t mode = block_all(!hot, c) ? HIST_MODE_WAVEHIST : HIST_MODE_AHIST;
+    uint32_t kind_lg;
+    const uint32_t word = decide_pattern(P, c, h, bytes, &kind_lg);
+    Decision *d = &P.slots[(uint64_t)k % P.nslot];
+    st_agent(&d->hist[t], h);
+    publish_decision(P, d, (uint64_t)k, mode, kind_lg, word);
     if (t == 0) __hip_atomic_fetch_add(&st->done, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return;
   }
   const uint32_t slot = (uint32_t)((uint64_t)k % P.R);
-  st_agent(&st->ring[slot * 256u + t], ((uint64_t)(uint32_t)(k + 1) << 32) | h);
+  st_agent(&st->ring[(size_t)slot * 256u + t], ((uint64_t)(uint32_t)(k + 1) << 32) | h);
+  if (t == 0) st_agent(&st->ring_n[slot], ((uint64_t)((uint32_t)(k + 1) & kSizeGenMask) << kSizeBits) | bytes);
   order_global();     // every entry is in before the CAS below (so a failing CAS means the
   __syncthreads();    // sequencer's last look will find them)
   sequence_stream(P, c, st);
@@ -861,9 +929,9 @@ __device__ __forceinline__ void finalize_segment(const Params &P, Ctl &c, uint32
       __builtin_amdgcn_s_sleep(2);
     }
     for (uint32_t q = 0; q < copies; ++q) st_agent(&part[(q << 8) | t], 0u);
-    if (sd.out) sd.out[t] = tot;
-    if (sd.acc) atomicAdd(reinterpret_cast<unsigned long long *>(&sd.acc[t]), (unsigned long long)tot);
-    if (sd.chunk >= 0) stream_epilogue(P, c, sd.stream_idx, (int64_t)P.chunk_base + sd.chunk, tot);
+    if (sd.out) *gmem(&sd.out[t]) = tot;
+    if (sd.acc) __hip_atomic_fetch_add(gmem(&sd.acc[t]), (uint64_t)tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (sd.chunk >= 0) stream_epilogue(P, c, sd.stream_idx, (int64_t)P.chunk_base + sd.chunk, tot, sd.size);
     else if (sd.chunk == kServerChunk) server_epilogue(P, c, sd.stream_idx, tot);
     if (t == 0) st_agent(&P.seg_done[s], 0u);
   }
