@@ -557,13 +557,18 @@ def main():
         # the same stream, sequential semantics (pattern for chunk k+1 from chunk k) and paper sizes
         # (the switch exercised: theta 45 sends peaked chunks to AHist and wide ones to the
         # per-wavefront kernel; one HIP stream: no overlap between consecutive launches)
-        for name, (l, th, s_, r_, nh) in {"stream_lag0_auto": (0, theta, S, rmax, 2),
-                                          "stream_theta45_lag0": (0, 45, S, rmax, 2),
-                                          "stream_theta45_lag%d" % lag: (lag, 45, S, rmax, 2),
-                                          "stream_paper960_theta45_lag0": (0, 45, 960, 8, 2),
-                                          "stream_paper960_theta45_lag%d" % lag: (lag, 45, 960, 8, 2),
-                                          "stream_lag%d_one_hip_stream" % lag: (lag, theta, S, rmax, 1)}.items():
-            st = hm.Stream(W=1, theta_pct=th, S=s_, rmax=r_, lag=l, trace_cap=0)
+        # (moving windows of W chunks: the chunks are sequenced in order on the device)
+        for name, (w_, l, th, s_, r_, nh) in {"stream_lag0_auto": (1, 0, theta, S, rmax, 2),
+                                              "stream_theta45_lag0": (1, 0, 45, S, rmax, 2),
+                                              "stream_theta45_lag%d" % lag: (1, lag, 45, S, rmax, 2),
+                                              "stream_paper960_theta45_lag0": (1, 0, 45, 960, 8, 2),
+                                              "stream_paper960_theta45_lag%d" % lag: (1, lag, 45, 960, 8, 2),
+                                              "stream_lag%d_one_hip_stream" % lag: (1, lag, theta, S, rmax, 1),
+                                              "stream_window_W32_lag%d" % lag: (32, lag, theta, S, rmax, 2),
+                                              "stream_window_W256_lag%d" % lag: (256, lag, theta, S, rmax, 2),
+                                              "stream_window_W32_theta45_paper960_lag%d" % lag:
+                                                  (32, lag, 45, 960, 8, 2)}.items():
+            st = hm.Stream(W=w_, theta_pct=th, S=s_, rmax=r_, lag=l, trace_cap=0)
             tms, _ = run_stream(st, 8, 3, per_launch_events=False, n_hip=nh)
             st.close()
             extras[name] = {"GB/s": round(nbytes * 8 / (tms * 1e-3) / 1e9, 1), "ms_per_step": round(tms / 8, 4)}

@@ -277,3 +277,73 @@ def test_xray_frame_stream(hm, frame_bytes, count):
         n_ahist = sum(1 for m in ref["modes"] if m == O.MODE_AHIST)
         if theta <= 4:   # narrow frames cross theta: both kernels run
             assert 0 < n_ahist < count, (theta, n_ahist)
+
+
+@pytest.mark.parametrize("W,S,rmax,theta,lag", [(5, 8192, 32, 0, 3), (6, 960, 8, 30, 1), (7, 8192, 32, 45, 0),
+                                                (12, 300, 64, 20, 4), (64, 2048, 16, 10, 7)])
+def test_window_sizes_around_sequencer_batch(hm, W, S, rmax, theta, lag):
+    # the device sequences W > 1 streams several chunks per round trip; windows shorter and
+    # longer than that batch (the chunk leaving the window inside or outside the batch), many
+    # small chunks that finish out of order, and only the first chunks traced (the rest are
+    # published by tag alone), over two HIP streams
+    chunks = mixed_chunks(900 + W, 300, 60_000)
+    ref = O.stream_reference(chunks, W=W, theta_pct=theta, S=S, rmax=rmax, lag=lag)
+    traced = 40
+    st = hm.Stream(W=W, theta_pct=theta, S=S, rmax=rmax, lag=lag, trace_cap=traced)
+    ds = [dev(c) if c.size else None for c in chunks]
+    outs = torch.full((len(chunks), 256), -1, dtype=torch.int32, device="cuda")
+    bufs = [(int(x.data_ptr()) if x is not None else 0, c.size) for x, c in zip(ds, chunks)]
+    torch.cuda.synchronize()
+    hs = [torch.cuda.Stream(), torch.cuda.Stream()]
+    k, call = 0, 0
+    while k < len(chunks):
+        n = min(len(chunks) - k, (17, 64, 3, 100)[call % 4])
+        st.push_many(bufs[k:k + n], d_out=outs[k:k + n], stream=hs[call & 1])
+        k += n
+        call += 1
+    snap, modes, pats = st.read(traced, stream=hs[0])
+    torch.cuda.synchronize()
+    tag = (W, S, rmax, theta, lag)
+    assert np.array_equal(outs.cpu().numpy().astype(np.int64) & 0xFFFFFFFF, ref["hists"].astype(np.int64)), tag
+    assert [int(x) for x in snap.acc] == ref["acc"], tag
+    assert [int(x) for x in snap.mw] == ref["mw"], tag
+    assert int(snap.chunks) == len(chunks)
+    assert [int(m) for m in modes] == ref["modes"][:traced], tag
+    assert [list(map(int, p)) for p in pats] == ref["patterns"][:traced], tag
+    assert int(snap.next_mode) == O.decide_mode(ref["mw"], theta)
+    assert snap.next_pattern.words() == O.rule_p(ref["mw"], S, rmax)
+    d = hm.diag()
+    assert d.invalid_patterns == 0 and d.wait_timeouts == 0 and d.merge_timeouts == 0
+    st.close()
+
+
+@pytest.mark.parametrize("W", [32, 256])
+def test_full_size_moving_window_overlapping(hm, W):
+    # the bench's moving-window streams: 66 x 4 MiB pushed three times over two HIP streams at
+    # lag 31, the first push traced
+    chunks = config2_like(4 << 20)
+    hists = [O.hist(c) for c in chunks] * 3
+    lag, S, rmax, theta = 31, 8192, 32, 0
+    ref = O.stream_reference(None, W=W, theta_pct=theta, S=S, rmax=rmax, lag=lag, hists=hists)
+    d = dev(np.concatenate(chunks))
+    base = int(d.data_ptr())
+    bufs = [(base + k * (4 << 20), 4 << 20) for k in range(len(chunks))]
+    outs = [torch.full((len(chunks), 256), -1, dtype=torch.int32, device="cuda") for _ in range(3)]
+    st = hm.Stream(W=W, theta_pct=theta, S=S, rmax=rmax, lag=lag, trace_cap=len(chunks))
+    torch.cuda.synchronize()
+    hs = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for r in range(3):
+        st.push_many(bufs, d_out=outs[r], stream=hs[r & 1])
+    snap, modes, pats = st.read(len(chunks), stream=hs[0])
+    torch.cuda.synchronize()
+    got = np.concatenate([o.cpu().numpy().astype(np.int64) & 0xFFFFFFFF for o in outs])
+    assert np.array_equal(got, ref["hists"].astype(np.int64))
+    assert [int(x) for x in snap.acc] == ref["acc"]
+    assert [int(x) for x in snap.mw] == ref["mw"]
+    assert [int(m) for m in modes] == ref["modes"][:len(chunks)]
+    assert [list(map(int, p)) for p in pats] == ref["patterns"][:len(chunks)]
+    assert int(snap.next_mode) == O.decide_mode(ref["mw"], theta)
+    assert snap.next_pattern.words() == O.rule_p(ref["mw"], S, rmax)
+    dg = hm.diag()
+    assert dg.invalid_patterns == 0 and dg.wait_timeouts == 0 and dg.merge_timeouts == 0
+    st.close()
