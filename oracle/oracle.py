@@ -30,6 +30,12 @@ Adaptive CUDA Streams", 2010):
 * ``is_degenerate`` -- the degeneracy criterion (Sec. III.C): switch to AHist
   when any bin of the last moving-window histogram exceeds the critical
   degeneracy (40-50 %); tested exactly in integers as 100*max > theta*sum.
+* ``change_alarm`` -- change detection (Sec. III.B: the moving window, the stream's
+  present, compared with the Accumulator, its general nature, to detect an attack or a
+  need to reprocess).  The paper fixes no measure; our reading: alarm when some value's
+  share of the window differs from its share of the Accumulator by more than alarm_pct
+  percentage points (strict), computed with exact fractions.  Pinned by hand-worked
+  examples, a closed form and invariants (tests/test_change_cpu.py).
 * ``stream_reference`` -- Accumulator and moving-window (MW) histograms of a
   chunked stream and the kernel/pattern decision carried from chunk to chunk
   (Sec. III.B, Sec. III.C), with a pipeline lag (Sec. III.B, Figure 2: the
@@ -283,12 +289,40 @@ def decide_mode(mw: Sequence[int], theta_pct: int) -> int:
 
 
 # ----------------------------------------------------------------------------
+# Change detection: the moving window against the Accumulator (Sec. III.B)
+# ----------------------------------------------------------------------------
+
+def share_departure(mw: Sequence[int], acc: Sequence[int]):
+    """Largest difference, over the 256 values, between a value's share of the window and its
+    share of the Accumulator, as an exact fraction (0 when either histogram is empty)."""
+    from fractions import Fraction
+    mw, acc = [int(x) for x in mw], [int(x) for x in acc]   # exact (numpy integers would wrap)
+    n_mw, n_acc = sum(mw), sum(acc)
+    if n_mw == 0 or n_acc == 0:
+        return Fraction(0)
+    return max(abs(Fraction(m, n_mw) - Fraction(a, n_acc)) for m, a in zip(mw, acc))
+
+
+def change_alarm(mw: Sequence[int], acc: Sequence[int], alarm_pct: int) -> bool:
+    """Our reading of the comparison the paper proposes (the window, the stream's present, set
+    against the Accumulator, its general nature, to detect an attack or a need to reprocess;
+    the paper fixes no measure): alarm iff some value's share of the window differs from its
+    share of the Accumulator by more than alarm_pct percentage points (strict).  Off when
+    alarm_pct is 0 or either histogram is empty."""
+    if alarm_pct == 0:
+        return False
+    from fractions import Fraction
+    return share_departure(mw, acc) > Fraction(alarm_pct, 100)
+
+
+# ----------------------------------------------------------------------------
 # Stream semantics (Sec. III.B: Accumulator and MW; Sec. III.C: switching)
 # ----------------------------------------------------------------------------
 
 def stream_reference(chunks: Sequence, W: int = 1, theta_pct: int = 45, S: int = 960,
                      rmax: int = 8, lag: int = 0, mode: int = MODE_AUTO,
-                     hists: Optional[Sequence[Sequence[int]]] = None) -> Dict[str, object]:
+                     hists: Optional[Sequence[Sequence[int]]] = None,
+                     alarm_pct: int = 0) -> Dict[str, object]:
     """Run a chunked stream through the adaptive scheme; return every per-chunk quantity.
 
     Chunk k gets histogram h_k.  After chunk k:
@@ -299,10 +333,12 @@ def stream_reference(chunks: Sequence, W: int = 1, theta_pct: int = 45, S: int =
     run the per-wavefront kernel with the identity pattern.  A forced mode
     (AHIST / WAVEHIST) replaces the decided kernel but not the pattern.
 
+    With alarm_pct > 0, A_k = change_alarm(MW_k, Acc_k, alarm_pct) after every chunk.
+
     `hists` may pass precomputed chunk histograms (from ``hist``) to skip recounting.
     Returns dict with keys: hists (uint64[k,256]), acc (int list), mw (int list,
     after the last chunk), modes (kernel used per chunk), patterns (pattern used
-    per chunk, 256 words each).
+    per chunk, 256 words each), alarms (0/1 per chunk).
     """
     if W < 1 or lag < 0:
         raise ValueError("need W >= 1 and lag >= 0")
@@ -313,6 +349,7 @@ def stream_reference(chunks: Sequence, W: int = 1, theta_pct: int = 45, S: int =
     modes: List[int] = []
     patterns: List[List[int]] = []
     mw = [0] * 256
+    alarms: List[int] = []
     for k in range(nchunk):
         j = k - 1 - lag
         if j >= 0:
@@ -325,10 +362,12 @@ def stream_reference(chunks: Sequence, W: int = 1, theta_pct: int = 45, S: int =
         lo = max(0, k - W + 1)
         mw = [sum(hs[i][b] for i in range(lo, k + 1)) for b in range(256)]
         decisions.append((decide_mode(mw, theta_pct), rule_p(mw, S, rmax)))
+        alarms.append(1 if change_alarm(mw, acc, alarm_pct) else 0)
     return {
         "hists": np.array(hs, dtype=np.uint64).reshape(nchunk, 256),
         "acc": acc,
         "mw": mw,
         "modes": modes,
         "patterns": patterns,
+        "alarms": alarms,
     }
