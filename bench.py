@@ -557,21 +557,29 @@ def main():
         # the same stream, sequential semantics (pattern for chunk k+1 from chunk k) and paper sizes
         # (the switch exercised: theta 45 sends peaked chunks to AHist and wide ones to the
         # per-wavefront kernel; one HIP stream: no overlap between consecutive launches)
-        # (moving windows of W chunks: the chunks are sequenced in order on the device)
-        for name, (w_, l, th, s_, r_, nh) in {"stream_lag0_auto": (1, 0, theta, S, rmax, 2),
-                                              "stream_theta45_lag0": (1, 0, 45, S, rmax, 2),
-                                              "stream_theta45_lag%d" % lag: (1, lag, 45, S, rmax, 2),
-                                              "stream_paper960_theta45_lag0": (1, 0, 45, 960, 8, 2),
-                                              "stream_paper960_theta45_lag%d" % lag: (1, lag, 45, 960, 8, 2),
-                                              "stream_lag%d_one_hip_stream" % lag: (1, lag, theta, S, rmax, 1),
-                                              "stream_window_W32_lag%d" % lag: (32, lag, theta, S, rmax, 2),
-                                              "stream_window_W256_lag%d" % lag: (256, lag, theta, S, rmax, 2),
-                                              "stream_window_W32_theta45_paper960_lag%d" % lag:
-                                                  (32, lag, 45, 960, 8, 2)}.items():
-            st = hm.Stream(W=w_, theta_pct=th, S=s_, rmax=r_, lag=l, trace_cap=0)
+        # (moving windows of W chunks: the chunks are sequenced in order on the device; with
+        # change detection on, the window is also compared with the Accumulator after every chunk)
+        for name, (w_, l, th, s_, r_, nh, al) in {
+                "stream_lag0_auto": (1, 0, theta, S, rmax, 2, 0),
+                "stream_theta45_lag0": (1, 0, 45, S, rmax, 2, 0),
+                "stream_theta45_lag%d" % lag: (1, lag, 45, S, rmax, 2, 0),
+                "stream_paper960_theta45_lag0": (1, 0, 45, 960, 8, 2, 0),
+                "stream_paper960_theta45_lag%d" % lag: (1, lag, 45, 960, 8, 2, 0),
+                "stream_lag%d_one_hip_stream" % lag: (1, lag, theta, S, rmax, 1, 0),
+                "stream_window_W32_lag%d" % lag: (32, lag, theta, S, rmax, 2, 0),
+                "stream_window_W256_lag%d" % lag: (256, lag, theta, S, rmax, 2, 0),
+                "stream_window_W32_theta45_paper960_lag%d" % lag: (32, lag, 45, 960, 8, 2, 0),
+                "stream_window_W32_alarm4_lag%d" % lag: (32, lag, theta, S, rmax, 2, 4),
+                "stream_alarm4_W1_lag%d" % lag: (1, lag, theta, S, rmax, 2, 4)}.items():
+            st = hm.Stream(W=w_, theta_pct=th, S=s_, rmax=r_, lag=l, trace_cap=0, alarm_pct=al)
             tms, _ = run_stream(st, 8, 3, per_launch_events=False, n_hip=nh)
+            row = {"GB/s": round(nbytes * 8 / (tms * 1e-3) / 1e9, 1), "ms_per_step": round(tms / 8, 4)}
+            if al:
+                snap, _, _ = st.read(0)
+                row["chunks"] = int(snap.chunks)
+                row["alarms"] = int(snap.alarms)
             st.close()
-            extras[name] = {"GB/s": round(nbytes * 8 / (tms * 1e-3) / 1e9, 1), "ms_per_step": round(tms / 8, 4)}
+            extras[name] = row
         # one 1 MiB image (config 1): latency of one call, back to back
         x = torch.from_numpy(G.image_1mib()).to(dev)
         o1 = torch.zeros(256, dtype=torch.int32, device=dev)

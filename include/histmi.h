@@ -151,7 +151,8 @@ typedef struct {
     uint32_t S;          /* sub-histogram budget for rule P, 256..HIST_S_MAX */
     uint32_t rmax;       /* most sub-bins per value, power of two <= HIST_RMAX_MAX */
     uint32_t lag;        /* chunk k runs with the decision made after chunk k-1-lag (0 = sequential) */
-    uint32_t trace_cap;  /* chunks whose (mode, pattern) are recorded for hist_stream_read */
+    uint32_t trace_cap;  /* chunks whose (mode, pattern, alarm) are recorded for hist_stream_read */
+    uint32_t alarm_pct;  /* change detection (see below): 0 = off, else 1..100 percentage points */
 } hist_stream_config_t;
 
 /*
@@ -161,6 +162,15 @@ typedef struct {
  * Chunk k runs with D_{k-1-lag}; chunks with k-1-lag < 0 run WAVEHIST with the identity
  * pattern.  A forced mode in push replaces the decided kernel but not the pattern.  All
  * state lives on the device; no host round trip happens between chunks.
+ *
+ * Change detection (Sec. III.B proposes comparing the moving window, the stream's present,
+ * with the Accumulator, its general nature, to detect an attack or a need to reprocess; the
+ * measure is this library's reading): with alarm_pct > 0 the device raises an alarm after
+ * chunk k iff some value v's share of MW differs from its share of Acc by more than
+ * alarm_pct percentage points, i.e. 100 * |MW(v) * sum Acc - Acc(v) * sum MW| >
+ * alarm_pct * sum MW * sum Acc (exact integers; never with an empty MW or Acc; exact while
+ * the Accumulator holds fewer than 2^60 bytes).  A stream with alarms on is sequenced in
+ * chunk order on the device (as every stream with W > 1 is).
  *
  * Pushes of one stream must be issued from one host thread at a time, in chunk order, but
  * may go to different HIP streams: a chunk waits on the device for the decision it runs
@@ -186,6 +196,9 @@ typedef struct {
     uint64_t mw[256];      /* moving window after the last chunk */
     uint32_t next_mode;    /* decided kernel after the last chunk (HIST_MODE_AHIST / WAVEHIST) */
     hist_pattern_t next_pattern;  /* rule P of the current moving window */
+    uint64_t alarms;       /* change detection: chunks after which an alarm was raised */
+    uint64_t first_alarm;  /* index + 1 of the first such chunk, 0 if none */
+    uint64_t last_alarm;   /* index + 1 of the last such chunk, 0 if none */
 } hist_stream_snapshot_t;
 
 /* Synchronous: waits for `stream` and for this stream's launches on any HIP stream, then
@@ -194,6 +207,12 @@ typedef struct {
  * words chunk k ran with (k < trace_cap). */
 hist_status_t hist_stream_read(hist_stream_t *st, hist_stream_snapshot_t *snap, uint8_t *h_mode_trace,
                                uint32_t *h_pattern_trace, uint32_t trace_len, void *stream);
+
+/* Change detection trace (Sec. III.B).  Synchronous like hist_stream_read.  h_alarm_trace:
+ * HOST uint8[trace_len]; entry k is 1 iff an alarm was raised after chunk k (k < trace_cap;
+ * entries of chunks not yet pushed are 0).  HIST_EINVAL if the stream has alarms off or
+ * h_alarm_trace is NULL with trace_len > 0. */
+hist_status_t hist_stream_read_alarms(hist_stream_t *st, uint8_t *h_alarm_trace, uint32_t trace_len, void *stream);
 
 /* Synchronous; waits for the device before freeing. */
 hist_status_t hist_stream_destroy(hist_stream_t *st);

@@ -58,7 +58,8 @@ class DeviceInfo(ctypes.Structure):
 
 class StreamConfig(ctypes.Structure):
     _fields_ = [("W", ctypes.c_uint32), ("theta_pct", ctypes.c_uint32), ("S", ctypes.c_uint32),
-                ("rmax", ctypes.c_uint32), ("lag", ctypes.c_uint32), ("trace_cap", ctypes.c_uint32)]
+                ("rmax", ctypes.c_uint32), ("lag", ctypes.c_uint32), ("trace_cap", ctypes.c_uint32),
+                ("alarm_pct", ctypes.c_uint32)]
 
 
 class IngestConfig(ctypes.Structure):
@@ -67,7 +68,8 @@ class IngestConfig(ctypes.Structure):
 
 class StreamSnapshot(ctypes.Structure):
     _fields_ = [("chunks", ctypes.c_uint64), ("acc", ctypes.c_uint64 * 256), ("mw", ctypes.c_uint64 * 256),
-                ("next_mode", ctypes.c_uint32), ("next_pattern", Pattern)]
+                ("next_mode", ctypes.c_uint32), ("next_pattern", Pattern), ("alarms", ctypes.c_uint64),
+                ("first_alarm", ctypes.c_uint64), ("last_alarm", ctypes.c_uint64)]
 
 
 class Diag(ctypes.Structure):
@@ -112,6 +114,7 @@ _SIGS = [
     ("hist_stream_push", ctypes.c_int, [_VP, _VP, ctypes.c_size_t, ctypes.c_int, _VP, _VP]),
     ("hist_stream_push_many", ctypes.c_int, [_VP, ctypes.POINTER(_VP), c_u64p, ctypes.c_uint32, ctypes.c_int, _VP, _VP]),
     ("hist_stream_read", ctypes.c_int, [_VP, ctypes.POINTER(StreamSnapshot), c_u8p, c_u32p, ctypes.c_uint32, _VP]),
+    ("hist_stream_read_alarms", ctypes.c_int, [_VP, c_u8p, ctypes.c_uint32, _VP]),
     ("hist_stream_destroy", ctypes.c_int, [_VP]),
     ("hist_batch", ctypes.c_int, [ctypes.POINTER(_VP), c_u64p, ctypes.c_uint32, _VP, ctypes.c_int,
                                   ctypes.POINTER(Pattern), _VP]),
@@ -312,8 +315,8 @@ class Stream:
     """A device-resident histogram stream (Accumulator, moving window, adaptive kernel switch)."""
 
     def __init__(self, W: int = 1, theta_pct: int = 45, S: int = 960, rmax: int = 8, lag: int = 0,
-                 trace_cap: int = 1024):
-        cfg = StreamConfig(W, theta_pct, S, rmax, lag, trace_cap)
+                 trace_cap: int = 1024, alarm_pct: int = 0):
+        cfg = StreamConfig(W, theta_pct, S, rmax, lag, trace_cap, alarm_pct)
         self.cfg = cfg
         self._h = ctypes.c_void_p()
         _check(load().hist_stream_create(ctypes.byref(self._h), ctypes.byref(cfg)), "hist_stream_create")
@@ -336,6 +339,13 @@ class Stream:
                                        pats.ctypes.data_as(c_u32p), int(trace_len), _stream(stream)),
                "hist_stream_read")
         return snap, modes[:trace_len], pats[:trace_len]
+
+    def read_alarms(self, trace_len: int, stream=None) -> np.ndarray:
+        """Change detection trace: entry k is 1 iff an alarm was raised after chunk k."""
+        out = np.zeros(max(trace_len, 1), dtype=np.uint8)
+        _check(load().hist_stream_read_alarms(self._h, out.ctypes.data_as(c_u8p), int(trace_len), _stream(stream)),
+               "hist_stream_read_alarms")
+        return out[:trace_len]
 
     def close(self):
         if self._h:

@@ -390,18 +390,18 @@ hist_status_t run_multi(DevCtx *d, Params &P, const MultiPlan &mp, uint32_t copi
 }
 
 hist_status_t stream_state_alloc(uint32_t count, uint32_t W, uint32_t theta, uint32_t S, uint32_t rmax, uint32_t lag,
-                                 uint32_t nslot, uint32_t trace_cap, StreamAlloc *sa) {
+                                 uint32_t nslot, uint32_t trace_cap, uint32_t alarm_pct, StreamAlloc *sa) {
   const size_t tc = std::max<uint32_t>(trace_cap, 1);
-  // W > 1: chunks are sequenced in order (moving window) from a ring of recent histograms.
+  // W > 1 or alarms on: chunks are sequenced in order from a ring of recent histograms.
   // Chunk j's histogram is needed until chunk j + W is sequenced; the chunk that reuses its
   // slot (j + R) is counted only after its decision, made when chunk j + R - 1 - lag was
   // sequenced, so R >= W + lag + 1 suffices (plus a margin).
-  const uint32_t R = W > 1 ? W + lag + 66 : 1;
+  const uint32_t R = (W > 1 || alarm_pct > 0) ? W + lag + 66 : 1;
   sa->R = R;
   bool ok = hipMalloc(&sa->d_st, (size_t)count * sizeof(StreamDev)) == hipSuccess &&
             hipMalloc(&sa->d_ring, (size_t)count * R * 257 * 8) == hipSuccess &&
             hipMalloc(&sa->d_slots, (size_t)count * nslot * sizeof(Decision)) == hipSuccess &&
-            hipMalloc(&sa->d_mode_trace, (size_t)count * tc) == hipSuccess &&
+            hipMalloc(&sa->d_mode_trace, (size_t)count * tc * 2) == hipSuccess &&
             hipMalloc(&sa->d_pat_trace, (size_t)count * tc * 256 * 4) == hipSuccess;
   if (!ok) {
     stream_state_free(sa);
@@ -420,16 +420,18 @@ hist_status_t stream_state_alloc(uint32_t count, uint32_t W, uint32_t theta, uin
     x.trace_cap = trace_cap;
     x.lookup_rr = rmax > 32 ? 64 : 32;
     x.R = R;
+    x.alarm_pct = alarm_pct;
     x.ring = sa->d_ring + (size_t)i * R * 256;
     x.ring_n = sa->d_ring + (size_t)count * R * 256 + (size_t)i * R;
     x.slots = sa->d_slots + (size_t)i * nslot;
     x.mode_trace = sa->d_mode_trace + (size_t)i * tc;
+    x.alarm_trace = sa->d_mode_trace + (size_t)count * tc + (size_t)i * tc;
     x.pat_trace = sa->d_pat_trace + (size_t)i * tc * 256;
   }
   ok = hipMemcpy(sa->d_st, h.data(), (size_t)count * sizeof(StreamDev), hipMemcpyHostToDevice) == hipSuccess &&
        hipMemset(sa->d_ring, 0, (size_t)count * R * 257 * 8) == hipSuccess &&
        hipMemset(sa->d_slots, 0, (size_t)count * nslot * sizeof(Decision)) == hipSuccess &&
-       hipMemset(sa->d_mode_trace, 0, (size_t)count * tc) == hipSuccess &&
+       hipMemset(sa->d_mode_trace, 0, (size_t)count * tc * 2) == hipSuccess &&
        hipMemset(sa->d_pat_trace, 0, (size_t)count * tc * 256 * 4) == hipSuccess;
   if (!ok) {
     stream_state_free(sa);
@@ -702,7 +704,7 @@ hist_status_t hist_stream_create(hist_stream_t **out, const hist_stream_config_t
   if (!out || !cfg) return HIST_EINVAL;
   const hist_stream_config_t c = *cfg;
   if (c.W < 1 || c.W > (1u << 16) || c.theta_pct > 100 || c.S < 256 || c.S > HIST_S_MAX || !is_pow2(c.rmax) ||
-      c.rmax > HIST_RMAX_MAX || c.lag > 4096 || c.trace_cap > (1u << 22))
+      c.rmax > HIST_RMAX_MAX || c.lag > 4096 || c.trace_cap > (1u << 22) || c.alarm_pct > 100)
     return HIST_EINVAL;
   DevCtx *d;
   TRY(get_dev(&d));
@@ -712,7 +714,8 @@ hist_status_t hist_stream_create(hist_stream_t **out, const hist_stream_config_t
   // in flight span at most 2 * kMaxChunksPerLaunch chunks, plus the lag + 1 decisions made
   // before them
   st->nslot = c.lag + 2 + 2 * kMaxChunksPerLaunch;
-  hist_status_t r = stream_state_alloc(1, c.W, c.theta_pct, c.S, c.rmax, c.lag, st->nslot, c.trace_cap, &st->sa);
+  hist_status_t r =
+      stream_state_alloc(1, c.W, c.theta_pct, c.S, c.rmax, c.lag, st->nslot, c.trace_cap, c.alarm_pct, &st->sa);
   for (int i = 0; i < 2 && r == HIST_OK; ++i)
     if (hipEventCreateWithFlags(&st->ev[i], hipEventDisableTiming) != hipSuccess) r = HIST_EDEVICE;
   if (r != HIST_OK) {
@@ -735,6 +738,7 @@ static void stream_params(const hist_stream *st, Params *P) {
   P->lag = st->cfg.lag;
   P->nslot = st->nslot;
   P->W = st->cfg.W;
+  P->alarm_pct = st->cfg.alarm_pct;
   P->theta = st->cfg.theta_pct;
   P->S = st->cfg.S;
   P->rmax = st->cfg.rmax;
@@ -819,11 +823,15 @@ hist_status_t hist_stream_read(hist_stream_t *st, hist_stream_snapshot_t *snap, 
     snap->chunks = h.done;
     std::memcpy(snap->acc, h.acc, sizeof(snap->acc));
     std::memcpy(snap->mw, h.mw, sizeof(snap->mw));
+    snap->alarms = h.alarms;
+    snap->first_alarm = h.first_alarm;
+    snap->last_alarm = h.last_alarm;
+    const bool sequenced = st->cfg.W > 1 || st->cfg.alarm_pct > 0;
     if (h.done > 0) {
       Decision dec;
       TRY_HIP(hipMemcpy(&dec, st->sa.d_slots + (h.done - 1) % st->nslot, sizeof(dec), hipMemcpyDeviceToHost));
       snap->next_mode = tag_mode(dec.tag);
-      if (st->cfg.W == 1)
+      if (!sequenced)   // the window is the last chunk, kept with its decision
         for (int v = 0; v < 256; ++v) snap->mw[v] = dec.hist[v];
       const uint32_t kl = tag_kind_lg(dec.tag);
       if ((kl >> 8) == KIND_UNIFORM) {   // the words of a uniform pattern are not stored
@@ -843,6 +851,19 @@ hist_status_t hist_stream_read(hist_stream_t *st, hist_stream_snapshot_t *snap, 
   if (h_mode_trace && n) TRY_HIP(hipMemcpy(h_mode_trace, st->sa.d_mode_trace, n, hipMemcpyDeviceToHost));
   if (h_pattern_trace && n)
     TRY_HIP(hipMemcpy(h_pattern_trace, st->sa.d_pat_trace, (size_t)n * 256 * 4, hipMemcpyDeviceToHost));
+  return HIST_OK;
+}
+
+hist_status_t hist_stream_read_alarms(hist_stream_t *st, uint8_t *h_alarm_trace, uint32_t trace_len, void *stream) {
+  if (!st || st->cfg.alarm_pct == 0 || (!h_alarm_trace && trace_len > 0)) return HIST_EINVAL;
+  TRY_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+  for (int i = 0; i < 2; ++i)   // launches of this stream on other HIP streams
+    if (st->ev_used[i]) TRY_HIP(hipEventSynchronize(st->ev[i]));
+  const uint32_t n = std::min<uint32_t>(trace_len, st->cfg.trace_cap);
+  if (n)   // the alarm trace follows the mode trace (one stream, trace_cap entries each)
+    TRY_HIP(hipMemcpy(h_alarm_trace, st->sa.d_mode_trace + std::max<uint32_t>(st->cfg.trace_cap, 1), n,
+                      hipMemcpyDeviceToHost));
+  if (trace_len > n) std::memset(h_alarm_trace + n, 0, trace_len - n);
   return HIST_OK;
 }
 

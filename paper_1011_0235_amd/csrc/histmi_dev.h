@@ -51,17 +51,26 @@ constexpr uint32_t kSizeGenMask = 0xFFFFFFu;
 // Device-resident state of one stream (Accumulator, moving window, decisions, traces).
 struct StreamDev {
   uint32_t W, theta, S, rmax, lag, nslot, trace_cap, lookup_rr;
-  uint32_t R;            // sequenced streams (W > 1): histogram ring slots
+  uint32_t R;            // sequenced streams: histogram ring slots
   uint32_t seq_lock;     // sequenced streams: 1 while a workgroup sequences chunks
-  uint64_t done;         // W = 1: chunk epilogues completed (counted); W > 1: chunks sequenced
-  uint64_t win_n;        // W > 1: bytes in the moving window after the last sequenced chunk
+  uint32_t alarm_pct;    // change detection threshold (0 = off)
+  uint32_t pad;
+  // A stream is sequenced (its chunks taken in order by the device) when W > 1 or alarms
+  // are on; otherwise every chunk's epilogue decides on its own.
+  uint64_t done;         // unsequenced: chunk epilogues completed (counted); sequenced: chunks sequenced
+  uint64_t win_n;        // sequenced: bytes in the moving window after the last sequenced chunk
   uint64_t acc[256];     // Accumulator (every chunk's finalizer adds its histogram)
-  uint64_t mw[256];      // moving window after the last sequenced chunk (W > 1)
-  uint64_t *ring;        // [R][256] recent histograms (W > 1), chunk j in slot j % R, each
+  uint64_t mw[256];      // sequenced: moving window after the last sequenced chunk
+  // change detection (sequenced): the Accumulator in chunk order, its bytes, and the alarms
+  uint64_t sacc[256];
+  uint64_t sacc_n;
+  uint64_t alarms, first_alarm, last_alarm;   // count; chunk index + 1 (0 = none)
+  uint64_t *ring;        // [R][256] recent histograms (sequenced), chunk j in slot j % R, each
                          // entry (j + 1) << 32 | count: a load tells whether it is chunk j's
   uint64_t *ring_n;      // [R] the same chunks' sizes, (j + 1 mod 2^24) << 40 | bytes
   Decision *slots;       // [nslot]; decision made after chunk j lives in slot j % nslot
   uint8_t *mode_trace;   // [trace_cap]
+  uint8_t *alarm_trace;  // [trace_cap] 1 iff an alarm was raised after chunk k
   uint32_t *pat_trace;   // [trace_cap][256]
 };
 
@@ -122,7 +131,8 @@ struct Params {
   uint32_t theta;            // critical degeneracy, percent
   uint32_t S;                // sub-bin budget of rule P
   uint32_t rmax;             // sub-bin cap of rule P
-  uint32_t R;                // histogram ring slots (W > 1)
+  uint32_t R;                // histogram ring slots (sequenced streams)
+  uint32_t alarm_pct;        // change detection threshold (0 = off); sequenced when W > 1 or on
   uint64_t trace_cap;
   Decision *slots;           // the stream's decision ring
   // LDS layout (in 32-bit words)

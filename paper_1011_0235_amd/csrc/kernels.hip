@@ -56,6 +56,7 @@ struct Ctl {
   uint64_t seqj;           // the stream sequencer's next chunk
   uint64_t seqn;           // and the bytes in its window
   uint32_t sflag[2][kWaves];  // the sequencer's per-wavefront flags, by chunk parity
+  uint64_t alarms[3];      // the sequencer's change-detection count, first and last alarm
   // multi-segment launches, double-buffered so that one barrier per step suffices:
   SegDesc sd[2];           // the current segment's descriptor (and the next one's, being staged)
   TileRec nrec[2];         // the next tile's record, by tile parity
@@ -724,15 +725,45 @@ __device__ __forceinline__ void publish_decision(const Params &P, Decision *d, u
 // while it held the lock is never left behind (its own finalizer's CAS failed only while the
 // lock was held).  Nothing waits.
 //
-// The sequencer works in batches of kSeqBatch chunks, one memory round trip each: the ring
-// entries of chunks j .. j + kSeqBatch - 1 (and of the chunks leaving the window) are loaded together;
+// The sequencer works in batches of B chunks, one memory round trip each: the ring entries
+// of chunks j .. j + B - 1 (and of the chunks leaving the window) are loaded together;
 // every entry carries its chunk's generation, so each wavefront finds with one ballot per
 // chunk which of them are there, and which windows have a bin above theta percent of their
 // bytes (Sec. III.C); the four wavefronts' results meet in LDS behind one barrier.  The
 // chunks that are there, in order from j, are then decided and published.  An entry of a
 // chunk leaving the window that is itself in the batch may not have been loaded yet; the
 // chunk that needs it then counts as absent and is taken by the next batch.
-constexpr uint32_t kSeqBatch = 6;   // as many as fit beside the tile loop's registers (occupancy 4)
+// Batch sizes: as many chunks as fit beside the tile loop's registers (occupancy 4); change
+// detection's 128-bit arithmetic leaves room for fewer.
+constexpr uint32_t kSeqBatch = 6;
+constexpr uint32_t kSeqBatchAlarm = 3;
+static_assert(kSeqBatch <= 8 && kSeqBatchAlarm <= 8, "per-chunk flags: bits 0-7 absent, 16-23 over theta, 24-31 alarms");
+
+// Change detection for value t (Sec. III.B; the measure is our reading): its share of the
+// window departs from its share of the Accumulator by more than pct percentage points,
+// 100 * |mw * N_acc - acc * N_mw| > lim with lim = pct * N_mw * N_acc, in exact 128-bit
+// integers held as (hi, lo) 64-bit halves (never with an empty window or Accumulator; lim is
+// the same for every thread and computed once per chunk).
+struct U128 {
+  uint64_t hi, lo;
+};
+__device__ __forceinline__ U128 mul_64x64(uint64_t a, uint64_t b) { return {__umul64hi(a, b), a * b}; }
+__device__ __forceinline__ bool gt_128(U128 a, U128 b) { return a.hi > b.hi || (a.hi == b.hi && a.lo > b.lo); }
+__device__ __forceinline__ U128 sub_128(U128 a, U128 b) {
+  return {a.hi - b.hi - (a.lo < b.lo ? 1u : 0u), a.lo - b.lo};
+}
+// pct * nmw * nacc (nmw, nacc < 2^64, pct <= 100; exact while the product is below 2^128)
+__device__ __forceinline__ U128 alarm_limit(uint32_t pct, uint64_t nmw, uint64_t nacc) {
+  const U128 p = mul_64x64(nmw, nacc);
+  return {p.hi * pct + __umul64hi(p.lo, pct), p.lo * pct};
+}
+__device__ __forceinline__ bool share_departs(uint64_t mwv, uint64_t accv, uint64_t nmw, uint64_t nacc, U128 lim) {
+  if (nmw == 0 || nacc == 0) return false;
+  const U128 x = mul_64x64(mwv, nacc), y = mul_64x64(accv, nmw);
+  const U128 d = gt_128(x, y) ? sub_128(x, y) : sub_128(y, x);
+  const U128 d100 = {d.hi * 100u + __umul64hi(d.lo, 100u), d.lo * 100u};
+  return gt_128(d100, lim);
+}
 
 __device__ __forceinline__ uint64_t lane_u64(uint64_t v, uint32_t lane) {
   const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, lane);
@@ -740,11 +771,14 @@ __device__ __forceinline__ uint64_t lane_u64(uint64_t v, uint32_t lane) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+template <uint32_t B, bool ALARM>
 __device__ __forceinline__ void sequence_stream(const Params &P, Ctl &c, StreamDev *st) {
   const uint32_t t = threadIdx.x, lane = lane_id();
   const uint32_t W = P.W, R = P.R, nslot = P.nslot;
+  const uint32_t apct = P.alarm_pct;
   const uint64_t *ring = st->ring;
   const uint64_t *ring_n = st->ring_n;
+  uint8_t *alarm_trace = st->alarm_trace;
   Decision *slots = P.slots;
   auto wrap = [R](uint32_t s, uint32_t d) -> uint32_t { return s + d >= R ? s + d - R : s + d; };
   uint32_t par = 0;
@@ -754,30 +788,59 @@ __device__ __forceinline__ void sequence_stream(const Params &P, Ctl &c, StreamD
     const bool holder = c.flag != 0;
     __syncthreads();
     if (!holder) return;
-    // the previous holder stored these before it released the lock
-    uint64_t j = ld_agent(&st->done);
-    uint64_t N = ld_agent(&st->win_n);
+    // the previous holder stored these before it released the lock (values every thread
+    // shares are moved to scalar registers)
+    uint64_t j = lane_u64(ld_agent(&st->done), 0);
+    uint64_t N = lane_u64(ld_agent(&st->win_n), 0);
     uint64_t mw = ld_agent(&st->mw[t]);
+    // change detection: the Accumulator in chunk order and its bytes
+    uint64_t sacc = 0, NA = 0;
+    if (ALARM) {
+      sacc = ld_agent(&st->sacc[t]);
+      NA = lane_u64(ld_agent(&st->sacc_n), 0);
+      if (t == 0) {   // kept in LDS while the lock is held
+        c.alarms[0] = ld_agent(&st->alarms);
+        c.alarms[1] = ld_agent(&st->first_alarm);
+        c.alarms[2] = ld_agent(&st->last_alarm);
+      }
+    }
     // ring slots of chunk j and of chunk j - W (meaningful once j >= W), decision slot of j
     uint32_t sj = (uint32_t)(j % R);
     uint32_t so = sj >= W ? sj - W : sj + R - W;
     uint32_t dj = (uint32_t)(j % nslot);
+    // change detection: a batch's alarms (this wavefront's ballots) travel with the next
+    // batch's flags, so they cost no barrier of their own; thread 0 then records them
+    uint32_t pend = 0, pcnt = 0;
+    uint64_t pj = 0;
+    auto record = [&](uint32_t al, uint64_t j0, uint32_t n) {
+      if (t != 0) return;
+      for (uint32_t b = 0; b < n; ++b) {
+        const uint64_t q = j0 + b;
+        const uint32_t hit = (al >> b) & 1u;
+        if (hit) {
+          ++c.alarms[0];
+          if (c.alarms[1] == 0) c.alarms[1] = q + 1;
+          c.alarms[2] = q + 1;
+        }
+        if (q < P.trace_cap) *gmem(&alarm_trace[q]) = (uint8_t)hit;
+      }
+    };
     for (;;) {
       // one round trip: this thread's bins of chunks j + b and j + b - W, and in lane b the
       // sizes of those two chunks
-      uint64_t e[kSeqBatch], eo[kSeqBatch];
+      uint64_t e[B], eo[B];
 #pragma unroll
-      for (uint32_t b = 0; b < kSeqBatch; ++b) {
+      for (uint32_t b = 0; b < B; ++b) {
         e[b] = ld_agent(&ring[(size_t)wrap(sj, b) * 256u + t]);
         eo[b] = ld_agent(&ring[(size_t)wrap(so, b) * 256u + t]);
       }
-      const uint32_t bl = lane < kSeqBatch ? lane : 0u;
+      const uint32_t bl = lane < B ? lane : 0u;
       const uint64_t nv = ld_agent(&ring_n[wrap(sj, bl)]);
       const uint64_t nov = ld_agent(&ring_n[wrap(so, bl)]);
       uint32_t bad = 0, hot = 0;
       uint64_t m = mw, NN = N;
 #pragma unroll
-      for (uint32_t b = 0; b < kSeqBatch; ++b) {
+      for (uint32_t b = 0; b < B; ++b) {
         const uint64_t q = j + b;
         const uint32_t g = (uint32_t)(q + 1), go = (uint32_t)(q + 1 - W);
         const bool old = q >= W;
@@ -792,15 +855,17 @@ __device__ __forceinline__ void sequence_stream(const Params &P, Ctl &c, StreamD
       }
       uint32_t *f = c.sflag[par];
       par ^= 1u;
-      if (lane == 0) f[wave_id()] = bad | (hot << 16);
+      if (lane == 0) f[wave_id()] = bad | (hot << 16) | (ALARM ? pend << 24 : 0u);
       __syncthreads();
       uint32_t fl = 0;
 #pragma unroll
       for (uint32_t w = 0; w < kWaves; ++w) fl |= f[w];
+      if (ALARM && pcnt) record(fl >> 24, pj, pcnt);
       // chunks j .. j + cnt - 1 are there (all four wavefronts saw every entry)
-      const uint32_t cnt = (uint32_t)__builtin_ctz((fl & 0xFFFFu) | (1u << kSeqBatch));
+      const uint32_t cnt = (uint32_t)__builtin_ctz((fl & 0xFFu) | (1u << B));
+      uint32_t alarm = 0;
 #pragma unroll
-      for (uint32_t b = 0; b < kSeqBatch; ++b) {
+      for (uint32_t b = 0; b < B; ++b) {
         if (b >= cnt) break;
         const uint64_t q = j + b;
         const bool old = q >= W;
@@ -811,17 +876,45 @@ __device__ __forceinline__ void sequence_stream(const Params &P, Ctl &c, StreamD
         const uint32_t mode = (fl >> (16 + b)) & 1u ? HIST_MODE_AHIST : HIST_MODE_WAVEHIST;
         const uint32_t d = dj + b >= nslot ? dj + b - nslot : dj + b;
         publish_decision(P, &slots[d], q, mode, kind_lg, word);
+        if (ALARM) {
+          sacc += (uint32_t)e[b];
+          NA += lane_u64(nv, b) & kSizeMask;
+          if (__ballot(share_departs(mw, sacc, N, NA, alarm_limit(apct, N, NA))) != 0) alarm |= 1u << b;
+        }
       }
+      pend = alarm;
+      pcnt = cnt;
+      pj = j;
       j += cnt;
       sj = wrap(sj, cnt);
       so = wrap(so, cnt);
       dj = dj + cnt >= nslot ? dj + cnt - nslot : dj + cnt;
-      if (cnt < kSeqBatch) break;
+      if (cnt < B) break;
+    }
+    if (ALARM && pcnt) {
+      // the last batch's alarms
+      uint32_t *fa = c.sflag[par];
+      par ^= 1u;
+      if (lane == 0) fa[wave_id()] = pend;
+      __syncthreads();
+      uint32_t al = 0;
+#pragma unroll
+      for (uint32_t w = 0; w < kWaves; ++w) al |= fa[w];
+      record(al, pj, pcnt);
     }
     st_agent(&st->mw[t], mw);
     if (t == 0) {
       st_agent(&st->done, j);
       st_agent(&st->win_n, N);
+    }
+    if (ALARM) {
+      st_agent(&st->sacc[t], sacc);
+      if (t == 0) {
+        st_agent(&st->sacc_n, NA);
+        st_agent(&st->alarms, c.alarms[0]);
+        st_agent(&st->first_alarm, c.alarms[1]);
+        st_agent(&st->last_alarm, c.alarms[2]);
+      }
     }
     order_global();
     __syncthreads();
@@ -839,7 +932,8 @@ __device__ __forceinline__ void sequence_stream(const Params &P, Ctl &c, StreamD
 // Accumulator, the trace of what chunk k ran with, then the moving window, degeneracy switch
 // and rule P (Sec. III.B, Sec. III.C).  With a window of one chunk (W = 1) the decision after
 // chunk k depends on h_k alone, so epilogues of different chunks run independently; with
-// W > 1 the chunks are sequenced (see sequence_stream).
+// W > 1, or with change detection (which needs the Accumulator in chunk order), the chunks
+// are sequenced (see sequence_stream).
 __device__ __forceinline__ void stream_epilogue(const Params &P, Ctl &c, uint32_t sidx, int64_t k, uint32_t h,
                                                 uint64_t bytes) {
   const uint32_t t = threadIdx.x;
@@ -849,7 +943,7 @@ __device__ __forceinline__ void stream_epilogue(const Params &P, Ctl &c, uint32_
     st_agent(&st->pat_trace[(size_t)k * 256u + t], c.words[t]);
     if (t == 0) *gmem(&st->mode_trace[k]) = (uint8_t)c.used_mode;
   }
-  if (P.W == 1) {
+  if (P.W == 1 && P.alarm_pct == 0) {
     // degeneracy of the window (this chunk): AHist iff some bin exceeds theta percent (strict)
     const bool hot = 100ull * h > (uint64_t)P.theta * bytes;
     const uint32_t mode = block_all(!hot, c) ? HIST_MODE_WAVEHIST : HIST_MODE_AHIST;
@@ -866,7 +960,10 @@ __device__ __forceinline__ void stream_epilogue(const Params &P, Ctl &c, uint32_
   if (t == 0) st_agent(&st->ring_n[slot], ((uint64_t)((uint32_t)(k + 1) & kSizeGenMask) << kSizeBits) | bytes);
   order_global();     // every entry is in before the CAS below (so a failing CAS means the
   __syncthreads();    // sequencer's last look will find them)
-  sequence_stream(P, c, st);
+  if (P.alarm_pct)
+    sequence_stream<kSeqBatchAlarm, true>(P, c, st);
+  else
+    sequence_stream<kSeqBatch, false>(P, c, st);
 }
 
 // Merge of a segment.

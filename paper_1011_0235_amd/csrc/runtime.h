@@ -148,11 +148,11 @@ struct StreamAlloc {
   uint32_t R = 1;                 // histogram ring slots per stream
   uint64_t *d_ring = nullptr;
   Decision *d_slots = nullptr;
-  uint8_t *d_mode_trace = nullptr;
+  uint8_t *d_mode_trace = nullptr;    // [count][trace_cap] modes, then [count][trace_cap] alarms
   uint32_t *d_pat_trace = nullptr;
 };
 hist_status_t stream_state_alloc(uint32_t count, uint32_t W, uint32_t theta, uint32_t S, uint32_t rmax, uint32_t lag,
-                                 uint32_t nslot, uint32_t trace_cap, StreamAlloc *sa);
+                                 uint32_t nslot, uint32_t trace_cap, uint32_t alarm_pct, StreamAlloc *sa);
 void stream_state_free(StreamAlloc *sa);
 
 }  // namespace rt

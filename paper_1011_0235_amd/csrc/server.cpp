@@ -208,7 +208,7 @@ hist_status_t hist_server_create(hist_server_t **out, const hist_server_config_t
   sv->dev = d->dev;
   sv->d = d;
   std::memset(&sv->stats, 0, sizeof(sv->stats));
-  hist_status_t st = stream_state_alloc(c.n_stream_ids, 1, c.theta_pct, c.S, c.rmax, 0, 1, 0, &sv->sa);
+  hist_status_t st = stream_state_alloc(c.n_stream_ids, 1, c.theta_pct, c.S, c.rmax, 0, 1, 0, 0, &sv->sa);
   if (st != HIST_OK) {
     delete sv;
     return st;

@@ -111,8 +111,9 @@ def test_stream_and_server_config_errors(hm):
     h = ctypes.c_void_p()
     for cfg in (hm._lib.StreamConfig(0, 45, 960, 8, 0, 1), hm._lib.StreamConfig(1, 101, 960, 8, 0, 1),
                 hm._lib.StreamConfig(1, 45, 100, 8, 0, 1), hm._lib.StreamConfig(1, 45, 960, 6, 0, 1),
-                hm._lib.StreamConfig(1, 45, 20000, 8, 0, 1)):
+                hm._lib.StreamConfig(1, 45, 20000, 8, 0, 1), hm._lib.StreamConfig(32, 45, 960, 8, 0, 1, 101)):
         assert lib.hist_stream_create(ctypes.byref(h), ctypes.byref(cfg)) == hm.EINVAL
+    assert lib.hist_stream_read_alarms(None, None, 0, None) == hm.EINVAL
     for cfg in (hm._lib.ServerConfig(0, 4, 4, 1, 4, 0, 45, 960, 8), hm._lib.ServerConfig(1 << 20, 0, 4, 1, 4, 0, 45, 960, 8),
                 hm._lib.ServerConfig(1 << 20, 4, 4, 17, 4, 0, 45, 960, 8),
                 hm._lib.ServerConfig(1 << 20, 4, 4, 1, 4, 5, 45, 960, 8)):
