@@ -30,6 +30,11 @@ Adaptive CUDA Streams", 2010):
 * ``is_degenerate`` -- the degeneracy criterion (Sec. III.C): switch to AHist
   when any bin of the last moving-window histogram exceeds the critical
   degeneracy (40-50 %); tested exactly in integers as 100*max > theta*sum.
+* ``collision_index`` / ``collides`` -- an alternative switching criterion (the paper
+  leaves other criteria to future work and names one that measures the serialisation the
+  data would cause): the probability sum_v p_v^2 that two lanes add into the same bin,
+  compared with kappa.  Our reading; pinned by closed forms and invariants
+  (tests/test_criterion_cpu.py).
 * ``change_alarm`` -- change detection (Sec. III.B: the moving window, the stream's
   present, compared with the Accumulator, its general nature, to detect an attack or a
   need to reprocess).  The paper fixes no measure; our reading: alarm when some value's
@@ -283,9 +288,53 @@ def is_degenerate(mw: Sequence[int], theta_pct: int) -> bool:
     return 100 * max(mw) > int(theta_pct) * sum(mw)
 
 
-def decide_mode(mw: Sequence[int], theta_pct: int) -> int:
-    """AHist when the moving-window histogram is degenerate, the per-wavefront kernel otherwise."""
-    return MODE_AHIST if is_degenerate(mw, theta_pct) else MODE_WAVEHIST
+def decide_mode(mw: Sequence[int], theta_pct: int, criterion: int = 0, kappa_pct: int = 0) -> int:
+    """AHist when the moving-window histogram calls for it, the per-wavefront kernel otherwise.
+
+    criterion 0 (CRIT_MAXBIN): the paper's degeneracy test, some bin above theta percent.
+    criterion 1 (CRIT_COLLISION): the alternative criterion, the collision index above kappa.
+    criterion 2 (CRIT_BOTH): either (the paper suggests combining the two kinds of test)."""
+    deg = is_degenerate(mw, theta_pct)
+    if criterion == CRIT_MAXBIN:
+        ahist = deg
+    elif criterion == CRIT_COLLISION:
+        ahist = collides(mw, kappa_pct)
+    elif criterion == CRIT_BOTH:
+        ahist = deg or collides(mw, kappa_pct)
+    else:
+        raise ValueError("unknown criterion")
+    return MODE_AHIST if ahist else MODE_WAVEHIST
+
+
+# ----------------------------------------------------------------------------
+# An alternative switching criterion (Sec. IV: future work)
+# ----------------------------------------------------------------------------
+
+CRIT_MAXBIN = 0
+CRIT_COLLISION = 1
+CRIT_BOTH = 2
+
+
+def collision_index(mw: Sequence[int]):
+    """Probability that two bytes drawn independently from the window's distribution are equal,
+    sum_v p_v^2 with p_v = mw(v) / sum(mw), as an exact fraction (0 for an empty window).
+
+    The paper leaves other switching criteria to future work and names one that measures the
+    serialisation the data would cause.  The per-wavefront kernel serialises when lanes of a
+    wavefront add into the same bin at once; for bytes drawn from p, two given lanes do so with
+    probability sum_v p_v^2, so this index is our reading of that criterion."""
+    from fractions import Fraction
+    mw = [int(x) for x in mw]
+    n = sum(mw)
+    if n == 0:
+        return Fraction(0)
+    return Fraction(sum(x * x for x in mw), n * n)
+
+
+def collides(mw: Sequence[int], kappa_pct: int) -> bool:
+    """The alternative criterion: the collision index exceeds kappa percent (strict)."""
+    from fractions import Fraction
+    return collision_index(mw) > Fraction(int(kappa_pct), 100)
 
 
 # ----------------------------------------------------------------------------
@@ -322,7 +371,7 @@ def change_alarm(mw: Sequence[int], acc: Sequence[int], alarm_pct: int) -> bool:
 def stream_reference(chunks: Sequence, W: int = 1, theta_pct: int = 45, S: int = 960,
                      rmax: int = 8, lag: int = 0, mode: int = MODE_AUTO,
                      hists: Optional[Sequence[Sequence[int]]] = None,
-                     alarm_pct: int = 0) -> Dict[str, object]:
+                     alarm_pct: int = 0, criterion: int = CRIT_MAXBIN, kappa_pct: int = 0) -> Dict[str, object]:
     """Run a chunked stream through the adaptive scheme; return every per-chunk quantity.
 
     Chunk k gets histogram h_k.  After chunk k:
@@ -334,6 +383,7 @@ def stream_reference(chunks: Sequence, W: int = 1, theta_pct: int = 45, S: int =
     (AHIST / WAVEHIST) replaces the decided kernel but not the pattern.
 
     With alarm_pct > 0, A_k = change_alarm(MW_k, Acc_k, alarm_pct) after every chunk.
+    `criterion` / `kappa_pct` choose the switching test (see decide_mode).
 
     `hists` may pass precomputed chunk histograms (from ``hist``) to skip recounting.
     Returns dict with keys: hists (uint64[k,256]), acc (int list), mw (int list,
@@ -361,7 +411,7 @@ def stream_reference(chunks: Sequence, W: int = 1, theta_pct: int = 45, S: int =
         acc = [a + b for a, b in zip(acc, hs[k])]
         lo = max(0, k - W + 1)
         mw = [sum(hs[i][b] for i in range(lo, k + 1)) for b in range(256)]
-        decisions.append((decide_mode(mw, theta_pct), rule_p(mw, S, rmax)))
+        decisions.append((decide_mode(mw, theta_pct, criterion, kappa_pct), rule_p(mw, S, rmax)))
         alarms.append(1 if change_alarm(mw, acc, alarm_pct) else 0)
     return {
         "hists": np.array(hs, dtype=np.uint64).reshape(nchunk, 256),
