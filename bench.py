@@ -559,7 +559,8 @@ def main():
         # per-wavefront kernel; one HIP stream: no overlap between consecutive launches)
         # (moving windows of W chunks: the chunks are sequenced in order on the device; with
         # change detection on, the window is also compared with the Accumulator after every chunk)
-        for name, (w_, l, th, s_, r_, nh, al) in {
+        # (the collision criterion: entries with a kappa below use it instead of theta)
+        for name, (w_, l, th, s_, r_, nh, al, *crit) in {
                 "stream_lag0_auto": (1, 0, theta, S, rmax, 2, 0),
                 "stream_theta45_lag0": (1, 0, 45, S, rmax, 2, 0),
                 "stream_theta45_lag%d" % lag: (1, lag, 45, S, rmax, 2, 0),
@@ -570,8 +571,14 @@ def main():
                 "stream_window_W256_lag%d" % lag: (256, lag, theta, S, rmax, 2, 0),
                 "stream_window_W32_theta45_paper960_lag%d" % lag: (32, lag, 45, 960, 8, 2, 0),
                 "stream_window_W32_alarm4_lag%d" % lag: (32, lag, theta, S, rmax, 2, 4),
-                "stream_alarm4_W1_lag%d" % lag: (1, lag, theta, S, rmax, 2, 4)}.items():
-            st = hm.Stream(W=w_, theta_pct=th, S=s_, rmax=r_, lag=l, trace_cap=0, alarm_pct=al)
+                "stream_alarm4_W1_lag%d" % lag: (1, lag, theta, S, rmax, 2, 4),
+                "stream_collision10_W1_lag%d" % lag: (1, lag, 100, S, rmax, 2, 0, hm.CRIT_COLLISION, 10),
+                "stream_collision3_W32_lag%d" % lag: (32, lag, 100, S, rmax, 2, 0, hm.CRIT_COLLISION, 3),
+                "stream_collision3_W32_paper960_lag%d" % lag: (32, lag, 100, 960, 8, 2, 0, hm.CRIT_COLLISION, 3)
+                }.items():
+            cr, kp = (crit[0], crit[1]) if crit else (hm.CRIT_MAXBIN, 0)
+            st = hm.Stream(W=w_, theta_pct=th, S=s_, rmax=r_, lag=l, trace_cap=0, alarm_pct=al, criterion=cr,
+                           kappa_pct=kp)
             tms, _ = run_stream(st, 8, 3, per_launch_events=False, n_hip=nh)
             row = {"GB/s": round(nbytes * 8 / (tms * 1e-3) / 1e9, 1), "ms_per_step": round(tms / 8, 4)}
             if al:

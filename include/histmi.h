@@ -153,12 +153,25 @@ typedef struct {
     uint32_t lag;        /* chunk k runs with the decision made after chunk k-1-lag (0 = sequential) */
     uint32_t trace_cap;  /* chunks whose (mode, pattern, alarm) are recorded for hist_stream_read */
     uint32_t alarm_pct;  /* change detection (see below): 0 = off, else 1..100 percentage points */
+    uint32_t criterion;  /* switching test: HIST_CRIT_MAXBIN (the paper's, default), _COLLISION, _BOTH */
+    uint32_t kappa_pct;  /* collision-index threshold in percent, 0..100 (HIST_CRIT_COLLISION / _BOTH) */
 } hist_stream_config_t;
+
+/* Switching criteria.  MAXBIN is the paper's degeneracy test (Sec. III.C).  COLLISION is an
+ * alternative (the paper leaves other criteria to future work, naming one that measures the
+ * serialisation the data would cause; this is the library's reading): the window's collision
+ * index sum_v p_v^2, the probability that two lanes of a wavefront add into the same bin,
+ * tested as 100 * sum_v MW(v)^2 > kappa * (sum_v MW(v))^2 in exact integers.  BOTH takes AHist
+ * when either test does. */
+#define HIST_CRIT_MAXBIN 0u
+#define HIST_CRIT_COLLISION 1u
+#define HIST_CRIT_BOTH 2u
 
 /*
  * Stream semantics.  Chunk k gets histogram h_k.  After chunk k the device updates
  *   Acc += h_k (uint64, the Accumulator), MW = h_{k-W+1} + ... + h_k (the moving window),
- *   D_k = (AHIST if 100 * max_v MW(v) > theta * sum_v MW(v) else WAVEHIST, rule P(MW)).
+ *   D_k = (AHIST if 100 * max_v MW(v) > theta * sum_v MW(v) else WAVEHIST, rule P(MW))
+ * (with the MAXBIN criterion; see HIST_CRIT_* for the others).
  * Chunk k runs with D_{k-1-lag}; chunks with k-1-lag < 0 run WAVEHIST with the identity
  * pattern.  A forced mode in push replaces the decided kernel but not the pattern.  All
  * state lives on the device; no host round trip happens between chunks.

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libhistmi.so")
 
 OK, EINVAL, ENOMEM, EOVERFLOW, EBUSY, EDEVICE, ENOTSUP, ETIMEDOUT, ECANCELED = 0, -1, -2, -3, -4, -5, -6, -7, -8
 MODE_AUTO, MODE_AHIST, MODE_WAVEHIST, MODE_WAVEAGG = 0, 1, 2, 3
+CRIT_MAXBIN, CRIT_COLLISION, CRIT_BOTH = 0, 1, 2
 PAT_IDENTITY, PAT_PAPER960, PAT_FLAT = 0, 1, 2
 S_MAX = 16384
 RMAX_MAX = 64
@@ -59,7 +60,7 @@ class DeviceInfo(ctypes.Structure):
 class StreamConfig(ctypes.Structure):
     _fields_ = [("W", ctypes.c_uint32), ("theta_pct", ctypes.c_uint32), ("S", ctypes.c_uint32),
                 ("rmax", ctypes.c_uint32), ("lag", ctypes.c_uint32), ("trace_cap", ctypes.c_uint32),
-                ("alarm_pct", ctypes.c_uint32)]
+                ("alarm_pct", ctypes.c_uint32), ("criterion", ctypes.c_uint32), ("kappa_pct", ctypes.c_uint32)]
 
 
 class IngestConfig(ctypes.Structure):
@@ -315,8 +316,8 @@ class Stream:
     """A device-resident histogram stream (Accumulator, moving window, adaptive kernel switch)."""
 
     def __init__(self, W: int = 1, theta_pct: int = 45, S: int = 960, rmax: int = 8, lag: int = 0,
-                 trace_cap: int = 1024, alarm_pct: int = 0):
-        cfg = StreamConfig(W, theta_pct, S, rmax, lag, trace_cap, alarm_pct)
+                 trace_cap: int = 1024, alarm_pct: int = 0, criterion: int = 0, kappa_pct: int = 0):
+        cfg = StreamConfig(W, theta_pct, S, rmax, lag, trace_cap, alarm_pct, criterion, kappa_pct)
         self.cfg = cfg
         self._h = ctypes.c_void_p()
         _check(load().hist_stream_create(ctypes.byref(self._h), ctypes.byref(cfg)), "hist_stream_create")

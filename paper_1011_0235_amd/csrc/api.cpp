@@ -704,7 +704,8 @@ hist_status_t hist_stream_create(hist_stream_t **out, const hist_stream_config_t
   if (!out || !cfg) return HIST_EINVAL;
   const hist_stream_config_t c = *cfg;
   if (c.W < 1 || c.W > (1u << 16) || c.theta_pct > 100 || c.S < 256 || c.S > HIST_S_MAX || !is_pow2(c.rmax) ||
-      c.rmax > HIST_RMAX_MAX || c.lag > 4096 || c.trace_cap > (1u << 22) || c.alarm_pct > 100)
+      c.rmax > HIST_RMAX_MAX || c.lag > 4096 || c.trace_cap > (1u << 22) || c.alarm_pct > 100 ||
+      c.criterion > HIST_CRIT_BOTH || c.kappa_pct > 100)
     return HIST_EINVAL;
   DevCtx *d;
   TRY(get_dev(&d));
@@ -739,6 +740,8 @@ static void stream_params(const hist_stream *st, Params *P) {
   P->nslot = st->nslot;
   P->W = st->cfg.W;
   P->alarm_pct = st->cfg.alarm_pct;
+  P->criterion = st->cfg.criterion;
+  P->kappa = st->cfg.kappa_pct;
   P->theta = st->cfg.theta_pct;
   P->S = st->cfg.S;
   P->rmax = st->cfg.rmax;

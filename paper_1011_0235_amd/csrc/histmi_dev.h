@@ -133,6 +133,8 @@ struct Params {
   uint32_t rmax;             // sub-bin cap of rule P
   uint32_t R;                // histogram ring slots (sequenced streams)
   uint32_t alarm_pct;        // change detection threshold (0 = off); sequenced when W > 1 or on
+  uint32_t criterion;        // HIST_CRIT_*
+  uint32_t kappa;            // collision-index threshold, percent
   uint64_t trace_cap;
   Decision *slots;           // the stream's decision ring
   // LDS layout (in 32-bit words)

@@ -57,6 +57,7 @@ struct Ctl {
   uint64_t seqn;           // and the bytes in its window
   uint32_t sflag[2][kWaves];  // the sequencer's per-wavefront flags, by chunk parity
   uint64_t alarms[3];      // the sequencer's change-detection count, first and last alarm
+  uint64_t coll[3][4][3];  // collision criterion: limb sums of sum MW^2 [batch mod 3][chunk][limb]
   // multi-segment launches, double-buffered so that one barrier per step suffices:
   SegDesc sd[2];           // the current segment's descriptor (and the next one's, being staged)
   TileRec nrec[2];         // the next tile's record, by tile parity
@@ -733,11 +734,12 @@ __device__ __forceinline__ void publish_decision(const Params &P, Decision *d, u
 // chunks that are there, in order from j, are then decided and published.  An entry of a
 // chunk leaving the window that is itself in the batch may not have been loaded yet; the
 // chunk that needs it then counts as absent and is taken by the next batch.
-// Batch sizes: as many chunks as fit beside the tile loop's registers (occupancy 4); change
-// detection's 128-bit arithmetic leaves room for fewer.
+// Batch sizes: as many chunks as fit beside the tile loop's registers (occupancy 4); the
+// 128-bit arithmetic of change detection and of the collision criterion leaves room for fewer.
 constexpr uint32_t kSeqBatch = 6;
-constexpr uint32_t kSeqBatchAlarm = 3;
-static_assert(kSeqBatch <= 8 && kSeqBatchAlarm <= 8, "per-chunk flags: bits 0-7 absent, 16-23 over theta, 24-31 alarms");
+constexpr uint32_t kSeqBatchExtra = 3;
+static_assert(kSeqBatch <= 8 && kSeqBatchExtra <= 4, "per-chunk flags: bits 0-7 absent, 16-23 over theta, "
+                                                    "24-31 alarms; collision sums for 4 chunks");
 
 // Change detection for value t (Sec. III.B; the measure is our reading): its share of the
 // window departs from its share of the Accumulator by more than pct percentage points,
@@ -765,17 +767,50 @@ __device__ __forceinline__ bool share_departs(uint64_t mwv, uint64_t accv, uint6
   return gt_128(d100, lim);
 }
 
+// The alternative switching criterion (the paper leaves others to future work; our reading):
+// the window's collision index sum_v p_v^2 above kappa percent, i.e.
+// 100 * sum_v MW(v)^2 > kappa * N^2, in exact integers.  Each thread splits MW(t)^2 (a 128-bit
+// value; MW(t) < 2^56) into limbs of bits [0,32), [32,64) and [64,128); 256 of each limb sum in
+// 64 bits, and the sums give sum_v MW(v)^2 back.
+__device__ __forceinline__ void square_limbs(uint64_t x, uint64_t *l) {
+  const uint64_t lo = x * x;
+  l[0] = lo & 0xFFFFFFFFu;
+  l[1] = lo >> 32;
+  l[2] = __umul64hi(x, x);
+}
+__device__ __forceinline__ U128 from_limbs(uint64_t s0, uint64_t s1, uint64_t s2) {
+  const uint64_t lo = s0 + (s1 << 32);
+  return {s2 + (s1 >> 32) + (lo < s0 ? 1u : 0u), lo};
+}
+__device__ __forceinline__ bool collision_above(U128 sq, uint64_t n, uint32_t kappa) {
+  if (n == 0) return false;
+  const U128 s100 = {sq.hi * 100u + __umul64hi(sq.lo, 100u), sq.lo * 100u};
+  const U128 nn = mul_64x64(n, n);
+  const U128 lim = {nn.hi * kappa + __umul64hi(nn.lo, kappa), nn.lo * kappa};
+  return gt_128(s100, lim);
+}
+// The switch (Sec. III.C and the alternative): AHist iff the chosen test fires.
+__device__ __forceinline__ uint32_t switch_mode(uint32_t criterion, bool maxbin, bool collision) {
+  const bool ahist = criterion == HIST_CRIT_MAXBIN ? maxbin
+                     : criterion == HIST_CRIT_COLLISION ? collision : (maxbin || collision);
+  return ahist ? HIST_MODE_AHIST : HIST_MODE_WAVEHIST;
+}
+
 __device__ __forceinline__ uint64_t lane_u64(uint64_t v, uint32_t lane) {
   const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, lane);
   const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), lane);
   return ((uint64_t)hi << 32) | lo;
 }
 
-template <uint32_t B, bool ALARM>
+template <uint32_t B, bool EXTRA>
 __device__ __forceinline__ void sequence_stream(const Params &P, Ctl &c, StreamDev *st) {
   const uint32_t t = threadIdx.x, lane = lane_id();
   const uint32_t W = P.W, R = P.R, nslot = P.nslot;
   const uint32_t apct = P.alarm_pct;
+  // EXTRA: the instantiation that can also run change detection and the collision criterion
+  const bool alarm_on = EXTRA && apct != 0;
+  const bool coll_on = EXTRA && P.criterion != HIST_CRIT_MAXBIN;
+  uint32_t cb = 0;   // collision limb sums: this batch's buffer (three, so they clear without a barrier)
   const uint64_t *ring = st->ring;
   const uint64_t *ring_n = st->ring_n;
   uint8_t *alarm_trace = st->alarm_trace;
@@ -783,7 +818,11 @@ __device__ __forceinline__ void sequence_stream(const Params &P, Ctl &c, StreamD
   auto wrap = [R](uint32_t s, uint32_t d) -> uint32_t { return s + d >= R ? s + d - R : s + d; };
   uint32_t par = 0;
   for (;;) {
-    if (t == 0) c.flag = (atomicCAS(&st->seq_lock, 0u, 1u) == 0u) ? 1u : 0u;
+    if (t == 0) {
+      c.flag = (atomicCAS(&st->seq_lock, 0u, 1u) == 0u) ? 1u : 0u;
+      if (coll_on && c.flag)
+        for (uint32_t i = 0; i < 3 * 4 * 3; ++i) (&c.coll[0][0][0])[i] = 0;
+    }
     __syncthreads();
     const bool holder = c.flag != 0;
     __syncthreads();
@@ -795,7 +834,7 @@ __device__ __forceinline__ void sequence_stream(const Params &P, Ctl &c, StreamD
     uint64_t mw = ld_agent(&st->mw[t]);
     // change detection: the Accumulator in chunk order and its bytes
     uint64_t sacc = 0, NA = 0;
-    if (ALARM) {
+    if (alarm_on) {
       sacc = ld_agent(&st->sacc[t]);
       NA = lane_u64(ld_agent(&st->sacc_n), 0);
       if (t == 0) {   // kept in LDS while the lock is held
@@ -852,15 +891,26 @@ __device__ __forceinline__ void sequence_stream(const Params &P, Ctl &c, StreamD
         NN += (n & kSizeMask) - (old ? (no & kSizeMask) : 0u);
         if (__ballot(!ok) != 0) bad |= 1u << b;
         if (__ballot(100ull * m > (uint64_t)P.theta * NN) != 0) hot |= 1u << b;
+        if (coll_on) {
+          uint64_t l[3];
+          square_limbs(m, l);
+#pragma unroll
+          for (uint32_t i = 0; i < 3; ++i)
+            atomicAdd(reinterpret_cast<unsigned long long *>(&c.coll[cb][b][i]), (unsigned long long)l[i]);
+        }
       }
       uint32_t *f = c.sflag[par];
       par ^= 1u;
-      if (lane == 0) f[wave_id()] = bad | (hot << 16) | (ALARM ? pend << 24 : 0u);
+      if (lane == 0) f[wave_id()] = bad | (hot << 16) | (alarm_on ? pend << 24 : 0u);
       __syncthreads();
       uint32_t fl = 0;
 #pragma unroll
       for (uint32_t w = 0; w < kWaves; ++w) fl |= f[w];
-      if (ALARM && pcnt) record(fl >> 24, pj, pcnt);
+      if (alarm_on && pcnt) record(fl >> 24, pj, pcnt);
+      // the buffer of the batch before this one: every thread read it before this barrier
+      const uint32_t cprev = cb == 0 ? 2u : cb - 1u;
+      if (coll_on && t == 0)
+        for (uint32_t i = 0; i < 4 * 3; ++i) (&c.coll[cprev][0][0])[i] = 0;
       // chunks j .. j + cnt - 1 are there (all four wavefronts saw every entry)
       const uint32_t cnt = (uint32_t)__builtin_ctz((fl & 0xFFu) | (1u << B));
       uint32_t alarm = 0;
@@ -873,15 +923,19 @@ __device__ __forceinline__ void sequence_stream(const Params &P, Ctl &c, StreamD
         N += (lane_u64(nv, b) & kSizeMask) - (old ? (lane_u64(nov, b) & kSizeMask) : 0u);
         uint32_t kind_lg;
         const uint32_t word = decide_pattern(P, c, mw, N, &kind_lg);
-        const uint32_t mode = (fl >> (16 + b)) & 1u ? HIST_MODE_AHIST : HIST_MODE_WAVEHIST;
+        bool coll = false;
+        if (coll_on)
+          coll = collision_above(from_limbs(c.coll[cb][b][0], c.coll[cb][b][1], c.coll[cb][b][2]), N, P.kappa);
+        const uint32_t mode = switch_mode(P.criterion, ((fl >> (16 + b)) & 1u) != 0, coll);
         const uint32_t d = dj + b >= nslot ? dj + b - nslot : dj + b;
         publish_decision(P, &slots[d], q, mode, kind_lg, word);
-        if (ALARM) {
+        if (alarm_on) {
           sacc += (uint32_t)e[b];
           NA += lane_u64(nv, b) & kSizeMask;
           if (__ballot(share_departs(mw, sacc, N, NA, alarm_limit(apct, N, NA))) != 0) alarm |= 1u << b;
         }
       }
+      cb = cb == 2 ? 0u : cb + 1u;
       pend = alarm;
       pcnt = cnt;
       pj = j;
@@ -891,7 +945,7 @@ __device__ __forceinline__ void sequence_stream(const Params &P, Ctl &c, StreamD
       dj = dj + cnt >= nslot ? dj + cnt - nslot : dj + cnt;
       if (cnt < B) break;
     }
-    if (ALARM && pcnt) {
+    if (alarm_on && pcnt) {
       // the last batch's alarms
       uint32_t *fa = c.sflag[par];
       par ^= 1u;
@@ -907,7 +961,7 @@ __device__ __forceinline__ void sequence_stream(const Params &P, Ctl &c, StreamD
       st_agent(&st->done, j);
       st_agent(&st->win_n, N);
     }
-    if (ALARM) {
+    if (alarm_on) {
       st_agent(&st->sacc[t], sacc);
       if (t == 0) {
         st_agent(&st->sacc_n, NA);
@@ -946,7 +1000,22 @@ __device__ __forceinline__ void stream_epilogue(const Params &P, Ctl &c, uint32_
   if (P.W == 1 && P.alarm_pct == 0) {
     // degeneracy of the window (this chunk): AHist iff some bin exceeds theta percent (strict)
     const bool hot = 100ull * h > (uint64_t)P.theta * bytes;
-    const uint32_t mode = block_all(!hot, c) ? HIST_MODE_WAVEHIST : HIST_MODE_AHIST;
+    const bool maxbin = !block_all(!hot, c);
+    bool coll = false;
+    if (P.criterion != HIST_CRIT_MAXBIN) {
+      // collision criterion: the limb sums of sum h^2 through LDS atomics
+      if (t < 3) c.coll[0][0][t] = 0;
+      __syncthreads();
+      uint64_t l[3];
+      square_limbs(h, l);
+#pragma unroll
+      for (uint32_t i = 0; i < 3; ++i)
+        atomicAdd(reinterpret_cast<unsigned long long *>(&c.coll[0][0][i]), (unsigned long long)l[i]);
+      __syncthreads();
+      coll = collision_above(from_limbs(c.coll[0][0][0], c.coll[0][0][1], c.coll[0][0][2]), bytes, P.kappa);
+      __syncthreads();
+    }
+    const uint32_t mode = switch_mode(P.criterion, maxbin, coll);
     uint32_t kind_lg;
     const uint32_t word = decide_pattern(P, c, h, bytes, &kind_lg);
     Decision *d = &P.slots[(uint64_t)k % P.nslot];
@@ -960,8 +1029,8 @@ __device__ __forceinline__ void stream_epilogue(const Params &P, Ctl &c, uint32_
   if (t == 0) st_agent(&st->ring_n[slot], ((uint64_t)((uint32_t)(k + 1) & kSizeGenMask) << kSizeBits) | bytes);
   order_global();     // every entry is in before the CAS below (so a failing CAS means the
   __syncthreads();    // sequencer's last look will find them)
-  if (P.alarm_pct)
-    sequence_stream<kSeqBatchAlarm, true>(P, c, st);
+  if (P.alarm_pct || P.criterion != HIST_CRIT_MAXBIN)
+    sequence_stream<kSeqBatchExtra, true>(P, c, st);
   else
     sequence_stream<kSeqBatch, false>(P, c, st);
 }

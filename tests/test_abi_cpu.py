@@ -111,7 +111,8 @@ def test_stream_and_server_config_errors(hm):
     h = ctypes.c_void_p()
     for cfg in (hm._lib.StreamConfig(0, 45, 960, 8, 0, 1), hm._lib.StreamConfig(1, 101, 960, 8, 0, 1),
                 hm._lib.StreamConfig(1, 45, 100, 8, 0, 1), hm._lib.StreamConfig(1, 45, 960, 6, 0, 1),
-                hm._lib.StreamConfig(1, 45, 20000, 8, 0, 1), hm._lib.StreamConfig(32, 45, 960, 8, 0, 1, 101)):
+                hm._lib.StreamConfig(1, 45, 20000, 8, 0, 1), hm._lib.StreamConfig(32, 45, 960, 8, 0, 1, 101),
+                hm._lib.StreamConfig(4, 45, 960, 8, 0, 1, 0, 3, 10), hm._lib.StreamConfig(4, 45, 960, 8, 0, 1, 0, 1, 101)):
         assert lib.hist_stream_create(ctypes.byref(h), ctypes.byref(cfg)) == hm.EINVAL
     assert lib.hist_stream_read_alarms(None, None, 0, None) == hm.EINVAL
     for cfg in (hm._lib.ServerConfig(0, 4, 4, 1, 4, 0, 45, 960, 8), hm._lib.ServerConfig(1 << 20, 0, 4, 1, 4, 0, 45, 960, 8),
@@ -142,3 +143,38 @@ def test_tuning_table(hm):
         hm.tune_set(1, tiles_per_wg=65)
     with pytest.raises(hm.HistError):
         hm.tune_set(5, blocks_per_cu=1)
+
+
+def test_struct_layouts_match_binding(hm, tmp_path):
+    # every struct of the C ABI, compiled by the host compiler from include/histmi.h, has the
+    # size and field offsets the binding's ctypes mirror assumes
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not installed")
+    L = hm._lib
+    pairs = {"hist_pattern_t": L.Pattern, "hist_device_info_t": L.DeviceInfo,
+             "hist_stream_config_t": L.StreamConfig, "hist_ingest_config_t": L.IngestConfig,
+             "hist_stream_snapshot_t": L.StreamSnapshot, "hist_diag_t": L.Diag, "hist_tune_t": L.Tune,
+             "hist_server_config_t": L.ServerConfig, "hist_server_result_t": L.ServerResult,
+             "hist_server_stats_t": L.ServerStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "histmi.h"', 'int main(void) {']
+    for cname, cls in pairs.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f in cls._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f[0], cname, f[0]))
+    lines.append('return 0; }')
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            a, b, c = line.split()
+            got[(a, b)] = int(c)
+    for cname, cls in pairs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f in cls._fields_:
+            assert got[(cname, f[0])] == getattr(cls, f[0]).offset, (cname, f[0])
