@@ -530,19 +530,47 @@ __device__ uint32_t table_bin(uint32_t *lds, const Ctl &c, uint32_t kind, uint32
       h += lds[(w << 8) | t];
       lds[(w << 8) | t] = 0u;
     }
+  } else if (kind == KIND_UNIFORM && lg >= 4) {
+    // value t's r sub-bins are one row of r / 4 16-byte quads: read four quads at a time
+    // (one wait per four reads instead of one per word), then clear them.  The quad order is
+    // rotated by row so that the 16 lanes of each LDS pass cover all 64 banks: 64 / r rows
+    // share a bank window, so the rotation steps once per 64 / r rows (lg <= 6).
+    const uint32_t nq = 1u << (lg - 2);
+    const uint32_t rot = t >> (6u - lg);
+    u32x4 *row = reinterpret_cast<u32x4 *>(lds + (t << lg));
+    const u32x4 z = {0u, 0u, 0u, 0u};
+    for (uint32_t k0 = 0; k0 < nq; k0 += 4) {
+      u32x4 x[4];
+#pragma unroll
+      for (uint32_t u = 0; u < 4; ++u) x[u] = row[(k0 + u + rot) & (nq - 1u)];
+#pragma unroll
+      for (uint32_t u = 0; u < 4; ++u) {
+        h += x[u][0] + x[u][1] + x[u][2] + x[u][3];
+        row[(k0 + u + rot) & (nq - 1u)] = z;
+      }
+    }
   } else if (kind == KIND_UNIFORM) {
-    const uint32_t r = 1u << lg;
+    const uint32_t r = 1u << lg;   // at most 8 sub-bins per value
     for (uint32_t j = 0; j < r; ++j) {
-      const uint32_t i = (t << lg) | ((j + t) & (r - 1u));   // rotated: distinct banks
+      const uint32_t i = (t << lg) | ((j + t) & (r - 1u));
       h += lds[i];
       lds[i] = 0u;
     }
   } else {
+    // any pattern: eight reads in flight at a time, then clear
     const uint32_t w = c.words[t];
     const uint32_t base = w & 0xFFFFu, r = 1u << ((w >> 16) & 0xFFu);
-    for (uint32_t j = 0; j < r; ++j) {
-      h += lds[base + j];
-      lds[base + j] = 0u;
+    for (uint32_t j0 = 0; j0 < r; j0 += 8) {
+      uint32_t x[8];
+#pragma unroll
+      for (uint32_t u = 0; u < 8; ++u) x[u] = (j0 + u < r) ? lds[base + j0 + u] : 0u;
+#pragma unroll
+      for (uint32_t u = 0; u < 8; ++u) {
+        if (j0 + u < r) {
+          h += x[u];
+          lds[base + j0 + u] = 0u;
+        }
+      }
     }
   }
   return h;
