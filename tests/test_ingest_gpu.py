@@ -36,10 +36,10 @@ def pinned(a: np.ndarray):
     return t
 
 
-def run(hm, chunks, n_hip, W, theta, S, rmax, lag, sequential=False, source="pinned"):
+def run(hm, chunks, n_hip, W, theta, S, rmax, lag, sequential=False, source="pinned", extra=None):
     slot = max(1, max(c.size for c in chunks))
     ing = hm.Ingest(n_hip_streams=n_hip, slot_bytes=slot)
-    st = hm.Stream(W=W, theta_pct=theta, S=S, rmax=rmax, lag=lag, trace_cap=len(chunks))
+    st = hm.Stream(W=W, theta_pct=theta, S=S, rmax=rmax, lag=lag, trace_cap=len(chunks), **(extra or {}))
     outs = torch.full((len(chunks), 256), -1, dtype=torch.int32, device="cuda")
     torch.cuda.synchronize()
     hosts = [pinned(c) if source == "pinned" else c for c in chunks]
@@ -49,10 +49,11 @@ def run(hm, chunks, n_hip, W, theta, S, rmax, lag, sequential=False, source="pin
             ing.sync()
     ing.sync()
     snap, modes, pats = st.read(len(chunks))
+    alarms = [int(a) for a in st.read_alarms(len(chunks))] if extra and extra.get("alarm_pct") else None
     got = outs.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
     st.close()
     ing.close()
-    return got, snap, modes, pats
+    return got, snap, modes, pats, alarms
 
 
 @pytest.mark.parametrize("n_hip,lag,W,sequential,source", [(1, 0, 1, True, "pinned"), (1, 0, 1, False, "pinned"),
@@ -61,7 +62,7 @@ def run(hm, chunks, n_hip, W, theta, S, rmax, lag, sequential=False, source="pin
 def test_ingest_matches_oracle(hm, n_hip, lag, W, sequential, source):
     chunks = chunks_mixed(500 + n_hip * 10 + lag, 40, 300_000)
     ref = O.stream_reference(chunks, W=W, theta_pct=45, S=960, rmax=8, lag=lag)
-    got, snap, modes, pats = run(hm, chunks, n_hip, W, 45, 960, 8, lag, sequential, source)
+    got, snap, modes, pats, _ = run(hm, chunks, n_hip, W, 45, 960, 8, lag, sequential, source)
     assert np.array_equal(got, ref["hists"].astype(np.int64))
     assert [int(x) for x in snap.acc] == ref["acc"]
     assert [int(x) for x in snap.mw] == ref["mw"]
@@ -71,12 +72,31 @@ def test_ingest_matches_oracle(hm, n_hip, lag, W, sequential, source):
     assert d.invalid_patterns == 0 and d.wait_timeouts == 0 and d.merge_timeouts == 0
 
 
+@pytest.mark.parametrize("W,alarm_pct,criterion,kappa", [(1, 10, 1, 5), (4, 5, 2, 20)])
+def test_ingest_with_detection_and_criterion(hm, W, alarm_pct, criterion, kappa):
+    # host-fed streams with change detection and the alternative switching criterion on
+    chunks = chunks_mixed(800 + W, 48, 200_000)
+    ref = O.stream_reference(chunks, W=W, theta_pct=45, S=960, rmax=8, lag=1, alarm_pct=alarm_pct,
+                             criterion=criterion, kappa_pct=kappa)
+    got, snap, modes, pats, alarms = run(hm, chunks, 4, W, 45, 960, 8, 1,
+                                         extra={"alarm_pct": alarm_pct, "criterion": criterion, "kappa_pct": kappa})
+    assert np.array_equal(got, ref["hists"].astype(np.int64))
+    assert [int(x) for x in snap.acc] == ref["acc"]
+    assert [int(x) for x in snap.mw] == ref["mw"]
+    assert [int(m) for m in modes] == ref["modes"]
+    assert [list(map(int, p)) for p in pats] == ref["patterns"]
+    assert alarms == ref["alarms"]
+    assert int(snap.alarms) == sum(ref["alarms"])
+    d = hm.diag()
+    assert d.invalid_patterns == 0 and d.wait_timeouts == 0 and d.merge_timeouts == 0
+
+
 def test_ingest_full_size_config2(hm):
     # the 66 x 4 MiB stream from pinned host memory over 16 HIP streams, the bench's settings
     chunks = G.stream_chunks(4 << 20)
     hists = [O.hist(c) for c in chunks]
     ref = O.stream_reference(None, W=1, theta_pct=0, S=8192, rmax=32, lag=31, hists=hists)
-    got, snap, modes, pats = run(hm, chunks, 16, 1, 0, 8192, 32, 31)
+    got, snap, modes, pats, _ = run(hm, chunks, 16, 1, 0, 8192, 32, 31)
     assert np.array_equal(got, ref["hists"].astype(np.int64))
     assert [int(m) for m in modes] == ref["modes"]
     assert [int(x) for x in snap.acc] == ref["acc"]
