@@ -53,8 +53,6 @@ struct Ctl {
   uint32_t used_mode;
   uint32_t tmp;
   uint64_t tag;            // decision tag of the current segment's stream chunk
-  uint64_t seqj;           // the stream sequencer's next chunk
-  uint64_t seqn;           // and the bytes in its window
   uint32_t sflag[2][kWaves];  // the sequencer's per-wavefront flags, by chunk parity
   uint64_t alarms[3];      // the sequencer's change-detection count, first and last alarm
   uint64_t coll[3][4][3];  // collision criterion: limb sums of sum MW^2 [batch mod 3][chunk][limb]
@@ -65,6 +63,7 @@ struct Ctl {
   uint32_t red32[kWaves];
   uint64_t red64[kWaves];
   uint32_t cls_cnt[kWaves][8];
+  uint32_t ehist[24];      // rule P: values per scale offset e
   uint32_t words[256];     // binning pattern words of the current segment
   uint32_t bitmap[512];    // overlap check of a pattern (up to HIST_S_MAX sub-bins)
 };
@@ -228,38 +227,55 @@ __device__ uint64_t spin_for_tag(const uint64_t *p, uint32_t gen, uint32_t *diag
 // histograms, Sec. III.B, without giving a rule).  Thread t holds h(t); N = sum h.
 //   256*rmax <= S: every value gets rmax.  N == 0: every value gets 1.
 //   Otherwise r_t(v) = min(rmax, pow2ceil(max(1, ceil(h(v) 2^t / N)))) at the largest t in
-//   [0, min(24, clz64(N))] with sum_v r_t(v) <= S (the sum grows with t: binary search).
+//   [0, min(24, clz64(N))] with sum_v r_t(v) <= S (the sum grows with t).
 //   Values are laid out by (r descending, value ascending); bases are running sums.
-// Returns this thread's pattern word.
+//
+// Evaluated without division and with one barrier for the search.  For h > 0 let e be the
+// largest e >= 0 with h 2^e <= N.  Then ceil(h 2^t / N) <= 2^k holds iff k >= t - e, so
+// log2 r_t(v) = min(log2 rmax, max(0, t - e(v))) (and 0 for h = 0).  The sum at scale t is
+// therefore 256 + sum over e < t of n_e (2^min(log2 rmax, t - e) - 1), with n_e the number of
+// values at e: a 24-bucket histogram of e in LDS gives every scale's sum, lane t of each
+// wavefront evaluates scale t, and one ballot picks the largest that fits.
 
-__device__ __forceinline__ uint32_t rule_p_lg(uint64_t h, uint64_t N, uint32_t tt, uint32_t rmax, uint32_t rmax_lg) {
-  const uint64_t num = h << tt;
-  const uint64_t q = num / N + ((num % N) != 0 ? 1u : 0u);
-  if (q <= 1) return 0;
-  if (q >= rmax) return rmax_lg;
-  return 64u - (uint32_t)__clzll((long long)(q - 1));
+// e(v) as above: h 2^e has the bit length of N, or one less when that would exceed N.
+__device__ __forceinline__ uint32_t rule_p_e(uint64_t h, uint64_t N) {
+  if (h == 0) return 64u;
+  const uint32_t bn = 64u - (uint32_t)__clzll((long long)N), bh = 64u - (uint32_t)__clzll((long long)h);
+  uint32_t e = bn - bh;
+  if ((h << e) > N) --e;   // bh + e = bn <= 64: no overflow; h <= N makes e >= 0 here
+  return e;
 }
 
-__device__ uint32_t rule_p_word(uint64_t h, uint64_t N, uint32_t S, uint32_t rmax, Ctl &c) {
+// Returns this thread's pattern word; *kind_lg = the table kind (KIND_UNIFORM << 8 | log2 r
+// when every value has the same r, which with this layout puts value v at v * r; else
+// KIND_LOOKUP << 8).  All threads call.
+__device__ uint32_t rule_p_word(uint64_t h, uint64_t N, uint32_t S, uint32_t rmax, Ctl &c, uint32_t *kind_lg) {
+  const uint32_t t = threadIdx.x;
   const uint32_t rmax_lg = 31u - (uint32_t)__clz((int)rmax);
+  const uint32_t lane = lane_id(), w = wave_id();
   uint32_t cls;
   if (256u * rmax <= S) {
     cls = rmax_lg;
   } else if (N == 0) {
     cls = 0;
   } else {
-    const uint32_t lz = (uint32_t)__clzll((long long)N);
-    uint32_t lo = 0, hi = lz < 24u ? lz : 24u;
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi + 1) >> 1;
-      const uint32_t s = block_sum_u32(1u << rule_p_lg(h, N, mid, rmax, rmax_lg), c);
-      if (s <= S) lo = mid;
-      else hi = mid - 1;
+    const uint32_t T = min(24u, (uint32_t)__clzll((long long)N));
+    const uint32_t e = rule_p_e(h, N);
+    if (t < 24) c.ehist[t] = 0;
+    __syncthreads();
+    if (e < 24) atomicAdd(&c.ehist[e], 1u);
+    __syncthreads();
+    // lane l of every wavefront: the sum at scale l (the same in all four wavefronts)
+    uint32_t sum = 256;
+    for (uint32_t x = 0; x < lane && x < 24; ++x) {
+      const uint32_t d = min(rmax_lg, lane - x);
+      sum += c.ehist[x] * ((1u << d) - 1u);
     }
-    cls = rule_p_lg(h, N, lo, rmax, rmax_lg);
+    const uint64_t fits = __ballot(lane <= T && sum <= S);   // a prefix 0..t* (scale 0 always fits)
+    const uint32_t ts = 63u - (uint32_t)__clzll((long long)fits);
+    cls = (e >= ts) ? 0u : min(rmax_lg, ts - e);
   }
   // layout by (r descending, value ascending)
-  const uint32_t lane = lane_id(), w = wave_id();
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   uint32_t rank = 0;
 #pragma unroll
@@ -276,19 +292,12 @@ __device__ uint32_t rule_p_word(uint64_t h, uint64_t N, uint32_t S, uint32_t rma
     for (uint32_t w2 = 0; w2 < kWaves; ++w2) cnt += c.cls_cnt[w2][k];
     offset += cnt << k;
   }
+  // one class holding all 256 values: the uniform table
+  uint32_t same = 0;
+  for (uint32_t w2 = 0; w2 < kWaves; ++w2) same += c.cls_cnt[w2][cls];
+  *kind_lg = (same == 256u) ? (((uint32_t)KIND_UNIFORM << 8) | cls) : ((uint32_t)KIND_LOOKUP << 8);
   __syncthreads();
   return (offset + (rank << cls)) | (cls << 16);
-}
-
-// Table kind of the pattern whose word for value t is `word` (all threads call): uniform iff
-// every value has the same r and sits at v * r.
-__device__ uint32_t pattern_kind_lg(uint32_t word, Ctl &c) {
-  const uint32_t t = threadIdx.x;
-  if (t == 0) c.tmp = word;
-  __syncthreads();
-  const uint32_t lg0 = (c.tmp >> 16) & 0xFFu;
-  const bool uni = (((word >> 16) & 0xFFu) == lg0) && ((word & 0xFFFFu) == (t << lg0));
-  return block_all(uni, c) ? (((uint32_t)KIND_UNIFORM << 8) | lg0) : ((uint32_t)KIND_LOOKUP << 8);
 }
 
 // ------------------------------------------------------------------ table staging
@@ -691,8 +700,8 @@ __device__ __forceinline__ void server_epilogue(const Params &P, Ctl &c, uint32_
   const uint64_t N = block_sum_u64(h, c);
   const uint64_t mx = block_max_u64(h, c);
   const uint32_t mode = (100ull * mx > (uint64_t)st->theta * N) ? HIST_MODE_AHIST : HIST_MODE_WAVEHIST;
-  const uint32_t word = rule_p_word(h, N, st->S, st->rmax, c);
-  const uint32_t kind_lg = pattern_kind_lg(word, c);
+  uint32_t kind_lg;
+  const uint32_t word = rule_p_word(h, N, st->S, st->rmax, c, &kind_lg);
   Decision *d = &st->slots[0];
   st_agent(&d->words[t], word);
   if (t == 0) {
@@ -716,9 +725,7 @@ __device__ __forceinline__ uint32_t decide_pattern(const Params &P, Ctl &c, uint
     *kind_lg = ((uint32_t)KIND_UNIFORM << 8) | lg;
     return (t << lg) | (lg << 16);
   }
-  const uint32_t word = rule_p_word(mw, N, P.S, P.rmax, c);
-  *kind_lg = pattern_kind_lg(word, c);
-  return word;
+  return rule_p_word(mw, N, P.S, P.rmax, c, kind_lg);
 }
 
 // Publish the decision made after chunk j into slot d (all threads call).  The chunk that
@@ -1314,7 +1321,8 @@ __global__ void __launch_bounds__(kBlock) pattern_update_kernel(const uint64_t *
   const uint32_t t = threadIdx.x;
   const uint64_t v = h[t];
   const uint64_t N = block_sum_u64(v, c);
-  out->word[t] = rule_p_word(v, N, S, rmax, c);
+  uint32_t kind_lg;
+  out->word[t] = rule_p_word(v, N, S, rmax, c, &kind_lg);
   if (t == 0) {
     out->total_S = S;
     out->rmax = rmax;
