@@ -4,17 +4,18 @@ One step = one pass of a single stream of 66 chunks x 4 MiB (264 MiB of 8-bit pi
 clipped Normal(128, sigma) chunks with sigma 96/32/8/2, a fully degenerate chunk and a
 two-spike chunk) through the device-resident stream: per-chunk exact histograms, the
 Accumulator, the moving window, the degeneracy switch and the pattern recomputation, all in
-one persistent launch.  Inputs are resident in HBM before timing starts; two copies of the
-stream are used in turn so no step reads bytes the 256 MB cache just saw.  Consecutive steps
-go to two HIP streams in turn: the next launch fills the device while the previous one drains
-(the paper pipelines its stream over several CUDA streams the same way).
+one persistent launch.  Chunk k + 1 runs with the decision made from chunk k (lag 0).
+Inputs are resident in HBM before timing starts; four copies of the stream are used in turn
+so no step reads bytes the 256 MB cache just saw.  Consecutive steps go to two HIP streams
+in turn: the next launch fills the device while the previous one drains (the paper
+pipelines its stream over several CUDA streams the same way).
 
 Prints ONE JSON line.  Extra fields: a roofline of the dominant kernel (algorithmic bytes
 per launch over the launch's share of the device: the mean interval between successive
 launch completions, from HIP events recorded on the launching HIP streams), the CPU
-oracle timed on the host's cores, the same stream at pipeline lag 0 and with the paper's
-960-entry sub-histogram, a 1 MiB single image, and the 8192 x 8192 input matrix of the
-paper's Table 2.
+oracle timed on the host's cores, the same stream at the tuned pipeline lag and with the
+paper's 960-entry sub-histogram, a 1 MiB single image, and the 8192 x 8192 input matrix of
+the paper's Table 2.
 """
 
 import argparse
@@ -38,7 +39,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--lag", type=int, default=None, help="pipeline lag of the headline stream")
+    ap.add_argument("--lag", type=int, default=0, help="pipeline lag of the headline stream (0: chunk k + 1 "
+                    "runs with the decision from chunk k)")
     ap.add_argument("--theta", type=int, default=None)
     ap.add_argument("--S", type=int, default=None)
     ap.add_argument("--rmax", type=int, default=None)
@@ -171,7 +173,7 @@ def bench_batched(hm, G, O, torch, dev, stream):
             "speedup_vs_sequential": round(ms_seq / ms_graph, 2), "parity_sampled_exact": ok}
 
 
-def bench_xray(hm, G, O, torch, dev, hip_streams, S, rmax, lag, theta, frames=512):
+def bench_xray(hm, G, O, torch, dev, hip_streams, S, rmax, lag, plag, theta, frames=512):
     """The X-ray-like frame stream (512 frames of 2048 x 2048, 2 GiB): the mean of each frame's
     clipped Normal walks (step sigma 4), its sigma is U[6, 40], 1 % of its pixels are saturated.
     Generated on the device under the root seed; all frames are pushed in one launch, the
@@ -198,9 +200,13 @@ def bench_xray(hm, G, O, torch, dev, hip_streams, S, rmax, lag, theta, frames=51
     outs = [torch.zeros((frames, 256), dtype=torch.int32, device=dev) for _ in range(2)]
     exp = np.stack(hists).astype(np.int64)
     res = {"frames": frames, "bytes": frames * n}
-    for name, (th, lg, mode) in {"auto": (theta, lag, hm.MODE_AUTO), "auto_theta45": (45, lag, hm.MODE_AUTO),
-                                 "auto_theta4": (4, lag, hm.MODE_AUTO), "ahist": (theta, lag, hm.MODE_AHIST),
-                                 "wavehist": (theta, lag, hm.MODE_WAVEHIST), "auto_lag0": (theta, 0, hm.MODE_AUTO)}.items():
+    # (the data-dependent switches at theta 45 and 4 run at the tuned pipeline lag: at lag 0
+    # every frame would wait for the decision from the frame before it)
+    for name, (th, lg, mode) in {"auto": (theta, lag, hm.MODE_AUTO), "ahist": (theta, lag, hm.MODE_AHIST),
+                                 "wavehist": (theta, lag, hm.MODE_WAVEHIST),
+                                 "auto_lag%d" % plag: (theta, plag, hm.MODE_AUTO),
+                                 "auto_theta45_lag%d" % plag: (45, plag, hm.MODE_AUTO),
+                                 "auto_theta4_lag%d" % plag: (4, plag, hm.MODE_AUTO)}.items():
         ref = O.stream_reference(None, W=1, theta_pct=th, S=S, rmax=rmax, lag=lg, hists=hists, mode=mode)
         st = hm.Stream(W=1, theta_pct=th, S=S, rmax=rmax, lag=lg, trace_cap=frames)
         st.push_many(bufs, mode=mode, d_out=outs[0], stream=hip_streams[0])
@@ -412,7 +418,8 @@ def main():
     torch.cuda.set_device(dev)
     info = hm.device_info()
     tune = tuned_defaults()
-    lag = tune["lag"] if args.lag is None else args.lag
+    lag = args.lag
+    plag = tune["lag"]   # the tuned pipeline lag, for the pipelined variants in the extras
     theta = tune["theta_pct"] if args.theta is None else args.theta
     S = tune["S"] if args.S is None else args.S
     rmax = tune["rmax"] if args.rmax is None else args.rmax
@@ -524,8 +531,9 @@ def main():
         "dtype": "u8",
         "data": "synthetic",
         "config": {"workload": "single stream, 66 chunks x 4 MiB (264 MiB u8): clipped Normal(128, sigma) with sigma "
-                               "96/32/8/2, one all-127 chunk, one two-spike chunk; adaptive switch, pattern from "
-                               "past chunks, per-chunk u32 histograms + u64 Accumulator on device",
+                               "96/32/8/2, one all-127 chunk, one two-spike chunk; adaptive switch, the pattern "
+                               "and kernel for chunk k+1 from chunk k's histogram, per-chunk u32 histograms + u64 "
+                               "Accumulator on device",
                    "chunk_bytes": 4 * MIB, "chunks": nchunk, "mode": "auto", "W": 1, "theta_pct": theta,
                    "S": S, "rmax": rmax, "lag": lag},
         "pct_of_hbm_peak": round(100.0 * value / HBM_PEAK_GBS, 2),
@@ -561,20 +569,20 @@ def main():
         # change detection on, the window is also compared with the Accumulator after every chunk)
         # (the collision criterion: entries with a kappa below use it instead of theta)
         for name, (w_, l, th, s_, r_, nh, al, *crit) in {
-                "stream_lag0_auto": (1, 0, theta, S, rmax, 2, 0),
+                "stream_lag%d_auto" % plag: (1, plag, theta, S, rmax, 2, 0),
                 "stream_theta45_lag0": (1, 0, 45, S, rmax, 2, 0),
-                "stream_theta45_lag%d" % lag: (1, lag, 45, S, rmax, 2, 0),
+                "stream_theta45_lag%d" % plag: (1, plag, 45, S, rmax, 2, 0),
                 "stream_paper960_theta45_lag0": (1, 0, 45, 960, 8, 2, 0),
-                "stream_paper960_theta45_lag%d" % lag: (1, lag, 45, 960, 8, 2, 0),
+                "stream_paper960_theta45_lag%d" % plag: (1, plag, 45, 960, 8, 2, 0),
                 "stream_lag%d_one_hip_stream" % lag: (1, lag, theta, S, rmax, 1, 0),
-                "stream_window_W32_lag%d" % lag: (32, lag, theta, S, rmax, 2, 0),
-                "stream_window_W256_lag%d" % lag: (256, lag, theta, S, rmax, 2, 0),
-                "stream_window_W32_theta45_paper960_lag%d" % lag: (32, lag, 45, 960, 8, 2, 0),
-                "stream_window_W32_alarm4_lag%d" % lag: (32, lag, theta, S, rmax, 2, 4),
-                "stream_alarm4_W1_lag%d" % lag: (1, lag, theta, S, rmax, 2, 4),
-                "stream_collision10_W1_lag%d" % lag: (1, lag, 100, S, rmax, 2, 0, hm.CRIT_COLLISION, 10),
-                "stream_collision3_W32_lag%d" % lag: (32, lag, 100, S, rmax, 2, 0, hm.CRIT_COLLISION, 3),
-                "stream_collision3_W32_paper960_lag%d" % lag: (32, lag, 100, 960, 8, 2, 0, hm.CRIT_COLLISION, 3)
+                "stream_window_W32_lag%d" % plag: (32, plag, theta, S, rmax, 2, 0),
+                "stream_window_W256_lag%d" % plag: (256, plag, theta, S, rmax, 2, 0),
+                "stream_window_W32_theta45_paper960_lag%d" % plag: (32, plag, 45, 960, 8, 2, 0),
+                "stream_window_W32_alarm4_lag%d" % plag: (32, plag, theta, S, rmax, 2, 4),
+                "stream_alarm4_W1_lag%d" % plag: (1, plag, theta, S, rmax, 2, 4),
+                "stream_collision10_W1_lag%d" % plag: (1, plag, 100, S, rmax, 2, 0, hm.CRIT_COLLISION, 10),
+                "stream_collision3_W32_lag%d" % plag: (32, plag, 100, S, rmax, 2, 0, hm.CRIT_COLLISION, 3),
+                "stream_collision3_W32_paper960_lag%d" % plag: (32, plag, 100, 960, 8, 2, 0, hm.CRIT_COLLISION, 3)
                 }.items():
             cr, kp = (crit[0], crit[1]) if crit else (hm.CRIT_MAXBIN, 0)
             st = hm.Stream(W=w_, theta_pct=th, S=s_, rmax=r_, lag=l, trace_cap=0, alarm_pct=al, criterion=cr,
@@ -624,7 +632,7 @@ def main():
             t2[kind] = row
             del xs
         extras["table2_64mib_GBps"] = t2
-        extras["xray_config3"] = bench_xray(hm, G, O, torch, dev, hip_streams, S, rmax, lag, theta)
+        extras["xray_config3"] = bench_xray(hm, G, O, torch, dev, hip_streams, S, rmax, lag, plag, theta)
         extras["host_ingest_config2"] = bench_ingest(hm, G, O, torch, dev)
         extras["batched_config4"] = bench_batched(hm, G, O, torch, dev, stream)
         extras["served_config5"] = bench_served(hm, G, O, torch, dev, stream)

@@ -460,6 +460,9 @@ struct hist_stream {
   uint32_t nslot = 0;
   uint64_t pushed = 0;
   StreamAlloc sa;
+  // sizes of the last lag + 1 chunks (chunk k in slot k % (lag + 1)): with decisions that
+  // depend on the chunk sizes only, the decision a chunk runs with is known on the host
+  std::vector<uint64_t> recent;
   // Launches of one stream may run on different HIP streams and overlap; the device makes
   // each chunk wait for its decision.  At most two launches are in flight: before a launch,
   // the HIP stream waits for the launch two before it (events recorded after each launch).
@@ -467,6 +470,22 @@ struct hist_stream {
   bool ev_used[2] = {false, false};
   uint32_t evi = 0;
 };
+
+// When is the decision after a chunk a function of the chunk sizes alone?  With W = 1 and no
+// change detection (so chunks are not sequenced), a budget that gives every value rmax
+// sub-bins (rule P's first case: the pattern is the uniform table whatever the histogram),
+// and a switching test that fires for any non-empty window (theta or kappa 0): then the
+// decision after chunk j is (AHist if chunk j holds a byte, else the per-wavefront kernel;
+// the uniform table).  The host hands such decisions to the chunks that run with them, so
+// they start without waiting; the device still makes and publishes the same decisions.
+static bool decisions_known(const hist_stream_config_t &c) {
+  if (c.W != 1 || c.alarm_pct != 0 || 256ull * c.rmax > c.S) return false;
+  switch (c.criterion) {
+  case HIST_CRIT_MAXBIN: return c.theta_pct == 0;
+  case HIST_CRIT_COLLISION: return c.kappa_pct == 0;
+  default: return c.theta_pct == 0 || c.kappa_pct == 0;
+  }
+}
 
 static hist_status_t stream_launch_begin(hist_stream *st, hipStream_t s) {
   if (st->ev_used[st->evi]) TRY_HIP(hipStreamWaitEvent(s, st->ev[st->evi], 0));
@@ -715,6 +734,7 @@ hist_status_t hist_stream_create(hist_stream_t **out, const hist_stream_config_t
   // in flight span at most 2 * kMaxChunksPerLaunch chunks, plus the lag + 1 decisions made
   // before them
   st->nslot = c.lag + 2 + 2 * kMaxChunksPerLaunch;
+  st->recent.assign((size_t)c.lag + 1, 0);
   hist_status_t r =
       stream_state_alloc(1, c.W, c.theta_pct, c.S, c.rmax, c.lag, st->nslot, c.trace_cap, c.alarm_pct, &st->sa);
   for (int i = 0; i < 2 && r == HIST_OK; ++i)
@@ -783,15 +803,19 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
     const uint32_t fam = kFamStream;
     const uint32_t maxg = (uint32_t)d->cus * blocks_per_cu(fam, lds_bytes(P));
     // tiles small enough that the lag + 1 chunks which may run at once still fill the grid
+    // (every chunk, when the host knows the decisions: then no chunk waits)
+    const bool known = decisions_known(st->cfg);
     uint64_t total = 0;
     for (uint32_t j = 0; j < m; ++j) total += h_sizes[first + j];
     const uint64_t per_chunk = std::max<uint64_t>(1, total / m);
-    const uint64_t inflight = (uint64_t)std::min<uint32_t>(st->cfg.lag + 1, m);
+    const uint64_t inflight = known ? m : (uint64_t)std::min<uint32_t>(st->cfg.lag + 1, m);
     uint64_t tile = (uint64_t)g_tune[fam].tile_kib * 1024;
     const uint64_t fill = ceil_div(per_chunk * inflight, maxg);     // lag + 1 chunks cover the grid
     const uint64_t several = ceil_div(total, (uint64_t)maxg * g_tune[fam].tpw);   // tiles per workgroup
     tile = std::min<uint64_t>(tile, std::max<uint64_t>(16384, ceil_div(std::min(fill, several), 16384) * 16384));
     std::vector<SegDesc> segs(m);
+    const uint32_t ring = st->cfg.lag + 1;
+    const uint32_t lgmax = log2u(st->cfg.rmax);
     for (uint32_t j = 0; j < m; ++j) {
       std::memset(&segs[j], 0, sizeof(SegDesc));
       segs[j].ptr = static_cast<const uint8_t *>(h_ptrs[first + j]);
@@ -799,6 +823,18 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
       segs[j].out = d_out ? d_out + (size_t)(first + j) * 256 : nullptr;
       segs[j].chunk = (int64_t)j;
       segs[j].stream_idx = 0;
+      if (known) {
+        // chunk k runs with the decision made after chunk k - 1 - lag
+        const int64_t src = (int64_t)(st->pushed + j) - 1 - (int64_t)st->cfg.lag;
+        if (src < 0) {
+          segs[j].known = kKnown | kKnownCold | ((uint32_t)HIST_MODE_WAVEHIST << 16) | ((uint32_t)KIND_UNIFORM << 8);
+        } else {
+          const uint64_t n = (uint64_t)src >= st->pushed ? h_sizes[first + (uint32_t)((uint64_t)src - st->pushed)]
+                                                         : st->recent[(uint64_t)src % ring];
+          const uint32_t md = n > 0 ? HIST_MODE_AHIST : HIST_MODE_WAVEHIST;
+          segs[j].known = kKnown | (md << 16) | ((uint32_t)KIND_UNIFORM << 8) | lgmax;
+        }
+      }
     }
     MultiPlan mp;
     TRY(plan_multi(segs, tile, maxg, false, false, &mp));
@@ -808,6 +844,7 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
     TRY(stream_launch_begin(st, s));
     TRY(run_multi(d, P, mp, copies, s, nullptr, true, true));
     TRY(stream_launch_end(st, s));
+    for (uint32_t j = 0; j < m; ++j) st->recent[(st->pushed + j) % ring] = h_sizes[first + j];
     st->pushed += m;
   }
   return HIST_OK;

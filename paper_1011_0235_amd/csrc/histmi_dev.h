@@ -84,10 +84,14 @@ struct SegDesc {
   uint32_t tile0;        // first tile (launch-global index)
   uint32_t ntiles;       // >= 1 (an empty buffer still has one empty tile so it gets finalized)
   uint32_t stream_idx;   // index into Params::st for stream chunks and server requests
-  uint32_t pad;
+  uint32_t known;        // ordered-stream chunk: the decision it runs with when the host can
+                         // tell it in advance (kKnown | mode << 16 | kind_lg, plus kKnownCold
+                         // when there is no history yet), else 0: wait for the device's decision
 };
 
 constexpr int64_t kServerChunk = -2;
+constexpr uint32_t kKnown = 1u << 31;
+constexpr uint32_t kKnownCold = 1u << 30;
 
 // One tile of a multi-segment launch, written by the host: its bytes and its segment.
 // Tiles never span segments; their sizes may differ (smaller tiles near the end of a

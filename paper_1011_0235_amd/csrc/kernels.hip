@@ -634,7 +634,10 @@ __device__ __forceinline__ uint32_t begin_segment(uint32_t *lds, const Params &P
         // no history, or (never expected) a wait that timed out: the per-wavefront kernel
         // with the identity pattern
         uint64_t tag = make_tag(0, HIST_MODE_WAVEHIST, (uint32_t)KIND_UNIFORM << 8);
-        if (j >= 0) {
+        if (sd.known) {
+          // the host knew this decision (it depends on the chunk sizes only): no wait
+          tag = make_tag((sd.known & kKnownCold) ? 0u : 1u, (sd.known >> 16) & 0xFFu, sd.known & 0xFFFFu);
+        } else if (j >= 0) {
           const uint32_t want = (uint32_t)(j + 1);
           const uint64_t got = (tag_gen(hint) == want) ? hint : spin_for_tag(&d->tag, want, P.diag);
           if (got) tag = got;
@@ -664,7 +667,16 @@ __device__ __forceinline__ uint32_t begin_segment(uint32_t *lds, const Params &P
       kind = c.kind;
       // each thread writes and later reads only its own value's word (lookup staging, table
       // sums, trace), so no barrier is needed after this
-      if (kind == KIND_LOOKUP || traced) c.words[t] = (tag_gen(c.tag) != 0) ? ld_agent(&d->words[t]) : t;
+      if (kind == KIND_LOOKUP || traced) {
+        if (tag_gen(c.tag) == 0) {
+          c.words[t] = t;
+        } else if (sd.known) {   // a known decision's pattern is the uniform table
+          const uint32_t lg = tag_kind_lg(c.tag) & 0xFFu;
+          c.words[t] = (t << lg) | (lg << 16);
+        } else {
+          c.words[t] = ld_agent(&d->words[t]);
+        }
+      }
       stage_table(lds, P, c, kind);
       return kind;
     }

@@ -347,3 +347,73 @@ def test_full_size_moving_window_overlapping(hm, W):
     dg = hm.diag()
     assert dg.invalid_patterns == 0 and dg.wait_timeouts == 0 and dg.merge_timeouts == 0
     st.close()
+
+
+@pytest.mark.parametrize("lag,criterion,theta,kappa,S,rmax", [(0, 0, 0, 0, 8192, 32), (2, 0, 0, 0, 16384, 64),
+                                                             (0, 1, 45, 0, 8192, 32), (1, 2, 30, 0, 4096, 16),
+                                                             (0, 2, 0, 40, 2048, 8)])
+def test_decisions_known_in_advance(hm, lag, criterion, theta, kappa, S, rmax):
+    # W = 1 with a saturated budget and a test that fires for any non-empty window: the host
+    # hands each chunk the decision it runs with (from the size of chunk k - 1 - lag), so no
+    # chunk waits; empty chunks make some of those decisions the per-wavefront kernel.  Pushes
+    # are split across launches and two HIP streams; every trace must still be the oracle's.
+    chunks = mixed_chunks(1300 + lag * 7 + criterion, 140, 120_000)
+    ref = O.stream_reference(chunks, W=1, theta_pct=theta, S=S, rmax=rmax, lag=lag, criterion=criterion,
+                             kappa_pct=kappa)
+    assert O.MODE_WAVEHIST in ref["modes"][lag + 1:] and O.MODE_AHIST in ref["modes"]
+    st = hm.Stream(W=1, theta_pct=theta, S=S, rmax=rmax, lag=lag, trace_cap=len(chunks), criterion=criterion,
+                   kappa_pct=kappa)
+    ds = [dev(c) if c.size else None for c in chunks]
+    outs = torch.full((len(chunks), 256), -1, dtype=torch.int32, device="cuda")
+    bufs = [(int(x.data_ptr()) if x is not None else 0, c.size) for x, c in zip(ds, chunks)]
+    torch.cuda.synchronize()
+    hs = [torch.cuda.Stream(), torch.cuda.Stream()]
+    k, call = 0, 0
+    while k < len(chunks):
+        n = min(len(chunks) - k, (1, 23, 4, 50)[call % 4])
+        if n == 1:
+            st.push(bufs[k][0], d_out=outs[k], n=bufs[k][1], stream=hs[call & 1])
+        else:
+            st.push_many(bufs[k:k + n], d_out=outs[k:k + n], stream=hs[call & 1])
+        k += n
+        call += 1
+    snap, modes, pats = st.read(len(chunks), stream=hs[0])
+    torch.cuda.synchronize()
+    assert np.array_equal(outs.cpu().numpy().astype(np.int64) & 0xFFFFFFFF, ref["hists"].astype(np.int64))
+    assert [int(x) for x in snap.acc] == ref["acc"]
+    assert [int(x) for x in snap.mw] == ref["mw"]
+    assert [int(m) for m in modes] == ref["modes"]
+    assert [list(map(int, p)) for p in pats] == ref["patterns"]
+    assert int(snap.next_mode) == O.decide_mode(ref["mw"], theta, criterion, kappa)
+    assert snap.next_pattern.words() == O.rule_p(ref["mw"], S, rmax)
+    d = hm.diag()
+    assert d.invalid_patterns == 0 and d.wait_timeouts == 0 and d.merge_timeouts == 0
+    st.close()
+
+
+def test_full_size_lag0_known_decisions(hm):
+    # the config-2 stream at lag 0 (chunk k + 1's pattern from chunk k) with the tuned switch:
+    # three pushes over two HIP streams, exact against the oracle
+    chunks = config2_like(4 << 20)
+    hists = [O.hist(c) for c in chunks] * 3
+    S, rmax, theta = 8192, 32, 0
+    ref = O.stream_reference(None, W=1, theta_pct=theta, S=S, rmax=rmax, lag=0, hists=hists)
+    d = dev(np.concatenate(chunks))
+    base = int(d.data_ptr())
+    bufs = [(base + k * (4 << 20), 4 << 20) for k in range(len(chunks))]
+    outs = [torch.full((len(chunks), 256), -1, dtype=torch.int32, device="cuda") for _ in range(3)]
+    st = hm.Stream(W=1, theta_pct=theta, S=S, rmax=rmax, lag=0, trace_cap=len(hists))
+    torch.cuda.synchronize()
+    hs = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for r in range(3):
+        st.push_many(bufs, d_out=outs[r], stream=hs[r & 1])
+    snap, modes, pats = st.read(len(hists), stream=hs[0])
+    torch.cuda.synchronize()
+    got = np.concatenate([o.cpu().numpy().astype(np.int64) & 0xFFFFFFFF for o in outs])
+    assert np.array_equal(got, ref["hists"].astype(np.int64))
+    assert [int(x) for x in snap.acc] == ref["acc"]
+    assert [int(m) for m in modes] == ref["modes"]
+    assert [list(map(int, p)) for p in pats] == ref["patterns"]
+    dg = hm.diag()
+    assert dg.invalid_patterns == 0 and dg.wait_timeouts == 0 and dg.merge_timeouts == 0
+    st.close()
