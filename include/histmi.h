@@ -389,8 +389,12 @@ typedef struct {
 } hist_tune_t;
 /* family: 0 = per-wavefront, 1 = lane-cyclic uniform sub-bins, 2 = pattern lookup,
  * 3 = wavefront aggregation (these four for hist_u8 / hist_batch / the server, by kernel),
- * 4 = ordered stream pushes (hist_stream_push / hist_stream_push_many). */
+ * 4 = ordered stream pushes whose chunks wait for the device's decisions (tiles handed out
+ * in chunk order), 5 = ordered stream pushes whose decisions the host knows in advance
+ * (W = 1, no change detection, a budget of rmax sub-bins for every value and a switching
+ * threshold of 0: nothing waits, and each workgroup takes one contiguous run of tiles). */
 #define HIST_TUNE_STREAM 4u
+#define HIST_TUNE_STREAM_KNOWN 5u
 hist_status_t hist_tune_set(uint32_t family, const hist_tune_t *t);
 hist_status_t hist_tune_get(uint32_t family, hist_tune_t *t);
 

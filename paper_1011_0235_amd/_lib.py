@@ -149,8 +149,9 @@ def declared_symbols():
 
 
 TUNING_PATH = os.path.join(HERE, "tuning.json")
-_FAMILIES = {"wavehist": 0, "uniform": 1, "lookup": 2, "waveagg": 3, "stream": 4}
+_FAMILIES = {"wavehist": 0, "uniform": 1, "lookup": 2, "waveagg": 3, "stream": 4, "stream_known": 5}
 TUNE_STREAM = 4
+TUNE_STREAM_KNOWN = 5
 
 
 def apply_tuning(path: str = TUNING_PATH):

@@ -29,7 +29,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 MIB = 1 << 20
-FAMILY = {"wavehist": 0, "uniform": 1, "lookup": 2, "waveagg": 3, "stream": 4}
+FAMILY = {"wavehist": 0, "uniform": 1, "lookup": 2, "waveagg": 3, "stream": 4, "stream_known": 5}
 
 
 def log(*a):
@@ -158,36 +158,51 @@ def main():
             rows[key] = round(nb / ms / 1e6, 1)
             cfgs[key] = {"S": S, "rmax": rmax, "theta_pct": theta, "lag": lag}
             log("stream", key, rows[key])
-    # the pipelined headline: the fastest configuration at a lag of at most 31 chunks
-    best = max((k for k in rows if cfgs[k]["lag"] <= 31), key=lambda k: rows[k])
+    # the pipelined stream: the fastest (S, rmax, theta) at a pipeline depth of 31 chunks (with
+    # decisions the host knows in advance every lag runs alike, so the depth is fixed rather
+    # than picked from noise)
+    best = max((k for k in rows if cfgs[k]["lag"] == 31), key=lambda k: rows[k])
     result["sweeps"]["stream"] = rows
     result["stream"] = cfgs[best]
     log("stream ->", cfgs[best])
-    # launch shape of stream pushes at that configuration: workgroups per CU x tiles per
-    # workgroup (each measured twice, in two interleaved passes, to damp run-to-run noise)
+    # launch shapes of stream pushes: workgroups per CU x tiles per workgroup (each measured
+    # twice, in two interleaved passes).  Two families: pushes whose
+    # decisions the host knows (the tuned configuration at lag 0: nothing waits, static tile
+    # runs) and pushes whose chunks wait for the device's decisions (here a moving window of
+    # 32 chunks at the tuned lag: tiles handed out in chunk order).
     c = cfgs[best]
-    shape = {}
-    for rep in range(2):
-        for bpc in (2, 3, 4):
-            for tpw in (2, 3, 4, 6):
-                hm.tune_set(FAMILY["stream"], blocks_per_cu=bpc, tiles_per_wg=tpw)
-                st = hm.Stream(W=1, theta_pct=c["theta_pct"], S=c["S"], rmax=c["rmax"], lag=c["lag"], trace_cap=0)
-                i = [0]
 
-                def f():
-                    k = i[0] & 1
-                    st.push_many(sbufs[k], d_out=souts[k], stream=hip_streams[k])
-                    i[0] += 1
-                ms = timed(torch, f, 10, hip_streams)
-                st.close()
-                shape.setdefault("bpc%d_tpw%d" % (bpc, tpw), []).append(nb / ms / 1e6)
-    rows = {k: round(float(np.mean(v)), 1) for k, v in shape.items()}
-    bk = max(rows, key=lambda k: rows[k])
-    bpc, tpw = int(bk[3]), int(bk.split("tpw")[1])
-    hm.tune_set(FAMILY["stream"], blocks_per_cu=bpc, tiles_per_wg=tpw)
-    result["families"]["stream"] = {"blocks_per_cu": bpc, "tiles_per_wg": tpw}
-    result["sweeps"]["stream_shape"] = rows
-    log("stream shape", rows, "->", bk)
+    def shape_sweep(family, make, bpcs, tpws):
+        shape = {}
+        for rep in range(2):
+            for bpc in bpcs:
+                for tpw in tpws:
+                    hm.tune_set(FAMILY[family], blocks_per_cu=bpc, tiles_per_wg=tpw)
+                    st = make()
+                    i = [0]
+
+                    def f():
+                        k = i[0] & 1
+                        st.push_many(sbufs[k], d_out=souts[k], stream=hip_streams[k])
+                        i[0] += 1
+                    ms = timed(torch, f, 10, hip_streams)
+                    st.close()
+                    shape.setdefault("bpc%d_tpw%d" % (bpc, tpw), []).append(nb / ms / 1e6)
+        # the better of the two passes: a rare stalled pass says nothing about the shape
+        rows = {k: round(float(np.max(v)), 1) for k, v in shape.items()}
+        bk = max(rows, key=lambda k: rows[k])
+        bpc, tpw = int(bk[3]), int(bk.split("tpw")[1])
+        hm.tune_set(FAMILY[family], blocks_per_cu=bpc, tiles_per_wg=tpw)
+        result["families"][family] = {"blocks_per_cu": bpc, "tiles_per_wg": tpw}
+        result["sweeps"][family + "_shape"] = rows
+        log(family, "shape", rows, "->", bk)
+
+    shape_sweep("stream_known",
+                lambda: hm.Stream(W=1, theta_pct=c["theta_pct"], S=c["S"], rmax=c["rmax"], lag=0, trace_cap=0),
+                (2, 3, 4), (1, 2, 4, 8))
+    shape_sweep("stream",
+                lambda: hm.Stream(W=32, theta_pct=c["theta_pct"], S=c["S"], rmax=c["rmax"], lag=c["lag"], trace_cap=0),
+                (2, 3, 4), (2, 3, 4, 6))
     del arenas, a0
 
     # ---- Figure 5: degenerate + uniform mixture, d = 0..100 %

@@ -19,7 +19,8 @@ namespace rt {
 
 // Defaults from the gfx950 probes: the lane-cyclic table streams best with 2 workgroups of
 // 4 wavefronts per CU and 4 loads in flight per lane.
-Tune g_tune[kFamilies] = {{4, 256, 4, 6}, {2, 256, 4, 6}, {2, 256, 4, 6}, {4, 256, 4, 6}, {3, 1024, 4, 4}};
+Tune g_tune[kFamilies] = {{4, 256, 4, 6}, {2, 256, 4, 6}, {2, 256, 4, 6}, {4, 256, 4, 6}, {3, 1024, 4, 4},
+                          {2, 1024, 4, 2}};
 uint32_t g_single_copies = 16;   // partial copies for a launch with one large segment
 
 static std::mutex g_mu;
@@ -263,7 +264,8 @@ void stream_layout(uint32_t S, uint32_t rmax, hist_mode_t mode, Params *P) {
 uint32_t lds_bytes(const Params &P) { return (P.table_words + P.look_words) * 4u + ctl_bytes(); }
 
 // Workgroups per CU: the family's tuned value, capped by what fits.
-uint32_t blocks_per_cu(uint32_t family, uint32_t lds) {
+// Workgroups of the counting kernel that fit on one CU with `lds` bytes of dynamic LDS.
+uint32_t resident_per_cu(uint32_t lds) {
   static std::mutex mu;
   static std::unordered_map<uint32_t, int> cache;   // dynamic LDS bytes -> resident workgroups per CU
   int occ = 0;
@@ -277,7 +279,11 @@ uint32_t blocks_per_cu(uint32_t family, uint32_t lds) {
     std::lock_guard<std::mutex> lk(mu);
     cache[lds] = occ;
   }
-  return std::max<uint32_t>(1, std::min<uint32_t>(g_tune[family].bpc, (uint32_t)occ));
+  return (uint32_t)occ;
+}
+
+uint32_t blocks_per_cu(uint32_t family, uint32_t lds) {
+  return std::max<uint32_t>(1, std::min<uint32_t>(g_tune[family].bpc, resident_per_cu(lds)));
 }
 
 hist_status_t run_single(DevCtx *d, Params &P, hipStream_t s) {
@@ -487,8 +493,11 @@ static bool decisions_known(const hist_stream_config_t &c) {
   }
 }
 
-static hist_status_t stream_launch_begin(hist_stream *st, hipStream_t s) {
+// Before a launch: wait for the launch two before it (at most two in flight), or, with
+// `serialize`, for both earlier ones (no overlap).
+static hist_status_t stream_launch_begin(hist_stream *st, hipStream_t s, bool serialize = false) {
   if (st->ev_used[st->evi]) TRY_HIP(hipStreamWaitEvent(s, st->ev[st->evi], 0));
+  if (serialize && st->ev_used[st->evi ^ 1u]) TRY_HIP(hipStreamWaitEvent(s, st->ev[st->evi ^ 1u], 0));
   return HIST_OK;
 }
 static hist_status_t stream_launch_end(hist_stream *st, hipStream_t s) {
@@ -771,9 +780,10 @@ static void stream_params(const hist_stream *st, Params *P) {
 
 hist_status_t hist_stream_push(hist_stream_t *st, const void *d_chunk, size_t n, hist_mode_t mode, uint32_t *d_out_k,
                                void *stream) {
-  // one chunk is a one-segment launch of the tiled kernel: every launch of an ordered
-  // stream hands its tiles out dynamically, so it completes with however many of its
-  // workgroups are resident -- which overlapping launches on other HIP streams rely on
+  // one chunk is a one-segment launch of the tiled kernel: a launch whose chunks may wait
+  // for decisions hands its tiles out dynamically, so it completes with however many of its
+  // workgroups are resident -- which overlapping launches on other HIP streams rely on (a
+  // launch with every decision known waits for nothing and plans its tiles statically)
   if (!st || (n && !d_chunk) || !mode_ok(mode)) return HIST_EINVAL;
   if ((uint64_t)n > kMaxSegBytes) return HIST_EOVERFLOW;
   const void *p = d_chunk;
@@ -800,11 +810,21 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
     stream_layout(st->cfg.S, st->cfg.rmax, mode, &P);
     stream_params(st, &P);
     P.chunk_base = st->pushed;
-    const uint32_t fam = kFamStream;
-    const uint32_t maxg = (uint32_t)d->cus * blocks_per_cu(fam, lds_bytes(P));
+    const bool known = decisions_known(st->cfg);
+    const uint32_t fam = known ? kFamStreamKnown : kFamStream;
+    // Chunks that wait for decisions spin on their CU.  Two launches of the stream may be in
+    // flight, and the hardware dispatches both at once: if they could not all be resident
+    // together, the later launch's waiting workgroups could hold the CUs that the earlier
+    // launch -- whose chunks they wait for -- needs.  So a launch that may wait takes at most
+    // half of what a CU holds; where a CU holds only one, launches of the stream do not
+    // overlap.
+    const uint32_t occ = resident_per_cu(lds_bytes(P));
+    const uint32_t bpc = known ? blocks_per_cu(fam, lds_bytes(P))
+                               : std::max<uint32_t>(1, std::min(blocks_per_cu(fam, lds_bytes(P)), occ / 2));
+    const bool serialize = !known && occ < 2;
+    const uint32_t maxg = (uint32_t)d->cus * bpc;
     // tiles small enough that the lag + 1 chunks which may run at once still fill the grid
     // (every chunk, when the host knows the decisions: then no chunk waits)
-    const bool known = decisions_known(st->cfg);
     uint64_t total = 0;
     for (uint32_t j = 0; j < m; ++j) total += h_sizes[first + j];
     const uint64_t per_chunk = std::max<uint64_t>(1, total / m);
@@ -837,12 +857,15 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
       }
     }
     MultiPlan mp;
-    TRY(plan_multi(segs, tile, maxg, false, false, &mp));
+    // Tiles are handed out in chunk order, so a chunk waiting for an earlier chunk's decision
+    // never waits on a workgroup that has not started.  When the host knows every decision
+    // nothing waits, and each workgroup takes one contiguous, cost-balanced run of tiles
+    // instead: a run crosses one or two chunk boundaries where dynamic tiles would change
+    // chunk at nearly every tile.
+    TRY(plan_multi(segs, tile, maxg, known, false, &mp));
     const uint32_t copies = std::min<uint32_t>(64, pow2ceil32(std::max<uint32_t>(1, g_tune[fam].copies)));
-    // tiles are handed out in chunk order, so a chunk waiting for an earlier chunk's decision
-    // never waits on a workgroup that has not started
-    TRY(stream_launch_begin(st, s));
-    TRY(run_multi(d, P, mp, copies, s, nullptr, true, true));
+    TRY(stream_launch_begin(st, s, serialize));
+    TRY(run_multi(d, P, mp, copies, s, nullptr, !known, true));
     TRY(stream_launch_end(st, s));
     for (uint32_t j = 0; j < m; ++j) st->recent[(st->pushed + j) % ring] = h_sizes[first + j];
     st->pushed += m;

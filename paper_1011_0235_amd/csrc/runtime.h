@@ -25,8 +25,9 @@ namespace rt {
 
 constexpr uint32_t kStaticLdsReserve = 8192;       // static LDS of the kernel (control block), with margin
 constexpr uint64_t kMaxSegBytes = 0xFFFFFFFFull;   // per-segment counts must fit the 32-bit partials
-constexpr uint32_t kFamilies = 5;                  // one tuning entry per Kind, then ordered streams
+constexpr uint32_t kFamilies = 6;                  // one tuning entry per Kind, then ordered streams
 constexpr uint32_t kFamStream = HIST_TUNE_STREAM;
+constexpr uint32_t kFamStreamKnown = HIST_TUNE_STREAM_KNOWN;
 constexpr uint32_t kMaxChunksPerLaunch = 1024;     // stream chunks in one persistent launch, at most
 
 #define TRY_HIP(x)                               \
@@ -119,6 +120,7 @@ hist_status_t select_kind(hist_mode_t mode, const hist_pattern_t *h_pat, Params 
 // Kind capacity and LDS layout of a launch whose chunks follow device-resident decisions.
 void stream_layout(uint32_t S, uint32_t rmax, hist_mode_t mode, Params *P);
 uint32_t lds_bytes(const Params &P);
+uint32_t resident_per_cu(uint32_t lds);
 uint32_t blocks_per_cu(uint32_t family, uint32_t lds);
 
 // One segment cut into one tile per workgroup.

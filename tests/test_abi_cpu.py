@@ -129,7 +129,7 @@ def test_stream_and_server_config_errors(hm):
 
 
 def test_tuning_table(hm):
-    for fam in (1, hm.TUNE_STREAM):
+    for fam in (1, hm.TUNE_STREAM, hm.TUNE_STREAM_KNOWN):
         old = hm.tune_get(fam)
         hm.tune_set(fam, blocks_per_cu=3, tile_kib=128, merge_copies=8, tiles_per_wg=5)
         t = hm.tune_get(fam)
@@ -142,7 +142,7 @@ def test_tuning_table(hm):
     with pytest.raises(hm.HistError):
         hm.tune_set(1, tiles_per_wg=65)
     with pytest.raises(hm.HistError):
-        hm.tune_set(5, blocks_per_cu=1)
+        hm.tune_set(6, blocks_per_cu=1)
 
 
 def test_struct_layouts_match_binding(hm, tmp_path):

@@ -417,3 +417,40 @@ def test_full_size_lag0_known_decisions(hm):
     dg = hm.diag()
     assert dg.invalid_patterns == 0 and dg.wait_timeouts == 0 and dg.merge_timeouts == 0
     st.close()
+
+
+def test_waiting_launches_do_not_starve(hm):
+    # Chunks that wait for decisions spin on their CU.  Two launches of a stream may be in
+    # flight and are dispatched together, so a launch that may wait must leave room for the
+    # other: with the tuned shape forced to four workgroups per CU (more than half of what a
+    # CU holds), the library still caps it.  A slow decision path (W = 32, the paper's
+    # 960-entry budget, the collision criterion) over two HIP streams must finish with no
+    # decision wait timing out, and every trace exact.
+    chunks = config2_like(4 << 20)
+    hists = [O.hist(c) for c in chunks] * 3
+    W, theta, S, rmax, lag = 32, 100, 960, 8, 31
+    ref = O.stream_reference(None, W=W, theta_pct=theta, S=S, rmax=rmax, lag=lag, hists=hists, criterion=1,
+                             kappa_pct=3)
+    d = dev(np.concatenate(chunks))
+    base = int(d.data_ptr())
+    bufs = [(base + k * (4 << 20), 4 << 20) for k in range(len(chunks))]
+    outs = [torch.full((len(chunks), 256), -1, dtype=torch.int32, device="cuda") for _ in range(3)]
+    old = hm.tune_get(hm.TUNE_STREAM)
+    hm.tune_set(hm.TUNE_STREAM, blocks_per_cu=4, tiles_per_wg=3)
+    try:
+        d0 = int(hm.diag().wait_timeouts)
+        st = hm.Stream(W=W, theta_pct=theta, S=S, rmax=rmax, lag=lag, trace_cap=len(hists), criterion=1, kappa_pct=3)
+        torch.cuda.synchronize()
+        hs = [torch.cuda.Stream(), torch.cuda.Stream()]
+        for r in range(3):
+            st.push_many(bufs, d_out=outs[r], stream=hs[r & 1])
+        snap, modes, pats = st.read(len(hists), stream=hs[0])
+        torch.cuda.synchronize()
+        st.close()
+    finally:
+        hm.tune_set(hm.TUNE_STREAM, old.blocks_per_cu, old.tile_kib, old.merge_copies, old.tiles_per_wg)
+    got = np.concatenate([o.cpu().numpy().astype(np.int64) & 0xFFFFFFFF for o in outs])
+    assert np.array_equal(got, ref["hists"].astype(np.int64))
+    assert int(hm.diag().wait_timeouts) == d0
+    assert [int(m) for m in modes] == ref["modes"]
+    assert [list(map(int, p)) for p in pats] == ref["patterns"]
