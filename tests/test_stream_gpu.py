@@ -391,6 +391,101 @@ def test_decisions_known_in_advance(hm, lag, criterion, theta, kappa, S, rmax):
     st.close()
 
 
+def with_empty_runs(chunks, run, at):
+    """Insert `run` empty chunks before each index in `at` (windows of up to `run` chunks then
+    hold no byte, so the switch picks the per-wavefront kernel)."""
+    out = []
+    for k, c in enumerate(chunks):
+        if k in at:
+            out.extend(np.zeros(0, dtype=np.uint8) for _ in range(run))
+        out.append(c)
+    return out
+
+
+@pytest.mark.parametrize("W,lag,alarm,criterion,theta,kappa", [
+    (2, 0, 0, 0, 0, 0), (3, 2, 0, 2, 30, 0), (32, 0, 5, 0, 0, 0), (5, 1, 3, 1, 100, 0), (1, 0, 4, 0, 0, 0)])
+def test_window_empty_runs_and_alarms(hm, W, lag, alarm, criterion, theta, kappa):
+    # A moving window (or change detection, which sequences the chunks too) with a saturated
+    # budget and a test that fires for any non-empty window: runs of empty chunks longer than
+    # the window empty it, so some decisions are the per-wavefront kernel.  Pushes of uneven
+    # sizes over two HIP streams; every trace, the window, the Accumulator and the alarms must
+    # be the oracle's.
+    S, rmax = 8192, 32
+    chunks = with_empty_runs(mixed_chunks(2100 + W * 3 + lag, 120, 100_000), W + 2, {30, 77})
+    ref = O.stream_reference(chunks, W=W, theta_pct=theta, S=S, rmax=rmax, lag=lag, criterion=criterion,
+                             kappa_pct=kappa, alarm_pct=alarm)
+    assert O.MODE_WAVEHIST in ref["modes"][lag + 1:] and O.MODE_AHIST in ref["modes"]
+    st = hm.Stream(W=W, theta_pct=theta, S=S, rmax=rmax, lag=lag, trace_cap=len(chunks), criterion=criterion,
+                   kappa_pct=kappa, alarm_pct=alarm)
+    ds = [dev(c) if c.size else None for c in chunks]
+    outs = torch.full((len(chunks), 256), -1, dtype=torch.int32, device="cuda")
+    bufs = [(int(x.data_ptr()) if x is not None else 0, c.size) for x, c in zip(ds, chunks)]
+    torch.cuda.synchronize()
+    hs = [torch.cuda.Stream(), torch.cuda.Stream()]
+    k, call = 0, 0
+    while k < len(chunks):
+        n = min(len(chunks) - k, (1, 37, 3, 66)[call % 4])
+        st.push_many(bufs[k:k + n], d_out=outs[k:k + n], stream=hs[call & 1])
+        k += n
+        call += 1
+    snap, modes, pats = st.read(len(chunks), stream=hs[0])
+    alarms = st.read_alarms(len(chunks), stream=hs[0]) if alarm else None
+    torch.cuda.synchronize()
+    assert np.array_equal(outs.cpu().numpy().astype(np.int64) & 0xFFFFFFFF, ref["hists"].astype(np.int64))
+    assert [int(x) for x in snap.acc] == ref["acc"]
+    assert [int(x) for x in snap.mw] == ref["mw"]
+    assert [int(m) for m in modes] == ref["modes"]
+    assert [list(map(int, p)) for p in pats] == ref["patterns"]
+    assert int(snap.next_mode) == O.decide_mode(ref["mw"], theta, criterion, kappa)
+    if alarm:
+        assert [int(a) for a in alarms] == ref["alarms"]
+        assert int(snap.alarms) == sum(ref["alarms"])
+    d = hm.diag()
+    assert d.invalid_patterns == 0 and d.wait_timeouts == 0 and d.merge_timeouts == 0
+    st.close()
+
+
+def test_window_ring_wraps(hm):
+    # The sequencer's ring of recent histograms holds W + lag + 66 chunks; a chunk reuses a
+    # slot only after its decision, which comes after the slot's old chunk has left the
+    # window.  Push 5000 small chunks (pushes larger than one launch's 1024 chunks, over two
+    # HIP streams, no synchronisation) so that the ring wraps dozens of times, and check every
+    # histogram, the alarms and the final window.
+    g = np.random.default_rng(515)
+    # uniform bytes, every eleventh chunk empty, and bursts of a constant value (alarms)
+    chunks = [np.zeros(0, dtype=np.uint8) if k % 11 == 0 else
+              G.constant_bytes(int(n), 7) if k % 97 < 8 else G.uniform_bytes(int(n), g)
+              for k, n in enumerate(g.integers(1, 3000, 5000))]
+    W, lag, S, rmax = 7, 0, 8192, 32
+    ref = O.stream_reference(chunks, W=W, theta_pct=0, S=S, rmax=rmax, lag=lag, alarm_pct=20)
+    st = hm.Stream(W=W, theta_pct=0, S=S, rmax=rmax, lag=lag, trace_cap=len(chunks), alarm_pct=20)
+    arena = dev(np.concatenate(chunks))
+    base, pos, bufs = int(arena.data_ptr()), 0, []
+    for c in chunks:
+        bufs.append((base + pos, c.size))
+        pos += c.size
+    outs = torch.full((len(chunks), 256), -1, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    hs = [torch.cuda.Stream(), torch.cuda.Stream()]
+    k, call = 0, 0
+    while k < len(chunks):
+        n = min(len(chunks) - k, (1500, 700, 2100)[call % 3])
+        st.push_many(bufs[k:k + n], d_out=outs[k:k + n], stream=hs[call & 1])
+        k += n
+        call += 1
+    snap, modes, _ = st.read(len(chunks), stream=hs[0])
+    alarms = st.read_alarms(len(chunks), stream=hs[0])
+    torch.cuda.synchronize()
+    assert np.array_equal(outs.cpu().numpy().astype(np.int64) & 0xFFFFFFFF, ref["hists"].astype(np.int64))
+    assert [int(x) for x in snap.mw] == ref["mw"]
+    assert [int(x) for x in snap.acc] == ref["acc"]
+    assert [int(m) for m in modes] == ref["modes"]
+    assert [int(a) for a in alarms] == ref["alarms"]
+    d = hm.diag()
+    assert d.invalid_patterns == 0 and d.wait_timeouts == 0 and d.merge_timeouts == 0
+    st.close()
+
+
 def test_full_size_lag0_known_decisions(hm):
     # the config-2 stream at lag 0 (chunk k + 1's pattern from chunk k) with the tuned switch:
     # three pushes over two HIP streams, exact against the oracle
