@@ -382,17 +382,19 @@ hist_status_t hist_read_probe(const void *d_in, size_t n_bytes, uint64_t *d_sum,
 /* Launch shape of one kernel family.  Zero fields keep the built-in default. */
 typedef struct {
     uint32_t blocks_per_cu;   /* persistent workgroups per compute unit */
-    uint32_t tile_kib;        /* largest tile of a multi-buffer launch in KiB (multiple of 16) */
+    uint32_t tile_kib;        /* largest tile of a multi-buffer launch in KiB (multiple of 16, 16..1048576) */
     uint32_t merge_copies;    /* partial-histogram copies a segment spreads its merge over (power of 2) */
     uint32_t tiles_per_wg;    /* multi-buffer launches: tiles are made small enough that every
-                                 workgroup gets about this many (1..64) */
+                                 workgroup gets about this many (1..64); launches that never
+                                 wait give each workgroup one equal share of the bytes, cut
+                                 into tiles at chunk boundaries, and family 5 ignores it */
 } hist_tune_t;
 /* family: 0 = per-wavefront, 1 = lane-cyclic uniform sub-bins, 2 = pattern lookup,
  * 3 = wavefront aggregation (these four for hist_u8 / hist_batch / the server, by kernel),
  * 4 = ordered stream pushes whose chunks wait for the device's decisions (tiles handed out
  * in chunk order), 5 = ordered stream pushes whose decisions the host knows in advance
  * (W = 1, no change detection, a budget of rmax sub-bins for every value and a switching
- * threshold of 0: nothing waits, and each workgroup takes one contiguous run of tiles). */
+ * threshold of 0: nothing waits, and each workgroup takes one equal share of the bytes). */
 #define HIST_TUNE_STREAM 4u
 #define HIST_TUNE_STREAM_KNOWN 5u
 hist_status_t hist_tune_set(uint32_t family, const hist_tune_t *t);

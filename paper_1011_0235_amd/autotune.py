@@ -166,10 +166,11 @@ def main():
     result["stream"] = cfgs[best]
     log("stream ->", cfgs[best])
     # launch shapes of stream pushes: workgroups per CU x tiles per workgroup (each measured
-    # twice, in two interleaved passes).  Two families: pushes whose
-    # decisions the host knows (the tuned configuration at lag 0: nothing waits, static tile
-    # runs) and pushes whose chunks wait for the device's decisions (here a moving window of
-    # 32 chunks at the tuned lag: tiles handed out in chunk order).
+    # twice, in two interleaved passes).  Two families: pushes whose decisions the host knows
+    # (the tuned configuration at lag 0: nothing waits, one equal share of the bytes per
+    # workgroup, so only the workgroups per CU matter) and pushes whose chunks wait for the
+    # device's decisions (here a moving window of 32 chunks at the tuned lag: tiles handed
+    # out in chunk order).
     c = cfgs[best]
 
     def shape_sweep(family, make, bpcs, tpws):
@@ -199,7 +200,7 @@ def main():
 
     shape_sweep("stream_known",
                 lambda: hm.Stream(W=1, theta_pct=c["theta_pct"], S=c["S"], rmax=c["rmax"], lag=0, trace_cap=0),
-                (2, 3, 4), (1, 2, 4, 8))
+                (2, 3, 4), (1,))
     shape_sweep("stream",
                 lambda: hm.Stream(W=32, theta_pct=c["theta_pct"], S=c["S"], rmax=c["rmax"], lag=c["lag"], trace_cap=0),
                 (2, 3, 4), (2, 3, 4, 6))

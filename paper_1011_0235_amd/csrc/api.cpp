@@ -311,8 +311,62 @@ hist_status_t run_single(DevCtx *d, Params &P, hipStream_t s) {
   return dev_err(launch_hist(P, sh, s));
 }
 
-hist_status_t plan_multi(std::vector<SegDesc> &segs, uint64_t tile, uint32_t max_grid, bool balanced, bool guided,
-                         MultiPlan *mp) {
+hist_status_t plan_split(std::vector<SegDesc> &segs, uint64_t tile, uint32_t max_grid, MultiPlan *mp) {
+  constexpr uint64_t kQuantum = 16384, kSwitchBytes = 65536;
+  const uint32_t n = (uint32_t)segs.size();
+  uint64_t total = 0, bytes = 0;
+  for (uint32_t j = 0; j < n; ++j) {
+    if (segs[j].size > kMaxSegBytes) return HIST_EOVERFLOW;
+    if (segs[j].size && !segs[j].ptr) return HIST_EINVAL;
+    total += segs[j].size + kSwitchBytes;
+    bytes += segs[j].size;
+  }
+  tile = std::max<uint64_t>(kQuantum, std::min<uint64_t>(tile, 1ull << 30));
+  const uint32_t G = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(max_grid, ceil_div(bytes, kQuantum)));
+  auto share_end = [&](uint32_t g) { return g + 1 >= G ? total : total / G * (g + 1) + total % G * (g + 1) / G; };
+  std::vector<TileRec> recs;
+  std::vector<uint32_t> owner;
+  recs.reserve((size_t)n + G + (size_t)(bytes / tile) + 1);
+  owner.reserve(recs.capacity());
+  uint64_t at = 0;   // the segment's start on the cost axis
+  uint32_t g = 0;    // the workgroup whose share holds the current position
+  for (uint32_t j = 0; j < n; ++j) {
+    segs[j].tile0 = (uint32_t)recs.size();
+    const uint64_t base = at + kSwitchBytes, sz = segs[j].size;
+    uint64_t off = 0;
+    do {   // an empty segment still gets one (empty) tile, so that it is finalized
+      while (g + 1 < G && share_end(g) <= base + off) ++g;
+      const uint64_t end = share_end(g);
+      const uint64_t cut = end > base ? ceil_div(end - base, kQuantum) * kQuantum : off + kQuantum;
+      const uint64_t len = std::min<uint64_t>({sz - off, tile, std::max<uint64_t>(cut, off + kQuantum) - off});
+      recs.push_back(TileRec{reinterpret_cast<uint64_t>(segs[j].ptr) + off, (uint32_t)len, j});
+      owner.push_back(g);
+      off += len;
+      if (recs.size() >= 0x7FFFFFFFull) return HIST_EOVERFLOW;
+    } while (off < sz);
+    segs[j].ntiles = (uint32_t)recs.size() - segs[j].tile0;
+    at = base + sz;
+  }
+  const uint32_t ntiles = (uint32_t)recs.size();
+  mp->nseg = n;
+  mp->ntiles = ntiles;
+  mp->grid = G;
+  mp->seg_bytes = ((size_t)n * sizeof(SegDesc) + 15) & ~(size_t)15;
+  mp->rec_bytes = (size_t)ntiles * sizeof(TileRec);
+  mp->blob.assign(mp->seg_bytes + mp->rec_bytes + ((size_t)G + 1) * 4, 0);
+  std::memcpy(mp->blob.data(), segs.data(), (size_t)n * sizeof(SegDesc));
+  std::memcpy(mp->blob.data() + mp->seg_bytes, recs.data(), mp->rec_bytes);
+  uint32_t *bounds = reinterpret_cast<uint32_t *>(mp->blob.data() + mp->seg_bytes + mp->rec_bytes);
+  // owners never decrease along the tiles: workgroup w runs tiles [bounds[w], bounds[w + 1])
+  uint32_t i = 0;
+  for (uint32_t w = 0; w <= G; ++w) {
+    while (i < ntiles && owner[i] < w) ++i;
+    bounds[w] = (w == G) ? ntiles : i;
+  }
+  return HIST_OK;
+}
+
+hist_status_t plan_multi(std::vector<SegDesc> &segs, uint64_t tile, uint32_t max_grid, MultiPlan *mp) {
   constexpr uint64_t kQuantum = 16384;
   const uint32_t n = (uint32_t)segs.size();
   tile = std::max<uint64_t>(kQuantum, std::min<uint64_t>(tile, 1ull << 30));
@@ -324,23 +378,14 @@ hist_status_t plan_multi(std::vector<SegDesc> &segs, uint64_t tile, uint32_t max
   }
   std::vector<TileRec> recs;
   recs.reserve((size_t)n + (size_t)(total / tile) + 1);
-  uint64_t done = 0;   // bytes in the tiles before the current one
   for (uint32_t j = 0; j < n; ++j) {
     segs[j].tile0 = (uint32_t)recs.size();
     const uint64_t sz = segs[j].size;
     uint64_t off = 0;
     do {   // an empty segment still gets one (empty) tile, so that it is finalized
-      uint64_t tb = tile;
-      if (guided) {
-        // the last bytes of the launch go in smaller tiles, so that the workgroups run out of
-        // work at about the same time: a tile is at most 1/(2G) of what remains
-        const uint64_t want = ceil_div(ceil_div(total - done, (uint64_t)max_grid * 2), kQuantum) * kQuantum;
-        tb = std::min<uint64_t>(tile, std::max<uint64_t>(kQuantum, want));
-      }
-      const uint64_t len = std::min<uint64_t>(tb, sz - off);
+      const uint64_t len = std::min<uint64_t>(tile, sz - off);
       recs.push_back(TileRec{reinterpret_cast<uint64_t>(segs[j].ptr) + off, (uint32_t)len, j});
       off += len;
-      done += len;
       if (recs.size() >= 0x7FFFFFFFull) return HIST_EOVERFLOW;
     } while (off < sz);
     segs[j].ntiles = (uint32_t)recs.size() - segs[j].tile0;
@@ -352,23 +397,10 @@ hist_status_t plan_multi(std::vector<SegDesc> &segs, uint64_t tile, uint32_t max
   mp->grid = G;
   mp->seg_bytes = ((size_t)n * sizeof(SegDesc) + 15) & ~(size_t)15;
   mp->rec_bytes = (size_t)ntiles * sizeof(TileRec);
+  // dynamic launches take tiles from the counter; the (unused) bounds are left zero
   mp->blob.assign(mp->seg_bytes + mp->rec_bytes + ((size_t)G + 1) * 4, 0);
   std::memcpy(mp->blob.data(), segs.data(), (size_t)n * sizeof(SegDesc));
   std::memcpy(mp->blob.data() + mp->seg_bytes, recs.data(), mp->rec_bytes);
-  uint32_t *bounds = reinterpret_cast<uint32_t *>(mp->blob.data() + mp->seg_bytes + mp->rec_bytes);
-  if (balanced) {
-    // contiguous tile ranges of about equal cost, one per workgroup (a tile also costs its
-    // staging and merge)
-    std::vector<uint64_t> wcum((size_t)ntiles + 1, 0);
-    for (uint32_t i = 0; i < ntiles; ++i) wcum[i + 1] = wcum[i] + recs[i].len + 8192;
-    const uint64_t cost = wcum[ntiles];
-    uint32_t k = 0;
-    for (uint32_t g = 0; g <= G; ++g) {
-      const uint64_t target = (g == G) ? cost : (cost * g) / G;
-      while (k < ntiles && wcum[k] < target) ++k;
-      bounds[g] = (g == G) ? ntiles : k;
-    }
-  }
   return HIST_OK;
 }
 
@@ -656,7 +688,7 @@ static hist_status_t batch_prepare(const void *const *h_ptrs, const uint64_t *h_
     segs[j].out = d_out + (size_t)j * 256;
     segs[j].chunk = -1;
   }
-  TRY(plan_multi(segs, tile, maxg, true, false, mp));
+  TRY(plan_split(segs, tile, maxg, mp));
   *copies = std::min<uint32_t>(64, pow2ceil32(std::max<uint32_t>(1, g_tune[fam].copies)));
   return HIST_OK;
 }
@@ -823,8 +855,8 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
                                : std::max<uint32_t>(1, std::min(blocks_per_cu(fam, lds_bytes(P)), occ / 2));
     const bool serialize = !known && occ < 2;
     const uint32_t maxg = (uint32_t)d->cus * bpc;
-    // tiles small enough that the lag + 1 chunks which may run at once still fill the grid
-    // (every chunk, when the host knows the decisions: then no chunk waits)
+    // launches that may wait: tiles small enough that the lag + 1 chunks which may run at
+    // once still fill the grid
     uint64_t total = 0;
     for (uint32_t j = 0; j < m; ++j) total += h_sizes[first + j];
     const uint64_t per_chunk = std::max<uint64_t>(1, total / m);
@@ -859,10 +891,14 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
     MultiPlan mp;
     // Tiles are handed out in chunk order, so a chunk waiting for an earlier chunk's decision
     // never waits on a workgroup that has not started.  When the host knows every decision
-    // nothing waits, and each workgroup takes one contiguous, cost-balanced run of tiles
-    // instead: a run crosses one or two chunk boundaries where dynamic tiles would change
-    // chunk at nearly every tile.
-    TRY(plan_multi(segs, tile, maxg, known, false, &mp));
+    // nothing waits, and each workgroup takes one equal share of the launch's bytes instead:
+    // a share crosses one or two chunk boundaries where dynamic tiles would change chunk at
+    // nearly every tile, and equal shares end together where whole tiles would leave some
+    // workgroups a tile more than others.
+    if (known)
+      TRY(plan_split(segs, (uint64_t)g_tune[fam].tile_kib * 1024, maxg, &mp));
+    else
+      TRY(plan_multi(segs, tile, maxg, &mp));
     const uint32_t copies = std::min<uint32_t>(64, pow2ceil32(std::max<uint32_t>(1, g_tune[fam].copies)));
     TRY(stream_launch_begin(st, s, serialize));
     TRY(run_multi(d, P, mp, copies, s, nullptr, !known, true));

@@ -135,11 +135,16 @@ struct MultiPlan {
   size_t seg_bytes = 0;
   size_t rec_bytes = 0;
 };
-// segs: ptr/size/out/acc/chunk/stream_idx filled; tile0/ntiles are filled here.  Tiles are
-// at most `tile` bytes; `guided` shrinks them towards the end of the launch (for dynamic
-// launches); `balanced` writes contiguous per-workgroup tile ranges (for static launches).
-hist_status_t plan_multi(std::vector<SegDesc> &segs, uint64_t tile, uint32_t max_grid, bool balanced, bool guided,
-                         MultiPlan *mp);
+// segs: ptr/size/out/acc/chunk/stream_idx filled; tile0/ntiles are filled here.
+// Launches whose chunks may wait: tiles of at most `tile` bytes, in segment order, handed out
+// by the launch's counter.
+hist_status_t plan_multi(std::vector<SegDesc> &segs, uint64_t tile, uint32_t max_grid, MultiPlan *mp);
+// Static launches that never wait: one equal share of the launch's bytes per workgroup,
+// cut at 16 KiB steps from each segment's start into tiles of at most `tile` bytes.  Each
+// segment also costs its workgroups a switch (flush, merge, next descriptor), about what
+// one workgroup counts in 4-5 us, so a segment's start is charged 64 KiB on the axis the
+// shares are cut from.
+hist_status_t plan_split(std::vector<SegDesc> &segs, uint64_t tile, uint32_t max_grid, MultiPlan *mp);
 // own: a dedicated scratch (already sized, descriptors already on the device) or nullptr.
 hist_status_t run_multi(DevCtx *d, Params &P, const MultiPlan &mp, uint32_t copies, hipStream_t s, Scratch *own,
                         bool dynamic, bool upload);

@@ -101,7 +101,7 @@ bool hist_server::launch(Slot &sl, std::vector<uint64_t> &batch) {
   const uint64_t tile = (uint64_t)g_tune[fam].tile_kib * 1024;
   const uint32_t maxg = (uint32_t)d->cus * blocks_per_cu(fam, lds_bytes(P));
   MultiPlan mp;
-  if (plan_multi(segs, tile, maxg, true, false, &mp) != HIST_OK) return false;
+  if (plan_split(segs, tile, maxg, &mp) != HIST_OK) return false;
   const uint32_t copies = std::min<uint32_t>(64, pow2ceil32(std::max<uint32_t>(1, g_tune[fam].copies)));
   hipStream_t s = hs[sl.hs];
   if (run_multi(d, P, mp, copies, s, &sl.sc, false, true) != HIST_OK) return false;
