@@ -557,10 +557,13 @@ def main():
             secs += t
             reps += 1
         assert np.array_equal(h.astype(np.int64), exp.sum(axis=0))
+        # one thread too: the median of five passes
+        one = sorted(O.hist_timed(host, 1)[0] for _ in range(5))[2]
         res["cpu_baseline"] = {"value": round(nbytes * reps / secs / 1e9, 3), "unit": "GB/s", "cores": threads,
                                "kind": "oracle",
                                "sample": "the same 264 MiB stream bytes in host RAM, %d passes of the plain C "
-                                         "counting loop split over %d threads (%.1f s wall)" % (reps, threads, secs)}
+                                         "counting loop split over %d threads (%.1f s wall)" % (reps, threads, secs),
+                               "single_thread_GBps": round(nbytes / one / 1e9, 3)}
 
     if not args.no_extras:
         extras = {}

@@ -1,0 +1,106 @@
+// Tile plans of multi-segment launches (host side): which tiles a launch has, and for
+// static launches which workgroup runs which of them.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "runtime.h"
+
+namespace histmi {
+namespace rt {
+
+hist_status_t plan_split(std::vector<SegDesc> &segs, uint64_t tile, uint32_t max_grid, MultiPlan *mp) {
+  constexpr uint64_t kQuantum = 16384, kSwitchBytes = 65536;
+  const uint32_t n = (uint32_t)segs.size();
+  uint64_t total = 0, bytes = 0;
+  for (uint32_t j = 0; j < n; ++j) {
+    if (segs[j].size > kMaxSegBytes) return HIST_EOVERFLOW;
+    if (segs[j].size && !segs[j].ptr) return HIST_EINVAL;
+    total += segs[j].size + kSwitchBytes;
+    bytes += segs[j].size;
+  }
+  tile = std::max<uint64_t>(kQuantum, std::min<uint64_t>(tile, 1ull << 30));
+  const uint32_t G = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(max_grid, ceil_div(bytes, kQuantum)));
+  auto share_end = [&](uint32_t g) { return g + 1 >= G ? total : total / G * (g + 1) + total % G * (g + 1) / G; };
+  std::vector<TileRec> recs;
+  std::vector<uint32_t> owner;
+  recs.reserve((size_t)n + G + (size_t)(bytes / tile) + 1);
+  owner.reserve(recs.capacity());
+  uint64_t at = 0;   // the segment's start on the cost axis
+  uint32_t g = 0;    // the workgroup whose share holds the current position
+  for (uint32_t j = 0; j < n; ++j) {
+    segs[j].tile0 = (uint32_t)recs.size();
+    const uint64_t base = at + kSwitchBytes, sz = segs[j].size;
+    uint64_t off = 0;
+    do {   // an empty segment still gets one (empty) tile, so that it is finalized
+      while (g + 1 < G && share_end(g) <= base + off) ++g;
+      const uint64_t end = share_end(g);
+      const uint64_t cut = end > base ? ceil_div(end - base, kQuantum) * kQuantum : off + kQuantum;
+      const uint64_t len = std::min<uint64_t>({sz - off, tile, std::max<uint64_t>(cut, off + kQuantum) - off});
+      recs.push_back(TileRec{reinterpret_cast<uint64_t>(segs[j].ptr) + off, (uint32_t)len, j});
+      owner.push_back(g);
+      off += len;
+      if (recs.size() >= 0x7FFFFFFFull) return HIST_EOVERFLOW;
+    } while (off < sz);
+    segs[j].ntiles = (uint32_t)recs.size() - segs[j].tile0;
+    at = base + sz;
+  }
+  const uint32_t ntiles = (uint32_t)recs.size();
+  mp->nseg = n;
+  mp->ntiles = ntiles;
+  mp->grid = G;
+  mp->seg_bytes = ((size_t)n * sizeof(SegDesc) + 15) & ~(size_t)15;
+  mp->rec_bytes = (size_t)ntiles * sizeof(TileRec);
+  mp->blob.assign(mp->seg_bytes + mp->rec_bytes + ((size_t)G + 1) * 4, 0);
+  std::memcpy(mp->blob.data(), segs.data(), (size_t)n * sizeof(SegDesc));
+  std::memcpy(mp->blob.data() + mp->seg_bytes, recs.data(), mp->rec_bytes);
+  uint32_t *bounds = reinterpret_cast<uint32_t *>(mp->blob.data() + mp->seg_bytes + mp->rec_bytes);
+  // owners never decrease along the tiles: workgroup w runs tiles [bounds[w], bounds[w + 1])
+  uint32_t i = 0;
+  for (uint32_t w = 0; w <= G; ++w) {
+    while (i < ntiles && owner[i] < w) ++i;
+    bounds[w] = (w == G) ? ntiles : i;
+  }
+  return HIST_OK;
+}
+
+hist_status_t plan_multi(std::vector<SegDesc> &segs, uint64_t tile, uint32_t max_grid, MultiPlan *mp) {
+  constexpr uint64_t kQuantum = 16384;
+  const uint32_t n = (uint32_t)segs.size();
+  tile = std::max<uint64_t>(kQuantum, std::min<uint64_t>(tile, 1ull << 30));
+  uint64_t total = 0;
+  for (uint32_t j = 0; j < n; ++j) {
+    if (segs[j].size > kMaxSegBytes) return HIST_EOVERFLOW;
+    if (segs[j].size && !segs[j].ptr) return HIST_EINVAL;
+    total += segs[j].size;
+  }
+  std::vector<TileRec> recs;
+  recs.reserve((size_t)n + (size_t)(total / tile) + 1);
+  for (uint32_t j = 0; j < n; ++j) {
+    segs[j].tile0 = (uint32_t)recs.size();
+    const uint64_t sz = segs[j].size;
+    uint64_t off = 0;
+    do {   // an empty segment still gets one (empty) tile, so that it is finalized
+      const uint64_t len = std::min<uint64_t>(tile, sz - off);
+      recs.push_back(TileRec{reinterpret_cast<uint64_t>(segs[j].ptr) + off, (uint32_t)len, j});
+      off += len;
+      if (recs.size() >= 0x7FFFFFFFull) return HIST_EOVERFLOW;
+    } while (off < sz);
+    segs[j].ntiles = (uint32_t)recs.size() - segs[j].tile0;
+  }
+  const uint32_t ntiles = (uint32_t)recs.size();
+  const uint32_t G = std::max<uint32_t>(1, std::min<uint32_t>(max_grid, ntiles));
+  mp->nseg = n;
+  mp->ntiles = ntiles;
+  mp->grid = G;
+  mp->seg_bytes = ((size_t)n * sizeof(SegDesc) + 15) & ~(size_t)15;
+  mp->rec_bytes = (size_t)ntiles * sizeof(TileRec);
+  // dynamic launches take tiles from the counter; the (unused) bounds are left zero
+  mp->blob.assign(mp->seg_bytes + mp->rec_bytes + ((size_t)G + 1) * 4, 0);
+  std::memcpy(mp->blob.data(), segs.data(), (size_t)n * sizeof(SegDesc));
+  std::memcpy(mp->blob.data() + mp->seg_bytes, recs.data(), mp->rec_bytes);
+  return HIST_OK;
+}
+
+}  // namespace rt
+}  // namespace histmi
