@@ -762,16 +762,18 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
                                : std::max<uint32_t>(1, std::min(blocks_per_cu(fam, lds_bytes(P)), occ / 2));
     const bool serialize = !known && occ < 2;
     const uint32_t maxg = (uint32_t)d->cus * bpc;
-    // launches that may wait: tiles small enough that the lag + 1 chunks which may run at
-    // once still fill the grid
-    uint64_t total = 0;
-    for (uint32_t j = 0; j < m; ++j) total += h_sizes[first + j];
-    const uint64_t per_chunk = std::max<uint64_t>(1, total / m);
-    const uint64_t inflight = known ? m : (uint64_t)std::min<uint32_t>(st->cfg.lag + 1, m);
+    // the largest tile; launches that may wait cut tiles small enough that the lag + 1 chunks
+    // which may run at once still fill the grid
     uint64_t tile = (uint64_t)g_tune[fam].tile_kib * 1024;
-    const uint64_t fill = ceil_div(per_chunk * inflight, maxg);     // lag + 1 chunks cover the grid
-    const uint64_t several = ceil_div(total, (uint64_t)maxg * g_tune[fam].tpw);   // tiles per workgroup
-    tile = std::min<uint64_t>(tile, std::max<uint64_t>(16384, ceil_div(std::min(fill, several), 16384) * 16384));
+    if (!known) {
+      uint64_t total = 0;
+      for (uint32_t j = 0; j < m; ++j) total += h_sizes[first + j];
+      const uint64_t per_chunk = std::max<uint64_t>(1, total / m);
+      const uint64_t inflight = std::min<uint32_t>(st->cfg.lag + 1, m);
+      const uint64_t fill = ceil_div(per_chunk * inflight, maxg);     // lag + 1 chunks cover the grid
+      const uint64_t several = ceil_div(total, (uint64_t)maxg * g_tune[fam].tpw);   // tiles per workgroup
+      tile = std::min<uint64_t>(tile, std::max<uint64_t>(16384, ceil_div(std::min(fill, several), 16384) * 16384));
+    }
     std::vector<SegDesc> segs(m);
     const uint32_t ring = st->cfg.lag + 1;
     const uint32_t lgmax = log2u(st->cfg.rmax);
@@ -803,7 +805,7 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
     // nearly every tile, and equal shares end together where whole tiles would leave some
     // workgroups a tile more than others.
     if (known)
-      TRY(plan_split(segs, (uint64_t)g_tune[fam].tile_kib * 1024, maxg, &mp));
+      TRY(plan_split(segs, tile, maxg, &mp));
     else
       TRY(plan_multi(segs, tile, maxg, &mp));
     const uint32_t copies = std::min<uint32_t>(64, pow2ceil32(std::max<uint32_t>(1, g_tune[fam].copies)));
