@@ -406,8 +406,8 @@ def main():
         lds_probe()
         return
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(each GPU would take whole streams or images; see DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
+              "(sharded, each GPU would take whole streams, or images of a batch)", file=sys.stderr)
         sys.exit(2)
 
     import torch
