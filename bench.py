@@ -102,7 +102,7 @@ def profiled_traffic():
     for f in ("kernels.hip", "histmi_dev.h"):
         with open(os.path.join(ROOT, "paper_1011_0235_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    p = os.path.join(ROOT, "profiles", "hist_main_stream_config2.md")
+    p = os.path.join(ROOT, "profiles", "hist_main_stream_66x4MiB.md")
     if not os.path.exists(p):
         return None
     text = open(p).read()
@@ -426,7 +426,7 @@ def main():
     S = tune["S"] if args.S is None else args.S
     rmax = tune["rmax"] if args.rmax is None else args.rmax
 
-    # ---- inputs: the config-2 stream, four copies resident in HBM (1.03 GiB), used in turn so
+    # ---- inputs: the single stream, four copies resident in HBM (1.03 GiB), used in turn so
     # that no step reads bytes read in the last 792 MiB (the device cache is 256 MB)
     chunks = G.stream_chunks(4 * MIB)
     host = np.concatenate(chunks)
@@ -600,7 +600,7 @@ def main():
                 row["alarms"] = int(snap.alarms)
             st.close()
             extras[name] = row
-        # one 1 MiB image (config 1): latency of one call, back to back
+        # one 1 MiB image: latency of one call, back to back
         x = torch.from_numpy(G.image_1mib()).to(dev)
         o1 = torch.zeros(256, dtype=torch.int32, device=dev)
         for mode, nm in ((hm.MODE_AUTO, "auto"), (hm.MODE_WAVEHIST, "wavehist"), (hm.MODE_AHIST, "ahist_identity")):
@@ -637,10 +637,10 @@ def main():
             t2[kind] = row
             del xs
         extras["table2_64mib_GBps"] = t2
-        extras["xray_config3"] = bench_xray(hm, G, O, torch, dev, hip_streams, S, rmax, lag, plag, theta)
-        extras["host_ingest_config2"] = bench_ingest(hm, G, O, torch, dev)
-        extras["batched_config4"] = bench_batched(hm, G, O, torch, dev, stream)
-        extras["served_config5"] = bench_served(hm, G, O, torch, dev, stream)
+        extras["xray_frames_512x4MiB"] = bench_xray(hm, G, O, torch, dev, hip_streams, S, rmax, lag, plag, theta)
+        extras["host_ingest_stream"] = bench_ingest(hm, G, O, torch, dev)
+        extras["batched_4096_images"] = bench_batched(hm, G, O, torch, dev, stream)
+        extras["served_poisson"] = bench_served(hm, G, O, torch, dev, stream)
         res["extras"] = extras
 
     print(json.dumps(res), flush=True)

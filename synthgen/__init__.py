@@ -91,7 +91,7 @@ def mixture_bytes(n: int, d: float, v: int, g: np.random.Generator) -> np.ndarra
 # ----------------------------------------------------------------------------
 
 def image_1mib() -> np.ndarray:
-    """Config 1: one 1024x1024 image of i.i.d. uniform bytes."""
+    """One 1024x1024 image of i.i.d. uniform bytes."""
     return uniform_bytes(1024 * 1024, rng(CFG_IMAGE, 0))
 
 
@@ -121,7 +121,7 @@ class ChunkSpec:
 
 
 def stream_specs() -> List[ChunkSpec]:
-    """Config 2 order: 16 x sigma 96, 16 x sigma 32, one all-127 chunk, 16 x sigma 8, one two-spike chunk, 16 x sigma 2."""
+    """The single stream's chunk order: 16 x sigma 96, 16 x sigma 32, one all-127 chunk, 16 x sigma 8, one two-spike chunk, 16 x sigma 2."""
     specs: List[ChunkSpec] = []
     specs += [ChunkSpec("normal", 96.0)] * 16
     specs += [ChunkSpec("normal", 32.0)] * 16
@@ -157,7 +157,7 @@ class FrameSpec:
 
 
 def xray_specs(count: int = 512) -> List[FrameSpec]:
-    """Config 3: mean walks mu_t = clip(mu_{t-1} + 4 N(0,1), 0, 255) from 128; sigma_t ~ U[6, 40]."""
+    """X-ray-like frames: the mean walks mu_t = clip(mu_{t-1} + 4 N(0,1), 0, 255) from 128; sigma_t ~ U[6, 40]."""
     g = rng(CFG_XRAY, 0)
     mu = 128.0
     out = []
@@ -193,7 +193,7 @@ class ImageSpec:
 
 
 def batch_specs(count: int = 4096, side_lo: int = 64, side_hi: int = 4096) -> List[ImageSpec]:
-    """Config 4: sides independent round(exp(U[ln lo, ln hi])); distribution uniform / Normal / 90% spike, 1/3 each."""
+    """Batch images: sides independent round(exp(U[ln lo, ln hi])); distribution uniform / Normal / 90% spike, 1/3 each."""
     g = rng(CFG_BATCH, 0)
     out = []
     for _ in range(count):
@@ -247,7 +247,7 @@ class Request:
 
 def serve_requests(rate_hz: float, duration_s: float, n_streams: int = 64, size_lo: int = 4096,
                    size_hi: int = 64 * MIB, pool_bytes: int = 256 * MIB, item: int = 0) -> List[Request]:
-    """Config 5: Poisson arrivals; size floor(exp(U[ln lo, ln hi])); stream id uniform; offset uniform in the pool."""
+    """Served requests: Poisson arrivals; size floor(exp(U[ln lo, ln hi])); stream id uniform; offset uniform in the pool."""
     g = rng(CFG_SERVE, item)
     out = []
     t = 0.0

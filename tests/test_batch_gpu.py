@@ -28,8 +28,8 @@ def run_batch(hm, arena, offs, sizes, mode=0, pattern=None):
 
 
 @pytest.mark.parametrize("align", [256, 1])
-def test_batch_config4_shapes(hm, align):
-    specs = G.batch_specs(96, 64, 1024)          # config-4 distributions, sides up to 1024
+def test_batch_image_shapes(hm, align):
+    specs = G.batch_specs(96, 64, 1024)          # the batch's distributions, sides up to 1024
     arena, offs, sizes = G.batch_arena(specs, align=align)
     exp = O.hist_many(arena, offs, sizes).astype(np.int64)
     for mode, pat in ((hm.MODE_AUTO, None), (hm.MODE_WAVEHIST, None), (hm.MODE_AHIST, None),
@@ -88,8 +88,8 @@ def test_batch_graph_replays(hm):
     graph.close()
 
 
-def test_batch_sampled_full_size_config4(hm):
-    # the full config-4 batch (4096 images, about 3.85 GB), generated on the device; a sample of
+def test_batch_sampled_full_size_4096_images(hm):
+    # the full 4096-image batch (4096 images, about 3.85 GB), generated on the device; a sample of
     # images is checked against the oracle one by one, and every output against sum == size
     specs = G.batch_specs(4096)
     sizes = np.array([s.size for s in specs], dtype=np.int64)

@@ -132,7 +132,7 @@ def test_untraced_chunks_still_counted(hm):
 
 
 def test_full_size_stream_with_alarms(hm):
-    # the config-2 stream (66 x 4 MiB) pushed three times at the bench's lag, W = 32, 4 points
+    # the single stream (66 x 4 MiB) pushed three times at the bench's lag, W = 32, 4 points
     # (its window departs from its Accumulator by up to about 6 points)
     chunks = G.stream_chunks(4 << 20)
     hists = [O.hist(c) for c in chunks] * 3

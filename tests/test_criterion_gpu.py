@@ -103,7 +103,7 @@ def test_criterion_with_change_detection(hm):
 
 @pytest.mark.parametrize("W,kappa", [(1, 10), (32, 3)])
 def test_full_size_stream_collision(hm, W, kappa):
-    # the config-2 stream (66 x 4 MiB) pushed three times at the bench's lag
+    # the single stream (66 x 4 MiB) pushed three times at the bench's lag
     chunks = G.stream_chunks(4 << 20)
     hists = [O.hist(c) for c in chunks] * 3
     ref = run_and_check(hm, chunks, W, 100, 8192, 32, 31, O.CRIT_COLLISION, kappa, hists=hists,

@@ -91,7 +91,7 @@ def test_ingest_with_detection_and_criterion(hm, W, alarm_pct, criterion, kappa)
     assert d.invalid_patterns == 0 and d.wait_timeouts == 0 and d.merge_timeouts == 0
 
 
-def test_ingest_full_size_config2(hm):
+def test_ingest_full_size_single_stream(hm):
     # the 66 x 4 MiB stream from pinned host memory over 16 HIP streams, the bench's settings
     chunks = G.stream_chunks(4 << 20)
     hists = [O.hist(c) for c in chunks]

@@ -301,8 +301,8 @@ def test_stream_chunks_recount():
     assert r["acc"][3] == 100 + 2
 
 
-def test_stream_config2_trace_shape():
-    # the config-2 stream: switch right after the degenerate chunk and the two-spike chunk
+def test_single_stream_trace_shape():
+    # the single stream: switch right after the degenerate chunk and the two-spike chunk
     specs = G.stream_specs()
     n = 4096
     hs = []

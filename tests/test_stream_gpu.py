@@ -21,8 +21,8 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def config2_like(chunk_bytes, count=None):
-    """The config-2 chunk order (Normal sigma 96/32/8/2, a degenerate and a two-spike chunk)."""
+def single_stream_chunks(chunk_bytes, count=None):
+    """The single stream's chunk order (Normal sigma 96/32/8/2, a degenerate and a two-spike chunk)."""
     return G.stream_chunks(chunk_bytes, count)
 
 
@@ -93,8 +93,8 @@ def check(hm, chunks, W=1, theta=45, S=960, rmax=8, lag=0, mode=0, many=True, un
 
 @pytest.mark.parametrize("many", [True, False])
 @pytest.mark.parametrize("lag", [0, 1, 3])
-def test_config2_order_small_chunks(hm, many, lag):
-    chunks = config2_like(1 << 16)
+def test_single_stream_order_small_chunks(hm, many, lag):
+    chunks = single_stream_chunks(1 << 16)
     ref = check(hm, chunks, W=1, theta=45, S=960, rmax=8, lag=lag, many=many)
     # the switch fires right after the degenerate and the two-spike chunk
     ahist = [k for k, m in enumerate(ref["modes"]) if m == O.MODE_AHIST]
@@ -151,9 +151,9 @@ def test_push_and_push_many_agree_across_calls(hm):
     st.close()
 
 
-def test_full_size_config2(hm):
-    # the config-2 stream at its real size: 66 chunks of 4 MiB, lag 0 and a pipelined lag
-    chunks = config2_like(4 << 20)
+def test_full_size_single_stream(hm):
+    # the single stream at its real size: 66 chunks of 4 MiB, lag 0 and a pipelined lag
+    chunks = single_stream_chunks(4 << 20)
     hists = [O.hist(c) for c in chunks]
     for lag, S, rmax, theta in ((0, 960, 8, 45), (15, 8192, 32, 45), (7, 960, 8, 0)):
         ref = O.stream_reference(None, W=1, theta_pct=theta, S=S, rmax=rmax, lag=lag, hists=hists)
@@ -225,7 +225,7 @@ def test_pushes_on_alternating_hip_streams(hm, W, lag, S, rmax, theta):
 
 def test_full_size_pushes_overlapping(hm):
     # the full 66 x 4 MiB stream pushed three times over two HIP streams at the bench's lag
-    chunks = config2_like(4 << 20)
+    chunks = single_stream_chunks(4 << 20)
     hists = [O.hist(c) for c in chunks] * 3
     lag, S, rmax, theta = 31, 8192, 32, 0
     ref = O.stream_reference(None, W=1, theta_pct=theta, S=S, rmax=rmax, lag=lag, hists=hists)
@@ -321,7 +321,7 @@ def test_window_sizes_around_sequencer_batch(hm, W, S, rmax, theta, lag):
 def test_full_size_moving_window_overlapping(hm, W):
     # the bench's moving-window streams: 66 x 4 MiB pushed three times over two HIP streams at
     # lag 31, the first push traced
-    chunks = config2_like(4 << 20)
+    chunks = single_stream_chunks(4 << 20)
     hists = [O.hist(c) for c in chunks] * 3
     lag, S, rmax, theta = 31, 8192, 32, 0
     ref = O.stream_reference(None, W=W, theta_pct=theta, S=S, rmax=rmax, lag=lag, hists=hists)
@@ -487,9 +487,9 @@ def test_window_ring_wraps(hm):
 
 
 def test_full_size_lag0_known_decisions(hm):
-    # the config-2 stream at lag 0 (chunk k + 1's pattern from chunk k) with the tuned switch:
+    # the single stream at lag 0 (chunk k + 1's pattern from chunk k) with the tuned switch:
     # three pushes over two HIP streams, exact against the oracle
-    chunks = config2_like(4 << 20)
+    chunks = single_stream_chunks(4 << 20)
     hists = [O.hist(c) for c in chunks] * 3
     S, rmax, theta = 8192, 32, 0
     ref = O.stream_reference(None, W=1, theta_pct=theta, S=S, rmax=rmax, lag=0, hists=hists)
@@ -521,7 +521,7 @@ def test_waiting_launches_do_not_starve(hm):
     # CU holds), the library still caps it.  A slow decision path (W = 32, the paper's
     # 960-entry budget, the collision criterion) over two HIP streams must finish with no
     # decision wait timing out, and every trace exact.
-    chunks = config2_like(4 << 20)
+    chunks = single_stream_chunks(4 << 20)
     hists = [O.hist(c) for c in chunks] * 3
     W, theta, S, rmax, lag = 32, 100, 960, 8, 31
     ref = O.stream_reference(None, W=W, theta_pct=theta, S=S, rmax=rmax, lag=lag, hists=hists, criterion=1,
