@@ -148,10 +148,11 @@ def bench_batched(hm, G, O, torch, dev, stream):
             arena[a:a + n].masked_fill_(m, sp.value)
     base = int(arena.data_ptr())
     bufs = [(base + int(o), int(n)) for o, n in zip(offs, sizes)]
+    rows = np.stack([base + offs, sizes], axis=1)   # the same buffers as one (4096, 2) array
     out = torch.zeros((4096, 256), dtype=torch.int32, device=dev)
     nb = int(sizes.sum())
-    ms_batch = timed(torch, stream, lambda: hm.hist_batch(bufs, out, mode=hm.MODE_AUTO, stream=stream), 5)
-    graph = hm.BatchGraph(bufs, out, mode=hm.MODE_AUTO)
+    ms_batch = timed(torch, stream, lambda: hm.hist_batch(rows, out, mode=hm.MODE_AUTO, stream=stream), 5)
+    graph = hm.BatchGraph(rows, out, mode=hm.MODE_AUTO)
     ms_graph = timed(torch, stream, lambda: graph.launch(stream=stream), 5)
     got = out.cpu().numpy().astype(np.int64)
     ok = bool(np.array_equal(got.sum(axis=1), sizes))

@@ -9,6 +9,7 @@ fails loudly otherwise.
 from __future__ import annotations
 
 import ctypes
+import itertools
 import os
 from typing import Optional, Sequence, Tuple
 
@@ -264,9 +265,24 @@ def read_probe(d_in, d_sum, workgroups: int = 0, stream=None, n: Optional[int] =
            "hist_read_probe")
 
 
-def _ptr_arrays(bufs) -> Tuple[ctypes.Array, np.ndarray]:
-    ptrs = (ctypes.c_void_p * len(bufs))()
-    sizes = np.zeros(len(bufs), dtype=np.uint64)
+def _ptr_arrays(bufs) -> Tuple[np.ndarray, np.ndarray]:
+    """Device addresses and byte counts as uint64 arrays, from an (n, 2) integer array of
+    (address, nbytes) rows, a sequence of (address, nbytes) pairs, or a sequence of device
+    tensors (mixed with pairs).  Arrays and pairs are converted without a per-item Python
+    loop, so that marshalling thousands of buffers stays well below a launch's duration."""
+    if isinstance(bufs, np.ndarray):
+        if bufs.ndim != 2 or bufs.shape[1] != 2 or bufs.dtype.kind not in "iu":
+            raise ValueError("an array of buffers must be (n, 2) integers: address, nbytes")
+        if bufs.dtype.kind == "i" and bufs.size and int(bufs.min()) < 0:
+            raise ValueError("buffer addresses and sizes must be non-negative")
+        a = bufs.astype(np.uint64, copy=False)
+        return np.ascontiguousarray(a[:, 0]), np.ascontiguousarray(a[:, 1])
+    n = len(bufs)
+    if all(type(b) is tuple and len(b) == 2 for b in bufs):
+        a = np.fromiter(itertools.chain.from_iterable(bufs), dtype=np.uint64, count=2 * n).reshape(n, 2)
+        return np.ascontiguousarray(a[:, 0]), np.ascontiguousarray(a[:, 1])
+    ptrs = np.zeros(n, dtype=np.uint64)
+    sizes = np.zeros(n, dtype=np.uint64)
     for i, b in enumerate(bufs):
         if isinstance(b, tuple):
             ptrs[i] = int(b[0])
@@ -277,10 +293,16 @@ def _ptr_arrays(bufs) -> Tuple[ctypes.Array, np.ndarray]:
     return ptrs, sizes
 
 
+def _vpp(a: np.ndarray):
+    """A uint64 address array as the C side's `const void *const *`."""
+    return a.ctypes.data_as(ctypes.POINTER(_VP))
+
+
 def hist_batch(bufs, d_out, mode: int = MODE_AUTO, pattern: Optional[Pattern] = None, stream=None):
-    """bufs: list of device tensors or (address, nbytes) pairs; d_out: int32 [n, 256] device tensor."""
+    """bufs: device tensors or (address, nbytes) pairs, or an (n, 2) integer array of such rows;
+    d_out: int32 [n, 256] device tensor."""
     ptrs, sizes = _ptr_arrays(bufs)
-    st = load().hist_batch(ptrs, sizes.ctypes.data_as(c_u64p), len(bufs), _ptr(d_out), int(mode),
+    st = load().hist_batch(_vpp(ptrs), sizes.ctypes.data_as(c_u64p), len(ptrs), _ptr(d_out), int(mode),
                            ctypes.byref(pattern) if pattern is not None else None, _stream(stream))
     _check(st, "hist_batch")
 
@@ -291,7 +313,7 @@ class BatchGraph:
     def __init__(self, bufs, d_out, mode: int = MODE_AUTO, pattern: Optional[Pattern] = None):
         ptrs, sizes = _ptr_arrays(bufs)
         self._h = ctypes.c_void_p()
-        st = load().hist_batch_graph_create(ctypes.byref(self._h), ptrs, sizes.ctypes.data_as(c_u64p), len(bufs),
+        st = load().hist_batch_graph_create(ctypes.byref(self._h), _vpp(ptrs), sizes.ctypes.data_as(c_u64p), len(ptrs),
                                             _ptr(d_out), int(mode),
                                             ctypes.byref(pattern) if pattern is not None else None)
         _check(st, "hist_batch_graph_create")
@@ -330,7 +352,7 @@ class Stream:
 
     def push_many(self, chunks, mode: int = MODE_AUTO, d_out=None, stream=None):
         ptrs, sizes = _ptr_arrays(chunks)
-        _check(load().hist_stream_push_many(self._h, ptrs, sizes.ctypes.data_as(c_u64p), len(chunks), int(mode),
+        _check(load().hist_stream_push_many(self._h, _vpp(ptrs), sizes.ctypes.data_as(c_u64p), len(ptrs), int(mode),
                                             _ptr(d_out), _stream(stream)), "hist_stream_push_many")
 
     def read(self, trace_len: int = 0, stream=None):

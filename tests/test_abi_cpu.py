@@ -178,3 +178,35 @@ def test_struct_layouts_match_binding(hm, tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(cls), cname
         for f in cls._fields_:
             assert got[(cname, f[0])] == getattr(cls, f[0]).offset, (cname, f[0])
+
+
+def test_buffer_marshalling_forms():
+    # the binding's buffer lists: pairs, an (n, 2) array and the per-item path agree
+    from paper_1011_0235_amd import _lib as L
+
+    class Buf:   # what the binding reads of a device tensor
+        def __init__(self, addr, n):
+            self.addr, self.n = addr, n
+
+        def data_ptr(self):
+            return self.addr
+
+        def numel(self):
+            return self.n
+
+        def element_size(self):
+            return 1
+
+    pairs = [((1 << 40) + 4096 * i, 1000 + i) for i in range(300)] + [(0, 0)]
+    p1, s1 = L._ptr_arrays(pairs)
+    p2, s2 = L._ptr_arrays(np.array(pairs, dtype=np.int64))
+    p3, s3 = L._ptr_arrays([Buf(a, n) if i % 2 else (a, n) for i, (a, n) in enumerate(pairs)])
+    for p, q in ((p1, s1), (p2, s2), (p3, s3)):
+        assert p.dtype == np.uint64 and q.dtype == np.uint64 and p.flags.c_contiguous and q.flags.c_contiguous
+    assert np.array_equal(p1, p2) and np.array_equal(s1, s2)
+    assert np.array_equal(p1, p3) and np.array_equal(s1, s3)
+    assert [int(x) for x in p1[:3]] == [1 << 40, (1 << 40) + 4096, (1 << 40) + 8192]
+    assert int(s1[-1]) == 0 and int(p1[-1]) == 0 and len(p1) == 301
+    for bad in (np.zeros((3, 3), dtype=np.int64), np.zeros((3, 2), dtype=np.float64), np.array([[-1, 5]])):
+        with pytest.raises(ValueError):
+            L._ptr_arrays(bad)
