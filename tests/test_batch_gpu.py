@@ -134,3 +134,24 @@ def test_batch_of_one(hm, n):
     for mode in (hm.MODE_AUTO, hm.MODE_WAVEHIST):
         got = run_batch(hm, host, [3], [n], mode)
         assert np.array_equal(got[0], O.hist(host[3:3 + n]).astype(np.int64)), (n, mode)
+
+
+@pytest.mark.parametrize("mode", [0, 2])
+def test_batch_one_large_among_many_tiny(hm, mode):
+    # equal byte shares: one 64 MiB image splits over many workgroups while the shares at
+    # either side hold hundreds of tiny images each; passed as an (n, 2) array of rows
+    g = np.random.default_rng(4242)
+    sizes = [int(x) for x in g.integers(0, 3000, 1000)] + [64 << 20] + [int(x) for x in g.integers(0, 3000, 1000)]
+    sizes[5] = sizes[1500] = 0
+    offs = np.zeros(len(sizes), dtype=np.int64)
+    offs[1:] = np.cumsum(sizes)[:-1]
+    arena = np.concatenate([G.uniform_bytes(n, g) if k % 3 else G.constant_bytes(n, k % 256)
+                            for k, n in enumerate(sizes)])
+    d = dev(arena)
+    rows = np.stack([int(d.data_ptr()) + offs, np.array(sizes, dtype=np.int64)], axis=1)
+    out = torch.full((len(sizes), 256), -1, dtype=torch.int32, device="cuda")
+    hm.hist_batch(rows, out, mode=mode)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+    for k, (o, n) in enumerate(zip(offs, sizes)):
+        assert np.array_equal(got[k], O.hist(arena[o:o + n]).astype(np.int64)), k

@@ -486,6 +486,42 @@ def test_window_ring_wraps(hm):
     st.close()
 
 
+def test_known_decisions_thousands_of_tiny_chunks(hm):
+    # decisions known on the host, so each workgroup takes an equal share of the launch's
+    # bytes: with 3000 chunks of 0..4000 bytes (one in seven empty) a share spans hundreds of
+    # chunks; pushes of uneven sizes over two HIP streams, every trace exact
+    g = np.random.default_rng(31337)
+    chunks = [np.zeros(0, dtype=np.uint8) if k % 7 == 3 else
+              (G.constant_bytes(int(n), k % 256) if k % 5 == 0 else G.uniform_bytes(int(n), g))
+              for k, n in enumerate(g.integers(1, 4000, 3000))]
+    S, rmax, lag = 8192, 32, 0
+    ref = O.stream_reference(chunks, W=1, theta_pct=0, S=S, rmax=rmax, lag=lag)
+    st = hm.Stream(W=1, theta_pct=0, S=S, rmax=rmax, lag=lag, trace_cap=len(chunks))
+    arena = dev(np.concatenate(chunks))
+    base, pos, rows = int(arena.data_ptr()), 0, []
+    for c in chunks:
+        rows.append((base + pos, c.size))
+        pos += c.size
+    rows = np.array(rows, dtype=np.int64)
+    outs = torch.full((len(chunks), 256), -1, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    hs = [torch.cuda.Stream(), torch.cuda.Stream()]
+    k, call = 0, 0
+    while k < len(chunks):
+        n = min(len(chunks) - k, (1100, 37, 900, 1)[call % 4])
+        st.push_many(rows[k:k + n], d_out=outs[k:k + n], stream=hs[call & 1])
+        k += n
+        call += 1
+    snap, modes, pats = st.read(len(chunks), stream=hs[0])
+    torch.cuda.synchronize()
+    assert np.array_equal(outs.cpu().numpy().astype(np.int64) & 0xFFFFFFFF, ref["hists"].astype(np.int64))
+    assert [int(x) for x in snap.acc] == ref["acc"]
+    assert [int(m) for m in modes] == ref["modes"]
+    assert [list(map(int, p)) for p in pats] == ref["patterns"]
+    d = hm.diag()
+    assert d.invalid_patterns == 0 and d.wait_timeouts == 0 and d.merge_timeouts == 0
+    st.close()
+
 def test_full_size_lag0_known_decisions(hm):
     # the single stream at lag 0 (chunk k + 1's pattern from chunk k) with the tuned switch:
     # three pushes over two HIP streams, exact against the oracle
