@@ -587,6 +587,8 @@ def main():
                 "stream_lag%d_one_hip_stream" % lag: (1, lag, theta, S, rmax, 1, 0),
                 "stream_window_W32_lag%d" % plag: (32, plag, theta, S, rmax, 2, 0),
                 "stream_window_W256_lag%d" % plag: (256, plag, theta, S, rmax, 2, 0),
+                # a lag of one push less one chunk: every decision comes from an earlier push
+                "stream_window_W32_lag65": (32, 65, theta, S, rmax, 2, 0),
                 "stream_window_W32_theta45_paper960_lag%d" % plag: (32, plag, 45, 960, 8, 2, 0),
                 "stream_window_W32_alarm4_lag%d" % plag: (32, plag, theta, S, rmax, 2, 4),
                 "stream_alarm4_W1_lag%d" % plag: (1, plag, theta, S, rmax, 2, 4),
@@ -597,8 +599,14 @@ def main():
             cr, kp = (crit[0], crit[1]) if crit else (hm.CRIT_MAXBIN, 0)
             st = hm.Stream(W=w_, theta_pct=th, S=s_, rmax=r_, lag=l, trace_cap=0, alarm_pct=al, criterion=cr,
                            kappa_pct=kp)
+            d0 = hm.diag()
             tms, _ = run_stream(st, 8, 3, per_launch_events=False, n_hip=nh)
+            d1 = hm.diag()
             row = {"GB/s": round(nbytes * 8 / (tms * 1e-3) / 1e9, 1), "ms_per_step": round(tms / 8, 4)}
+            # bounded waits that ran out (a decision or a merge): none is expected
+            if d1.wait_timeouts != d0.wait_timeouts or d1.merge_timeouts != d0.merge_timeouts:
+                row["wait_timeouts"] = int(d1.wait_timeouts - d0.wait_timeouts)
+                row["merge_timeouts"] = int(d1.merge_timeouts - d0.merge_timeouts)
             if al:
                 snap, _, _ = st.read(0)
                 row["chunks"] = int(snap.chunks)

@@ -804,13 +804,17 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
     // a share crosses one or two chunk boundaries where dynamic tiles would change chunk at
     // nearly every tile, and equal shares end together where whole tiles would leave some
     // workgroups a tile more than others.
-    if (known)
-      TRY(plan_split(segs, tile, maxg, &mp));
+    // When every chunk of the launch takes its decision from an earlier launch (lag + 1 >= m),
+    // its chunks wait only on launches that run on their own, never on each other, so equal
+    // shares are safe too (with the residency cap of launches that wait, set above).
+    const bool ahead = !known && m <= st->cfg.lag + 1;
+    if (known || ahead)
+      TRY(plan_split(segs, (uint64_t)g_tune[fam].tile_kib * 1024, maxg, &mp));
     else
       TRY(plan_multi(segs, tile, maxg, &mp));
     const uint32_t copies = std::min<uint32_t>(64, pow2ceil32(std::max<uint32_t>(1, g_tune[fam].copies)));
     TRY(stream_launch_begin(st, s, serialize));
-    TRY(run_multi(d, P, mp, copies, s, nullptr, !known, true));
+    TRY(run_multi(d, P, mp, copies, s, nullptr, !(known || ahead), true));
     TRY(stream_launch_end(st, s));
     for (uint32_t j = 0; j < m; ++j) st->recent[(st->pushed + j) % ring] = h_sizes[first + j];
     st->pushed += m;

@@ -522,6 +522,44 @@ def test_known_decisions_thousands_of_tiny_chunks(hm):
     assert d.invalid_patterns == 0 and d.wait_timeouts == 0 and d.merge_timeouts == 0
     st.close()
 
+@pytest.mark.parametrize("W,lag,theta,S,rmax,alarm,pieces", [
+    (32, 66, 0, 8192, 32, 0, (67, 40, 67)),            # every push within lag + 1 chunks
+    (5, 9, 0, 8192, 32, 3, (10, 3, 25, 1, 10, 7)),      # a 25-chunk push falls back to the in-order plan
+    (1, 12, 45, 960, 8, 0, (13, 13, 5, 40, 13)),        # data-dependent decisions, rule P rationed
+    (32, 20, 45, 960, 8, 0, (21, 21, 21, 3))])
+def test_decisions_from_earlier_launches(hm, W, lag, theta, S, rmax, alarm, pieces):
+    # A push of at most lag + 1 chunks takes every decision from earlier launches, so its
+    # chunks never wait on each other and it runs on equal byte shares while still waiting
+    # for the device's decisions; longer pushes keep the in-order plan.  Two HIP streams,
+    # every trace, the window, the Accumulator and the alarms exact.
+    chunks = mixed_chunks(4400 + W + lag, 150, 90_000)
+    ref = O.stream_reference(chunks, W=W, theta_pct=theta, S=S, rmax=rmax, lag=lag, alarm_pct=alarm)
+    st = hm.Stream(W=W, theta_pct=theta, S=S, rmax=rmax, lag=lag, trace_cap=len(chunks), alarm_pct=alarm)
+    ds = [dev(c) if c.size else None for c in chunks]
+    bufs = [(int(x.data_ptr()) if x is not None else 0, c.size) for x, c in zip(ds, chunks)]
+    outs = torch.full((len(chunks), 256), -1, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    hs = [torch.cuda.Stream(), torch.cuda.Stream()]
+    k, call = 0, 0
+    while k < len(chunks):
+        n = min(len(chunks) - k, pieces[call % len(pieces)])
+        st.push_many(bufs[k:k + n], d_out=outs[k:k + n], stream=hs[call & 1])
+        k += n
+        call += 1
+    snap, modes, pats = st.read(len(chunks), stream=hs[0])
+    alarms = st.read_alarms(len(chunks), stream=hs[0]) if alarm else None
+    torch.cuda.synchronize()
+    assert np.array_equal(outs.cpu().numpy().astype(np.int64) & 0xFFFFFFFF, ref["hists"].astype(np.int64))
+    assert [int(x) for x in snap.acc] == ref["acc"]
+    assert [int(x) for x in snap.mw] == ref["mw"]
+    assert [int(m) for m in modes] == ref["modes"]
+    assert [list(map(int, p)) for p in pats] == ref["patterns"]
+    if alarm:
+        assert [int(a) for a in alarms] == ref["alarms"]
+    d = hm.diag()
+    assert d.invalid_patterns == 0 and d.wait_timeouts == 0 and d.merge_timeouts == 0
+    st.close()
+
 def test_full_size_lag0_known_decisions(hm):
     # the single stream at lag 0 (chunk k + 1's pattern from chunk k) with the tuned switch:
     # three pushes over two HIP streams, exact against the oracle
