@@ -542,10 +542,11 @@ __device__ uint32_t table_bin(uint32_t *lds, const Ctl &c, uint32_t kind, uint32
   } else if (kind == KIND_UNIFORM && lg >= 4) {
     // value t's r sub-bins are one row of r / 4 16-byte quads: read four quads at a time
     // (one wait per four reads instead of one per word), then clear them.  The quad order is
-    // rotated by row so that the 16 lanes of each LDS pass cover all 64 banks: 64 / r rows
-    // share a bank window, so the rotation steps once per 64 / r rows (lg <= 6).
+    // rotated by row so that the lanes served together touch distinct banks, whether a
+    // 16-byte access is served 8 lanes at a time over 32 banks or 16 lanes over 64: rows that
+    // share a bank window get distinct rotations in every aligned group of 8 and of 16 lanes.
     const uint32_t nq = 1u << (lg - 2);
-    const uint32_t rot = t >> (6u - lg);
+    const uint32_t rot = lg == 4 ? (t >> 1) + (t >> 3) : lg == 5 ? t + (t >> 3) : t;
     u32x4 *row = reinterpret_cast<u32x4 *>(lds + (t << lg));
     const u32x4 z = {0u, 0u, 0u, 0u};
     for (uint32_t k0 = 0; k0 < nq; k0 += 4) {
