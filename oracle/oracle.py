@@ -234,6 +234,11 @@ def pattern_valid(words: Sequence[int], S: int, rmax: int) -> bool:
     return True
 
 
+def _ceil_div(a: int, b: int) -> int:
+    """ceil(a / b) for integers a >= 0, b > 0 (exact, no floating point)."""
+    return -(-a // b)
+
+
 def _pow2ceil(x: int) -> int:
     p = 1
     while p < x:
@@ -269,7 +274,7 @@ def rule_p(h: Sequence[int], S: int, rmax: int, T: int = 24) -> List[int]:
         tmax = min(T, 64 - N.bit_length())
         r = [1] * 256
         for t in range(0, tmax + 1):
-            rt = [min(rmax, _pow2ceil(max(1, -(-(hb << t) // N)))) for hb in h]
+            rt = [min(rmax, _pow2ceil(max(1, _ceil_div(hb << t, N)))) for hb in h]
             if sum(rt) <= S:
                 r = rt
             else:

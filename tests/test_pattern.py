@@ -319,3 +319,50 @@ def test_single_stream_trace_shape():
     ahist_at = [k for k, m in enumerate(r["modes"]) if m == O.MODE_AHIST]
     deg_k = [k for k, s in enumerate(specs) if s.kind in ("degenerate", "twospike")]
     assert ahist_at == [k + 1 for k in deg_k]
+
+
+# ---------------------------------------------------------------- rule P rounding (hand-worked)
+
+def _rounding_cases():
+    with open(os.path.join(GOLDEN, "rule_p_rounding.json")) as f:
+        return json.load(f)["cases"]
+
+
+def _check_rounding_case(case):
+    h = [0] * 256
+    for v, n in case["spikes"].items():
+        h[int(v)] = n
+    w = O.rule_p(h, case["S"], case["rmax"])
+    r = rs(w)
+    want = [case["r_other"]] * 256
+    for v, x in case["r"].items():
+        want[int(v)] = x
+    assert r == want
+    assert sum(r) == case["sum_r"]
+    for v, b in case["base"].items():
+        assert O.pat_base(w[int(v)]) == b
+
+
+@pytest.mark.parametrize("i", range(2))
+def test_rule_p_rounding_hand_cases(i):
+    # the scale t wins with shares such as 2.5 and 3.3: ceil, floor and round give
+    # different sub-bin counts, so these pin the ceiling of step 2 of rule P
+    _check_rounding_case(_rounding_cases()[i])
+
+
+@pytest.mark.parametrize("planted", ["floor", "round_half_up", "no_pow2ceil"])
+def test_rule_p_planted_rounding_is_caught(monkeypatch, planted):
+    # plant a plausible mistake in the oracle's rounding and check that a pin fails
+    if planted == "floor":
+        monkeypatch.setattr(O, "_ceil_div", lambda a, b: a // b)
+    elif planted == "round_half_up":
+        monkeypatch.setattr(O, "_ceil_div", lambda a, b: (2 * a + b) // (2 * b))
+    else:
+        monkeypatch.setattr(O, "_pow2ceil", lambda x: x)
+    failed = 0
+    for case in _rounding_cases():
+        try:
+            _check_rounding_case(case)
+        except (AssertionError, ValueError):   # a wrong count, or an invalid pattern
+            failed += 1
+    assert failed >= 1
