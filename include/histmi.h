@@ -212,12 +212,19 @@ typedef struct {
     uint64_t alarms;       /* change detection: chunks after which an alarm was raised */
     uint64_t first_alarm;  /* index + 1 of the first such chunk, 0 if none */
     uint64_t last_alarm;   /* index + 1 of the last such chunk, 0 if none */
+    uint64_t wait_timeouts;   /* chunks whose bounded wait for their decision gave up (they ran the
+                                 per-wavefront kernel: counts exact, trace entry not the rule's) */
+    uint64_t merge_timeouts;  /* chunks whose merge gave up before its total arrived (histogram may be short) */
 } hist_stream_snapshot_t;
 
 /* Synchronous: waits for `stream` and for this stream's launches on any HIP stream, then
  * copies the state.  h_mode_trace (uint8[trace_len])
  * and h_pattern_trace (uint32[trace_len][256]) may be NULL; entry k holds the mode / pattern
- * words chunk k ran with (k < trace_cap). */
+ * words chunk k ran with (k < trace_cap).
+ * Returns HIST_ETIMEDOUT, with everything still copied, when a bounded wait of one of the
+ * stream's chunks gave up (see wait_timeouts and merge_timeouts; never expected at the
+ * default limits, see hist_set_wait_limits).  The Accumulator, the moving window and the chunk
+ * count stay exact after a decision wait gave up; only that chunk's trace entry differs. */
 hist_status_t hist_stream_read(hist_stream_t *st, hist_stream_snapshot_t *snap, uint8_t *h_mode_trace,
                                uint32_t *h_pattern_trace, uint32_t trace_len, void *stream);
 
@@ -329,7 +336,10 @@ typedef struct {
     uint64_t max_inflight_bytes, max_inflight_requests, max_concurrent_batches;
 } hist_server_stats_t;
 
-/* Synchronous.  Starts the scheduler thread on the current device. */
+/* Synchronous.  Starts the scheduler thread on the current device.  The scheduler spins on
+ * one host core while micro-batches are in flight and for 2 ms after its last activity (a
+ * timed sleep would round up to the OS timer slack and set the latency floor); idle beyond
+ * that it blocks until the next submission. */
 hist_status_t hist_server_create(hist_server_t **sv, const hist_server_config_t *cfg);
 
 /* Thread-safe, non-blocking.  d_buf: n device bytes (any alignment) that stay unchanged until
@@ -340,10 +350,15 @@ hist_status_t hist_server_create(hist_server_t **sv, const hist_server_config_t 
 hist_status_t hist_server_submit(hist_server_t *sv, uint32_t stream_id, const void *d_buf, size_t n, uint32_t *d_out,
                                  uint64_t *ticket);
 
-/* Thread-safe, non-blocking: fills r (r->status HIST_EBUSY while the request is not done). */
+/* Thread-safe, non-blocking: fills r (r->status HIST_EBUSY while the request is not done).
+ * A ticket is retired once poll or wait has reported its final state (a status other than
+ * HIST_EBUSY); later calls with it, and calls with a ticket never issued, return HIST_EINVAL.
+ * Finished tickets that nobody polls are retired oldest first once more than 2^20 of them
+ * are held, so a server's host memory stays bounded. */
 hist_status_t hist_server_poll(hist_server_t *sv, uint64_t ticket, hist_server_result_t *r);
 
-/* Blocks until the request is done or timeout_ns passes (< 0: no limit); HIST_ETIMEDOUT then. */
+/* Blocks until the request is done or timeout_ns passes (< 0: no limit); HIST_ETIMEDOUT then
+ * (the ticket stays live).  r may be NULL.  Retires a finished ticket as poll does. */
 hist_status_t hist_server_wait(hist_server_t *sv, uint64_t ticket, int64_t timeout_ns, hist_server_result_t *r);
 
 /* Blocks until every submitted request is done (or timeout_ns passes: HIST_ETIMEDOUT). */
@@ -378,6 +393,17 @@ hist_status_t hist_diag_read(hist_diag_t *d);
  */
 hist_status_t hist_read_probe(const void *d_in, size_t n_bytes, uint64_t *d_sum, uint32_t workgroups,
                               void *stream);
+
+/*
+ * hist_set_wait_limits -- bounds of the in-kernel waits of launches issued after the call
+ * (process-wide; synchronous; never fails).  decision_polls: polls of a stream chunk's
+ * decision before the chunk gives up and runs the per-wavefront kernel (0 = the default,
+ * 2^22, about a second); merge_polls: re-reads of a segment's partial counts before its
+ * finalizer gives up (0 = the default, 2^20).  Every wait is bounded, so every kernel ends;
+ * a wait that gave up is counted in hist_diag_t and in the stream's snapshot.  Small limits
+ * exist to exercise those paths; they cost speed (and, for merges, exactness) only.
+ */
+hist_status_t hist_set_wait_limits(uint32_t decision_polls, uint32_t merge_polls);
 
 /* Launch shape of one kernel family.  Zero fields keep the built-in default. */
 typedef struct {

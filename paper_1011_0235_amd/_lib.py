@@ -71,7 +71,8 @@ class IngestConfig(ctypes.Structure):
 class StreamSnapshot(ctypes.Structure):
     _fields_ = [("chunks", ctypes.c_uint64), ("acc", ctypes.c_uint64 * 256), ("mw", ctypes.c_uint64 * 256),
                 ("next_mode", ctypes.c_uint32), ("next_pattern", Pattern), ("alarms", ctypes.c_uint64),
-                ("first_alarm", ctypes.c_uint64), ("last_alarm", ctypes.c_uint64)]
+                ("first_alarm", ctypes.c_uint64), ("last_alarm", ctypes.c_uint64),
+                ("wait_timeouts", ctypes.c_uint64), ("merge_timeouts", ctypes.c_uint64)]
 
 
 class Diag(ctypes.Structure):
@@ -126,6 +127,7 @@ _SIGS = [
     ("hist_batch_graph_destroy", ctypes.c_int, [_VP]),
     ("hist_diag_read", ctypes.c_int, [ctypes.POINTER(Diag)]),
     ("hist_read_probe", ctypes.c_int, [_VP, ctypes.c_size_t, _VP, ctypes.c_uint32, _VP]),
+    ("hist_set_wait_limits", ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32]),
     ("hist_tune_set", ctypes.c_int, [ctypes.c_uint32, ctypes.POINTER(Tune)]),
     ("hist_tune_get", ctypes.c_int, [ctypes.c_uint32, ctypes.POINTER(Tune)]),
     ("hist_ingest_create", ctypes.c_int, [ctypes.POINTER(_VP), ctypes.POINTER(IngestConfig)]),
@@ -222,6 +224,36 @@ def _nbytes(x) -> int:
     return int(x.numel() * x.element_size())
 
 
+def _in_bytes(d_in, n: Optional[int]) -> int:
+    """Bytes to read from d_in: all of a tensor, or n; an n beyond a tensor's bytes is refused
+    (the kernel would read past the allocation)."""
+    if isinstance(d_in, int) or d_in is None:
+        if n is None:
+            raise ValueError("a raw address needs an explicit byte count n")
+        return int(n)
+    nb = _nbytes(d_in)
+    if n is None:
+        return nb
+    if int(n) < 0 or int(n) > nb:
+        raise ValueError("n = %d exceeds the input tensor's %d bytes" % (int(n), nb))
+    if not d_in.is_contiguous():
+        raise ValueError("the input tensor must be contiguous")
+    return int(n)
+
+
+def _check_out(d_out, words: int, elem_bytes: int = 4, what: str = "d_out"):
+    """A tensor output must be contiguous, of elem_bytes-byte elements, and hold at least
+    `words` of them (raw addresses are the caller's responsibility)."""
+    if d_out is None or isinstance(d_out, int):
+        return
+    if d_out.element_size() != elem_bytes:
+        raise ValueError("%s must have %d-byte elements" % (what, elem_bytes))
+    if not d_out.is_contiguous():
+        raise ValueError("%s must be contiguous" % what)
+    if d_out.numel() < words:
+        raise ValueError("%s holds %d elements, needs at least %d" % (what, d_out.numel(), words))
+
+
 # ---------------------------------------------------------------- patterns (host)
 
 def pattern_init(kind: int, S: int = 0, rmax: int = 0) -> Pattern:
@@ -244,7 +276,8 @@ def pattern_update(d_hist, S: int, rmax: int, d_pat, stream=None):
 
 def hist_u8(d_in, d_out, mode: int = MODE_AUTO, pattern: Optional[Pattern] = None, stream=None, n: Optional[int] = None):
     """d_out (int32/uint32 tensor of 256, device) <- histogram of the bytes of d_in."""
-    nb = _nbytes(d_in) if n is None else int(n)
+    nb = _in_bytes(d_in, n)
+    _check_out(d_out, 256)
     st = load().hist_u8(_ptr(d_in), nb, _ptr(d_out), int(mode), ctypes.byref(pattern) if pattern is not None else None,
                         _stream(stream))
     _check(st, "hist_u8")
@@ -252,7 +285,8 @@ def hist_u8(d_in, d_out, mode: int = MODE_AUTO, pattern: Optional[Pattern] = Non
 
 def hist_u8_u64(d_in, d_acc, mode: int = MODE_AUTO, pattern: Optional[Pattern] = None, stream=None,
                 n: Optional[int] = None):
-    nb = _nbytes(d_in) if n is None else int(n)
+    nb = _in_bytes(d_in, n)
+    _check_out(d_acc, 256, 8, "d_acc")
     st = load().hist_u8_u64(_ptr(d_in), nb, _ptr(d_acc), int(mode),
                             ctypes.byref(pattern) if pattern is not None else None, _stream(stream))
     _check(st, "hist_u8_u64")
@@ -260,7 +294,8 @@ def hist_u8_u64(d_in, d_acc, mode: int = MODE_AUTO, pattern: Optional[Pattern] =
 
 def read_probe(d_in, d_sum, workgroups: int = 0, stream=None, n: Optional[int] = None):
     """Streaming read of d_in (HBM read roofline); adds its uint32 words to d_sum[0] (uint64)."""
-    nb = _nbytes(d_in) if n is None else int(n)
+    nb = _in_bytes(d_in, n)
+    _check_out(d_sum, 1, 8, "d_sum")
     _check(load().hist_read_probe(_ptr(d_in), nb, _ptr(d_sum), int(workgroups), _stream(stream)),
            "hist_read_probe")
 
@@ -302,6 +337,7 @@ def hist_batch(bufs, d_out, mode: int = MODE_AUTO, pattern: Optional[Pattern] = 
     """bufs: device tensors or (address, nbytes) pairs, or an (n, 2) integer array of such rows;
     d_out: int32 [n, 256] device tensor."""
     ptrs, sizes = _ptr_arrays(bufs)
+    _check_out(d_out, 256 * len(ptrs))
     st = load().hist_batch(_vpp(ptrs), sizes.ctypes.data_as(c_u64p), len(ptrs), _ptr(d_out), int(mode),
                            ctypes.byref(pattern) if pattern is not None else None, _stream(stream))
     _check(st, "hist_batch")
@@ -312,6 +348,7 @@ class BatchGraph:
 
     def __init__(self, bufs, d_out, mode: int = MODE_AUTO, pattern: Optional[Pattern] = None):
         ptrs, sizes = _ptr_arrays(bufs)
+        _check_out(d_out, 256 * len(ptrs))
         self._h = ctypes.c_void_p()
         st = load().hist_batch_graph_create(ctypes.byref(self._h), _vpp(ptrs), sizes.ctypes.data_as(c_u64p), len(ptrs),
                                             _ptr(d_out), int(mode),
@@ -346,22 +383,27 @@ class Stream:
         _check(load().hist_stream_create(ctypes.byref(self._h), ctypes.byref(cfg)), "hist_stream_create")
 
     def push(self, d_chunk, mode: int = MODE_AUTO, d_out=None, stream=None, n: Optional[int] = None):
-        nb = _nbytes(d_chunk) if n is None else int(n)
+        nb = _in_bytes(d_chunk, n)
+        _check_out(d_out, 256)
         _check(load().hist_stream_push(self._h, _ptr(d_chunk), nb, int(mode), _ptr(d_out), _stream(stream)),
                "hist_stream_push")
 
     def push_many(self, chunks, mode: int = MODE_AUTO, d_out=None, stream=None):
         ptrs, sizes = _ptr_arrays(chunks)
+        _check_out(d_out, 256 * len(ptrs))
         _check(load().hist_stream_push_many(self._h, _vpp(ptrs), sizes.ctypes.data_as(c_u64p), len(ptrs), int(mode),
                                             _ptr(d_out), _stream(stream)), "hist_stream_push_many")
 
-    def read(self, trace_len: int = 0, stream=None):
+    def read(self, trace_len: int = 0, stream=None, allow_timeouts: bool = False):
+        """(snapshot, mode trace, pattern trace).  A bounded wait that gave up raises
+        HistError(ETIMEDOUT) unless allow_timeouts (the snapshot then says how many)."""
         snap = StreamSnapshot()
         modes = np.zeros(max(trace_len, 1), dtype=np.uint8)
         pats = np.zeros((max(trace_len, 1), 256), dtype=np.uint32)
-        _check(load().hist_stream_read(self._h, ctypes.byref(snap), modes.ctypes.data_as(c_u8p),
-                                       pats.ctypes.data_as(c_u32p), int(trace_len), _stream(stream)),
-               "hist_stream_read")
+        st = load().hist_stream_read(self._h, ctypes.byref(snap), modes.ctypes.data_as(c_u8p),
+                                     pats.ctypes.data_as(c_u32p), int(trace_len), _stream(stream))
+        if not (allow_timeouts and st == ETIMEDOUT):
+            _check(st, "hist_stream_read")
         return snap, modes[:trace_len], pats[:trace_len]
 
     def read_alarms(self, trace_len: int, stream=None) -> np.ndarray:
@@ -397,9 +439,12 @@ class Ingest:
         """h_chunk: a host tensor / numpy array / host address (must stay valid until sync)."""
         if isinstance(h_chunk, np.ndarray):
             ptr, nb = int(h_chunk.ctypes.data), int(h_chunk.nbytes)
+            if n is not None and not 0 <= int(n) <= nb:
+                raise ValueError("n = %d exceeds the host chunk's %d bytes" % (int(n), nb))
+            nb = nb if n is None else int(n)
         else:
-            ptr, nb = _ptr(h_chunk), (_nbytes(h_chunk) if not isinstance(h_chunk, int) else 0)
-        nb = nb if n is None else int(n)
+            ptr, nb = _ptr(h_chunk), _in_bytes(h_chunk, n)
+        _check_out(d_out, 256)
         _check(load().hist_ingest_push(self._h, stream._h, ptr, nb, int(mode), _ptr(d_out)), "hist_ingest_push")
 
     def sync(self):
@@ -423,6 +468,11 @@ def diag() -> Diag:
     d = Diag()
     _check(load().hist_diag_read(ctypes.byref(d)), "hist_diag_read")
     return d
+
+
+def set_wait_limits(decision_polls: int = 0, merge_polls: int = 0):
+    """Bounds of the in-kernel waits of later launches (0 = the library's default)."""
+    _check(load().hist_set_wait_limits(int(decision_polls), int(merge_polls)), "hist_set_wait_limits")
 
 
 def tune_get(family: int) -> Tune:
@@ -457,15 +507,17 @@ class Server:
         _check(load().hist_server_create(ctypes.byref(self._h), ctypes.byref(cfg)), "hist_server_create")
 
     def submit(self, stream_id: int, d_buf, d_out=None, n: Optional[int] = None) -> int:
-        nb = _nbytes(d_buf) if (n is None and not isinstance(d_buf, int)) else int(n)
+        nb = _in_bytes(d_buf, n)
+        _check_out(d_out, 256)
         t = ctypes.c_uint64()
         _check(load().hist_server_submit(self._h, int(stream_id), _ptr(d_buf), nb, _ptr(d_out), ctypes.byref(t)),
                "hist_server_submit")
         return int(t.value)
 
     def try_submit(self, stream_id: int, d_buf, d_out=None, n: Optional[int] = None):
-        """(status, ticket) without raising."""
-        nb = _nbytes(d_buf) if (n is None and not isinstance(d_buf, int)) else int(n)
+        """(status, ticket) without raising on a library status (argument errors still raise)."""
+        nb = _in_bytes(d_buf, n)
+        _check_out(d_out, 256)
         t = ctypes.c_uint64()
         st = load().hist_server_submit(self._h, int(stream_id), _ptr(d_buf), nb, _ptr(d_out), ctypes.byref(t))
         return st, int(t.value)

@@ -22,6 +22,12 @@ namespace rt {
 Tune g_tune[kFamilies] = {{4, 256, 4, 6}, {2, 256, 4, 6}, {2, 256, 4, 6}, {4, 256, 4, 6}, {3, 1024, 4, 4},
                           {2, 1024, 4, 2}};
 uint32_t g_single_copies = 16;   // partial copies for a launch with one large segment
+// bounded waits: polls of a decision tag (each about 0.3 us apart, about 1.2 s in all) and
+// re-reads of a segment's partial copies before they give up
+constexpr uint32_t kDefaultWaitPolls = 1u << 22;
+constexpr uint32_t kDefaultMergePolls = 1u << 20;
+static uint32_t g_wait_polls = kDefaultWaitPolls;
+static uint32_t g_merge_polls = kDefaultMergePolls;
 
 static std::mutex g_mu;
 static std::unordered_map<int, DevCtx *> g_dev;
@@ -201,6 +207,8 @@ bool pattern_ok(const hist_pattern_t *p) {
 void init_params(Params *P) {
   std::memset(P, 0, sizeof(*P));
   P->seg0.chunk = -1;
+  P->wait_polls = g_wait_polls;
+  P->merge_polls = g_merge_polls;
 }
 
 // LDS layout: counting table of `table_words` at word 0, then the lookup table.
@@ -338,10 +346,16 @@ hist_status_t stream_state_alloc(uint32_t count, uint32_t W, uint32_t theta, uin
                                  uint32_t nslot, uint32_t trace_cap, uint32_t alarm_pct, StreamAlloc *sa) {
   const size_t tc = std::max<uint32_t>(trace_cap, 1);
   // W > 1 or alarms on: chunks are sequenced in order from a ring of recent histograms.
-  // Chunk j's histogram is needed until chunk j + W is sequenced; the chunk that reuses its
-  // slot (j + R) is counted only after its decision, made when chunk j + R - 1 - lag was
-  // sequenced, so R >= W + lag + 1 suffices (plus a margin).
-  const uint32_t R = (W > 1 || alarm_pct > 0) ? W + lag + 66 : 1;
+  // Chunk j's histogram is needed until chunk j + W is sequenced.  The ring may not rely on
+  // chunks waiting for their decisions (a wait that gives up lets its chunk run and write
+  // its entry anyway), only on how many chunks can be in flight: a workgroup that holds the
+  // sequencer belongs to a running launch X, so at most launches X and X + 1 write entries
+  // (a push waits for the launch two before it), while the oldest entry the holder can
+  // still read belongs to launch X - 2 (every earlier chunk was present, and so taken in
+  // order, before X - 1 ended), less the W chunks of the window before it.  Each launch
+  // holds at most kMaxChunksPerLaunch chunks, so W + 4 kMaxChunksPerLaunch slots suffice;
+  // lag + 1 more are kept as a margin.
+  const uint32_t R = (W > 1 || alarm_pct > 0) ? W + lag + 1 + 4 * kMaxChunksPerLaunch : 1;
   sa->R = R;
   bool ok = hipMalloc(&sa->d_st, (size_t)count * sizeof(StreamDev)) == hipSuccess &&
             hipMalloc(&sa->d_ring, (size_t)count * R * 257 * 8) == hipSuccess &&
@@ -828,6 +842,7 @@ hist_status_t hist_stream_read(hist_stream_t *st, hist_stream_snapshot_t *snap, 
   TRY_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
   for (int i = 0; i < 2; ++i)   // launches of this stream on other HIP streams
     if (st->ev_used[i]) TRY_HIP(hipEventSynchronize(st->ev[i]));
+  bool timed_out = false;
   if (snap) {
     StreamDev h;
     TRY_HIP(hipMemcpy(&h, st->sa.d_st, sizeof(h), hipMemcpyDeviceToHost));
@@ -838,6 +853,9 @@ hist_status_t hist_stream_read(hist_stream_t *st, hist_stream_snapshot_t *snap, 
     snap->alarms = h.alarms;
     snap->first_alarm = h.first_alarm;
     snap->last_alarm = h.last_alarm;
+    snap->wait_timeouts = h.wait_timeouts;
+    snap->merge_timeouts = h.merge_timeouts;
+    timed_out = h.wait_timeouts != 0 || h.merge_timeouts != 0;
     const bool sequenced = st->cfg.W > 1 || st->cfg.alarm_pct > 0;
     if (h.done > 0) {
       Decision dec;
@@ -863,7 +881,12 @@ hist_status_t hist_stream_read(hist_stream_t *st, hist_stream_snapshot_t *snap, 
   if (h_mode_trace && n) TRY_HIP(hipMemcpy(h_mode_trace, st->sa.d_mode_trace, n, hipMemcpyDeviceToHost));
   if (h_pattern_trace && n)
     TRY_HIP(hipMemcpy(h_pattern_trace, st->sa.d_pat_trace, (size_t)n * 256 * 4, hipMemcpyDeviceToHost));
-  return HIST_OK;
+  if (!snap) {
+    uint64_t to[2];
+    TRY_HIP(hipMemcpy(to, &st->sa.d_st->wait_timeouts, sizeof(to), hipMemcpyDeviceToHost));
+    timed_out = to[0] != 0 || to[1] != 0;
+  }
+  return timed_out ? HIST_ETIMEDOUT : HIST_OK;
 }
 
 hist_status_t hist_stream_read_alarms(hist_stream_t *st, uint8_t *h_alarm_trace, uint32_t trace_len, void *stream) {
@@ -900,6 +923,13 @@ hist_status_t hist_diag_read(hist_diag_t *out) {
   out->invalid_patterns = h[0];
   out->wait_timeouts = h[1];
   out->merge_timeouts = h[2];
+  return HIST_OK;
+}
+
+hist_status_t hist_set_wait_limits(uint32_t decision_polls, uint32_t merge_polls) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_wait_polls = decision_polls ? decision_polls : kDefaultWaitPolls;
+  g_merge_polls = merge_polls ? merge_polls : kDefaultMergePolls;
   return HIST_OK;
 }
 

@@ -65,6 +65,10 @@ struct StreamDev {
   uint64_t sacc[256];
   uint64_t sacc_n;
   uint64_t alarms, first_alarm, last_alarm;   // count; chunk index + 1 (0 = none)
+  // bounded waits of this stream's chunks that gave up: a decision wait (the chunk then ran
+  // the per-wavefront kernel; its trace entry is not the rule's) or a merge (the chunk's
+  // histogram may be short); reported to the caller by hist_stream_read
+  uint64_t wait_timeouts, merge_timeouts;
   uint64_t *ring;        // [R][256] recent histograms (sequenced), chunk j in slot j % R, each
                          // entry (j + 1) << 32 | count: a load tells whether it is chunk j's
   uint64_t *ring_n;      // [R] the same chunks' sizes, (j + 1 mod 2^24) << 40 | bytes
@@ -141,6 +145,10 @@ struct Params {
   uint32_t kappa;            // collision-index threshold, percent
   uint64_t trace_cap;
   Decision *slots;           // the stream's decision ring
+  // bounded waits: polls of a decision tag, and re-reads of a segment's partial copies,
+  // before they give up (counted in the diagnostics and the stream's state)
+  uint32_t wait_polls;
+  uint32_t merge_polls;
   // LDS layout (in 32-bit words)
   uint32_t table_words;      // counting table at word 0
   uint32_t look_off;         // lane-replicated lookup table (byte addresses into the counting table)

@@ -172,42 +172,15 @@ __device__ __forceinline__ void st_agent(T *p, T v) {
   __hip_atomic_store(gmem(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Bounded spin by thread 0 until *p == want.  Polls with relaxed agent-scope loads (no
-// cache invalidation per poll); what the flag guards is then read with agent-scope loads.  Returns false on timeout
-// (counted in diag[1]); the callers then go on with what they have, which can only cost
-// speed or a stale trace, never counts.
-__device__ bool spin_until_u32(const uint32_t *p, uint32_t want, uint32_t *diag) {
-  for (uint32_t i = 0; i < (1u << 22); ++i) {
-    if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == want) {
-#ifdef HISTMI_STRICT_FENCES
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-#endif
-      return true;
-    }
-    __builtin_amdgcn_s_sleep(8);
-  }
-  atomicAdd(&diag[1], 1u);
-  return false;
-}
-__device__ bool spin_until_u64(const uint64_t *p, uint64_t want, uint32_t *diag) {
-  for (uint32_t i = 0; i < (1u << 22); ++i) {
-    if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == want) {
-#ifdef HISTMI_STRICT_FENCES
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-#endif
-      return true;
-    }
-    __builtin_amdgcn_s_sleep(8);
-  }
-  atomicAdd(&diag[1], 1u);
-  return false;
-}
-
 // Bounded spin by thread 0 until the decision tag at p carries generation `gen`.  Returns
-// the tag, or 0 on timeout (counted in diag[1]): the caller then runs the per-wavefront
-// kernel, which needs no pattern, so a timeout costs speed and a trace entry, never counts.
-__device__ uint64_t spin_for_tag(const uint64_t *p, uint32_t gen, uint32_t *diag) {
-  for (uint32_t i = 0; i < (1u << 22); ++i) {
+// the tag, or 0 after `polls` polls (counted in diag[1] and in the stream's wait_timeouts):
+// the caller then runs the per-wavefront kernel, which needs no pattern, so a timeout costs
+// speed and a trace entry, never counts.  (A chunk that gave up still writes its histogram
+// into the stream's ring; the ring holds every chunk that two launches in flight can
+// produce, so that write never lands on an entry the sequencer still needs.)
+__device__ uint64_t spin_for_tag(const uint64_t *p, uint32_t gen, uint32_t polls, uint32_t *diag,
+                                 uint64_t *st_timeouts) {
+  for (uint32_t i = 0; i < polls; ++i) {
     const uint64_t tag = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (tag_gen(tag) == gen) {
 #ifdef HISTMI_STRICT_FENCES
@@ -218,6 +191,7 @@ __device__ uint64_t spin_for_tag(const uint64_t *p, uint32_t gen, uint32_t *diag
     __builtin_amdgcn_s_sleep(8);
   }
   atomicAdd(&diag[1], 1u);
+  __hip_atomic_fetch_add(st_timeouts, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return 0;
 }
 
@@ -613,14 +587,30 @@ __device__ __forceinline__ uint32_t begin_segment(uint32_t *lds, const Params &P
     if (sd.chunk == kServerChunk) {
       // served request: the stream's latest decision, whatever has been published (no wait)
       const Decision *d = &st->slots[0];
-      const uint64_t tag = ld_agent(&d->tag);
+      if (t == 0) c.tag = ld_agent(&d->tag);
+      __syncthreads();
+      const uint64_t tag = c.tag;
+      const uint32_t kind_lg = tag_kind_lg(tag);
+      dmode = tag_gen(tag) == 0 ? (uint32_t)HIST_MODE_WAVEHIST : tag_mode(tag);
+      const uint32_t mode = P.forced ? P.forced : dmode;
+      if (mode == HIST_MODE_AHIST && tag_gen(tag) != 0 && (kind_lg >> 8) == KIND_UNIFORM &&
+          (256u << (kind_lg & 0xFFu)) <= P.table_words) {
+        // a uniform table is carried by the tag alone, which this library's own epilogue
+        // stored in one piece: no pattern words to read or check
+        if (t == 0) {
+          c.lg = kind_lg & 0xFFu;
+          c.used_mode = HIST_MODE_AHIST;
+        }
+        __syncthreads();
+        return KIND_UNIFORM;
+      }
       if (tag_gen(tag) == 0) {
         c.words[t] = t;
-        dmode = HIST_MODE_WAVEHIST;
         S = 256;
       } else {
+        // requests of one stream may finish together and overwrite each other's words: the
+        // words are checked as a pattern below, and any mix that passes is a valid pattern
         c.words[t] = ld_agent(&d->words[t]);
-        dmode = tag_mode(tag);
         S = ld_agent(&d->S);
       }
     } else {
@@ -640,7 +630,10 @@ __device__ __forceinline__ uint32_t begin_segment(uint32_t *lds, const Params &P
           tag = make_tag((sd.known & kKnownCold) ? 0u : 1u, (sd.known >> 16) & 0xFFu, sd.known & 0xFFFFu);
         } else if (j >= 0) {
           const uint32_t want = (uint32_t)(j + 1);
-          const uint64_t got = (tag_gen(hint) == want) ? hint : spin_for_tag(&d->tag, want, P.diag);
+          const uint64_t got = (tag_gen(hint) == want)
+                                   ? hint
+                                   : spin_for_tag(&d->tag, want, P.wait_polls, P.diag,
+                                                  &P.st[sd.stream_idx].wait_timeouts);
           if (got) tag = got;
         }
         const uint32_t mode = P.forced ? P.forced : tag_mode(tag);
@@ -1136,8 +1129,13 @@ __device__ __forceinline__ void finalize_segment(const Params &P, Ctl &c, uint32
         for (uint32_t q = 0; q < copies; ++q) tot += ld_agent(&part[(q << 8) | t]);
       }
       if (block_sum_u64(tot, c) == sd.size) break;
-      if (tries == (1u << 20)) {   // never expected: contributions that do not land
-        if (t == 0) atomicAdd(&P.diag[2], 1u);
+      if (tries >= P.merge_polls) {   // never expected: contributions that do not land
+        if (t == 0) {
+          atomicAdd(&P.diag[2], 1u);
+          if (sd.chunk >= 0 || sd.chunk == kServerChunk)
+            __hip_atomic_fetch_add(&P.st[sd.stream_idx].merge_timeouts, (uint64_t)1, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
         break;
       }
       __builtin_amdgcn_s_sleep(2);

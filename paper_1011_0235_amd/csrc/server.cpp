@@ -5,6 +5,12 @@
 // The scheduler repeatedly (1) retires finished micro-batches (hipEventQuery), freeing their
 // budget and slots, and (2) admits queued requests in arrival order while the budget and the
 // slot limit allow, launching each admitted group as one persistent multi-segment kernel.
+// Between rounds it spins (no timed sleep: a sleep of a few microseconds is rounded up to
+// the kernel's timer slack, tens of microseconds, which would set the latency floor) while
+// a batch is in flight and for kIdleSpinNs after the last activity; only then does it block
+// until a submission wakes it.  Tickets are retired once poll or wait has returned their
+// final state, and finished tickets nobody asks about are dropped oldest first beyond
+// kFinishedCap, so the host memory a server holds stays bounded.
 // Device side: every request is a segment of that launch; its finalizing workgroup writes the
 // request's histogram and updates the state of the request's stream id (running uint64
 // histogram, moving window of one request, decision) -- see server_epilogue in kernels.hip.
@@ -12,12 +18,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
 #include <mutex>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "histmi.h"
@@ -53,7 +61,11 @@ struct Slot {
   std::vector<uint64_t> tickets;
 };
 
-constexpr size_t kQueueCap = 1u << 20;   // not-yet-admitted requests
+constexpr size_t kQueueCap = 1u << 20;      // not-yet-admitted requests
+constexpr size_t kFinishedCap = 1u << 20;   // finished requests kept for poll / wait
+constexpr uint64_t kIdleSpinNs = 2000000;   // the scheduler spins this long after its last activity
+
+inline void cpu_relax() { __builtin_ia32_pause(); }
 
 }  // namespace
 
@@ -67,7 +79,11 @@ struct hist_server {
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<uint64_t> pending;
-  std::vector<Req> reqs;            // ticket t lives at reqs[t - 1]
+  std::unordered_map<uint64_t, Req> reqs;   // live tickets: queued, admitted, or finished and not yet retired
+  std::deque<uint64_t> finished;            // finished tickets in finishing order (bounds what is kept)
+  uint64_t next_ticket = 1;
+  std::atomic<uint64_t> submissions{0};     // lets the spinning scheduler notice work without the lock
+  std::atomic<bool> stopping{false};
   uint64_t inflight_bytes = 0, inflight_reqs = 0;
   uint32_t busy_slots = 0;
   bool stop = false;
@@ -76,7 +92,24 @@ struct hist_server {
 
   void run();
   bool launch(Slot &sl, std::vector<uint64_t> &batch);
+  void finish(uint64_t tk, int32_t status, uint64_t t);
 };
+
+// Mark an admitted request finished (lock held).
+void hist_server::finish(uint64_t tk, int32_t status, uint64_t t) {
+  Req &r = reqs[tk];
+  r.status = status;
+  r.t_done = t;
+  inflight_bytes -= r.n;
+  inflight_reqs -= 1;
+  stats.completed += 1;
+  if (status == HIST_OK) stats.bytes_done += r.n;
+  finished.push_back(tk);
+  while (finished.size() > kFinishedCap) {
+    reqs.erase(finished.front());   // no-op if poll or wait already retired it
+    finished.pop_front();
+  }
+}
 
 // Launch one micro-batch on slot `sl` (called without the lock; the requests are admitted).
 bool hist_server::launch(Slot &sl, std::vector<uint64_t> &batch) {
@@ -88,7 +121,7 @@ bool hist_server::launch(Slot &sl, std::vector<uint64_t> &batch) {
   {
     std::lock_guard<std::mutex> lk(mu);
     for (size_t j = 0; j < batch.size(); ++j) {
-      const Req &r = reqs[batch[j] - 1];
+      const Req &r = reqs[batch[j]];
       std::memset(&segs[j], 0, sizeof(SegDesc));
       segs[j].ptr = static_cast<const uint8_t *>(r.buf);
       segs[j].size = r.n;
@@ -111,6 +144,7 @@ bool hist_server::launch(Slot &sl, std::vector<uint64_t> &batch) {
 void hist_server::run() {
   (void)hipSetDevice(dev);
   std::unique_lock<std::mutex> lk(mu);
+  uint64_t last_active = now_ns();
   for (;;) {
     // 1. retire finished micro-batches
     for (Slot &sl : slots) {
@@ -118,18 +152,11 @@ void hist_server::run() {
       const hipError_t e = hipEventQuery(sl.ev);
       if (e == hipErrorNotReady) continue;
       const uint64_t t = now_ns();
-      for (uint64_t tk : sl.tickets) {
-        Req &r = reqs[tk - 1];
-        r.status = (e == hipSuccess) ? HIST_OK : HIST_EDEVICE;
-        r.t_done = t;
-        inflight_bytes -= r.n;
-        inflight_reqs -= 1;
-        stats.completed += 1;
-        if (e == hipSuccess) stats.bytes_done += r.n;
-      }
+      for (uint64_t tk : sl.tickets) finish(tk, e == hipSuccess ? HIST_OK : HIST_EDEVICE, t);
       sl.tickets.clear();
       sl.busy = false;
       busy_slots -= 1;
+      last_active = t;
       cv_done.notify_all();
     }
     // 2. admit queued requests into free slots
@@ -139,7 +166,7 @@ void hist_server::run() {
       uint64_t bytes = 0;
       const uint64_t t = now_ns();
       while (!pending.empty() && batch.size() < cfg.max_batch) {
-        Req &r = reqs[pending.front() - 1];
+        Req &r = reqs[pending.front()];
         if (inflight_bytes + r.n > cfg.hbm_budget_bytes || inflight_reqs + 1 > cfg.max_slots) break;
         batch.push_back(pending.front());
         pending.pop_front();
@@ -156,36 +183,47 @@ void hist_server::run() {
       sl.bytes = bytes;
       stats.batches += 1;
       stats.max_concurrent_batches = std::max<uint64_t>(stats.max_concurrent_batches, busy_slots);
+      last_active = t;
       lk.unlock();
       const bool ok = launch(sl, batch);
       lk.lock();
       sl.tickets = batch;
       if (!ok) {
         // the launch never reached the device: fail these requests now
-        for (uint64_t tk : batch) {
-          Req &r = reqs[tk - 1];
-          r.status = HIST_EDEVICE;
-          r.t_done = now_ns();
-          inflight_bytes -= r.n;
-          inflight_reqs -= 1;
-          stats.completed += 1;
-        }
+        const uint64_t tf = now_ns();
+        for (uint64_t tk : batch) finish(tk, HIST_EDEVICE, tf);
         sl.tickets.clear();
         sl.busy = false;
         busy_slots -= 1;
         cv_done.notify_all();
       }
     }
-    // 3. wait for work
-    if (busy_slots > 0) {
-      lk.unlock();
-      std::this_thread::sleep_for(std::chrono::microseconds(2));
-      lk.lock();
-    } else if (pending.empty()) {
+    if (stop && pending.empty() && busy_slots == 0) break;
+    // 3. wait for work: spin while a batch is in flight or work came recently, else block.
+    // (Whatever is still pending now waits for a batch to finish: every free slot was
+    // offered the queue's front.)  Only this thread changes the slots, so they are read
+    // here without the lock.
+    const uint64_t seen = submissions.load(std::memory_order_acquire);
+    const bool inflight = busy_slots > 0;
+    if (!inflight && pending.empty() && now_ns() - last_active > kIdleSpinNs) {
       if (stop) break;
       cv_work.wait(lk, [this] { return stop || !pending.empty(); });
-      if (stop && pending.empty()) break;
+      last_active = now_ns();
+      continue;
     }
+    lk.unlock();
+    for (uint32_t spins = 0;; ++spins) {
+      bool done = false;
+      for (Slot &sl : slots)
+        if (sl.busy && hipEventQuery(sl.ev) != hipErrorNotReady) {
+          done = true;
+          break;
+        }
+      if (done || submissions.load(std::memory_order_acquire) != seen || (stopping.load() && !inflight)) break;
+      if (!inflight && now_ns() - last_active > kIdleSpinNs) break;
+      for (int i = 0; i < 32; ++i) cpu_relax();
+    }
+    lk.lock();
   }
 }
 
@@ -242,16 +280,17 @@ hist_status_t hist_server_submit(hist_server_t *sv, uint32_t stream_id, const vo
     std::lock_guard<std::mutex> lk(sv->mu);
     if (sv->stop) return HIST_ECANCELED;
     if (sv->pending.size() >= kQueueCap) return HIST_EBUSY;
-    Req r;
+    const uint64_t tk = sv->next_ticket++;
+    Req &r = sv->reqs[tk];
     r.sid = stream_id;
     r.buf = d_buf;
     r.n = n;
     r.out = d_out;
     r.t_submit = now_ns();
-    sv->reqs.push_back(r);
-    *ticket = sv->reqs.size();
-    sv->pending.push_back(*ticket);
+    *ticket = tk;
+    sv->pending.push_back(tk);
     sv->stats.submitted += 1;
+    sv->submissions.fetch_add(1, std::memory_order_release);
   }
   sv->cv_work.notify_one();
   return HIST_OK;
@@ -266,27 +305,39 @@ static void fill_result(const Req &r, hist_server_result_t *out) {
   out->t_done_ns = r.t_done;
 }
 
+// Fill r from a live ticket; a finished one is retired (lock held).
+static void report(hist_server *sv, std::unordered_map<uint64_t, Req>::iterator it, hist_server_result_t *r) {
+  if (r) fill_result(it->second, r);
+  if (it->second.status != HIST_EBUSY) sv->reqs.erase(it);
+}
+
 hist_status_t hist_server_poll(hist_server_t *sv, uint64_t ticket, hist_server_result_t *r) {
   if (!sv || !r) return HIST_EINVAL;
   std::lock_guard<std::mutex> lk(sv->mu);
-  if (ticket == 0 || ticket > sv->reqs.size()) return HIST_EINVAL;
-  fill_result(sv->reqs[ticket - 1], r);
+  auto it = sv->reqs.find(ticket);
+  if (it == sv->reqs.end()) return HIST_EINVAL;
+  report(sv, it, r);
   return HIST_OK;
 }
 
 hist_status_t hist_server_wait(hist_server_t *sv, uint64_t ticket, int64_t timeout_ns, hist_server_result_t *r) {
   if (!sv) return HIST_EINVAL;
   std::unique_lock<std::mutex> lk(sv->mu);
-  if (ticket == 0 || ticket > sv->reqs.size()) return HIST_EINVAL;
-  auto done = [&] { return sv->reqs[ticket - 1].status != HIST_EBUSY; };
-  if (timeout_ns < 0) {
-    sv->cv_done.wait(lk, done);
-  } else if (!sv->cv_done.wait_for(lk, std::chrono::nanoseconds(timeout_ns), done)) {
-    if (r) fill_result(sv->reqs[ticket - 1], r);
-    return HIST_ETIMEDOUT;
-  }
-  if (r) fill_result(sv->reqs[ticket - 1], r);
-  return HIST_OK;
+  if (sv->reqs.find(ticket) == sv->reqs.end()) return HIST_EINVAL;
+  // the ticket stays live until this call retires it (only poll or wait retire a ticket, and
+  // one ticket is waited on by one thread); finished tickets are not dropped for the cap
+  // while this thread waits for the lock, since that only happens after 2^20 later ones
+  auto done = [&] {
+    auto it = sv->reqs.find(ticket);
+    return it == sv->reqs.end() || it->second.status != HIST_EBUSY;
+  };
+  bool ok = true;
+  if (timeout_ns < 0) sv->cv_done.wait(lk, done);
+  else ok = sv->cv_done.wait_for(lk, std::chrono::nanoseconds(timeout_ns), done);
+  auto it = sv->reqs.find(ticket);
+  if (it == sv->reqs.end()) return HIST_EINVAL;
+  report(sv, it, r);
+  return ok ? HIST_OK : HIST_ETIMEDOUT;
 }
 
 hist_status_t hist_server_drain(hist_server_t *sv, int64_t timeout_ns) {
@@ -319,8 +370,9 @@ hist_status_t hist_server_destroy(hist_server_t *sv) {
   {
     std::lock_guard<std::mutex> lk(sv->mu);
     sv->stop = true;
+    sv->stopping.store(true);
     for (uint64_t tk : sv->pending) {
-      Req &r = sv->reqs[tk - 1];
+      Req &r = sv->reqs[tk];
       r.status = HIST_ECANCELED;
       r.t_done = now_ns();
       sv->stats.canceled += 1;

@@ -210,3 +210,28 @@ def test_buffer_marshalling_forms():
     for bad in (np.zeros((3, 3), dtype=np.int64), np.zeros((3, 2), dtype=np.float64), np.array([[-1, 5]])):
         with pytest.raises(ValueError):
             L._ptr_arrays(bad)
+
+
+def test_binding_refuses_sizes_beyond_the_tensors(hm):
+    # an explicit n beyond the input tensor's bytes would make the kernel read past the
+    # allocation, and a short or wrongly typed output would be written past its end: the
+    # binding refuses both before anything reaches the library
+    import torch
+    x = torch.zeros(100, dtype=torch.uint8)
+    out = torch.zeros(256, dtype=torch.int32)
+    with pytest.raises(ValueError):
+        hm.hist_u8(x, out, n=101)
+    with pytest.raises(ValueError):
+        hm.hist_u8(x, torch.zeros(255, dtype=torch.int32))
+    with pytest.raises(ValueError):
+        hm.hist_u8(x, torch.zeros(256, dtype=torch.int64))
+    with pytest.raises(ValueError):
+        hm.hist_u8(x, torch.zeros(512, dtype=torch.int32)[::2])
+    with pytest.raises(ValueError):
+        hm.hist_u8_u64(x, torch.zeros(256, dtype=torch.int32))
+    with pytest.raises(ValueError):
+        hm.read_probe(x, torch.zeros(1, dtype=torch.int64), n=112)
+    with pytest.raises(ValueError):
+        hm.hist_batch([x, x], torch.zeros((1, 256), dtype=torch.int32))
+    with pytest.raises(ValueError):
+        hm.hist_u8(12345, out)   # a raw address needs n

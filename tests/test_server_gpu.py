@@ -113,6 +113,13 @@ def test_wait_poll_and_cancel(hm):
     tks = [sv.submit(0, pool, n=64 << 20) for _ in range(50)]
     r = sv.wait(tks[0])
     assert r.status == hm.OK
+    # a ticket whose final state was reported is retired
+    with pytest.raises(hm.HistError) as e:
+        sv.poll(tks[0])
+    assert e.value.status == hm.EINVAL
+    r = sv.poll(tks[-1])                 # still queued: reported, not retired
+    assert r.status == hm.EBUSY
+    assert sv.poll(tks[-1]).status == hm.EBUSY
     # bad ids and tickets
     st, _ = sv.try_submit(5, pool, n=16)
     assert st == hm.EINVAL
