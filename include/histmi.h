@@ -120,6 +120,24 @@ hist_status_t hist_u8(const void *d_in, size_t n_bytes, uint32_t *d_out, hist_mo
 hist_status_t hist_u8_u64(const void *d_in, size_t n_bytes, uint64_t *d_acc, hist_mode_t mode,
                           const hist_pattern_t *h_pat, void *stream);
 
+/*
+ * hist_u8_noalloc -- hist_u8 for callers that cannot allocate device memory: code under
+ * HIP graph capture, serving loops and harnesses that forbid hipMalloc.  Same arguments,
+ * result and errors as hist_u8, and the same counting kernel; it calls no hipMalloc or
+ * hipFree, not even on its first call.  Its scratch (counters and partial histograms) is a
+ * fixed array of HIST_NOALLOC_SCRATCH_BYTES compiled into the library; each device the
+ * library runs on holds its own copy until the process ends.  Each call clears what it
+ * needs of it with a small kernel on `stream` (no memset), then launches the histogram.
+ * All calls on one device share that array: calls that overlap on the device (on
+ * different HIP streams without ordering between them, or from several host threads) race
+ * and may return wrong counts; order them.
+ * Extra error: HIST_ENOMEM if a launch would need more scratch than the array holds (not
+ * reached at the library's launch shapes: at most 16 partial copies of 1 KiB).
+ */
+#define HIST_NOALLOC_SCRATCH_BYTES 32768u
+hist_status_t hist_u8_noalloc(const void *d_in, size_t n_bytes, uint32_t *d_out, hist_mode_t mode,
+                              const hist_pattern_t *h_pat, void *stream);
+
 /* hist_pattern_init -- fill a HOST pattern of the given kind (synchronous).
  *   IDENTITY ignores S/rmax (S = 256, rmax = 1); PAPER960 ignores them (S = 960, rmax = 8);
  *   FLAT needs rmax a power of two <= HIST_RMAX_MAX (S = 256 * rmax; the S argument is ignored). */

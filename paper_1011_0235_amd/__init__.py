@@ -8,7 +8,8 @@ from ._lib import (  # noqa: F401
     AUTO_FLAT_R, EBUSY, ECANCELED, EDEVICE, EINVAL, ENOMEM, ENOTSUP, EOVERFLOW, ETIMEDOUT, OK,
     MODE_AHIST, MODE_AUTO, MODE_WAVEAGG, MODE_WAVEHIST, PAT_FLAT, PAT_IDENTITY, PAT_PAPER960, RMAX_MAX, S_MAX,
     BatchGraph, HistError, Ingest, Pattern, Server, Stream, declared_symbols, device_info, diag, hist_batch, hist_u8,
-    hist_u8_u64, load, pattern_init, pattern_update, pattern_validate, strerror, tune_get, tune_set, set_wait_limits,
+    hist_u8_noalloc, hist_u8_u64, load, pattern_init, pattern_update, pattern_validate, strerror, tune_get, tune_set,
+    set_wait_limits,
     TUNE_STREAM, TUNE_STREAM_KNOWN, read_probe, CRIT_MAXBIN, CRIT_COLLISION, CRIT_BOTH,
 )
 from ._lib import LIB_PATH  # noqa: F401

@@ -110,6 +110,7 @@ _SIGS = [
     ("hist_device_info", ctypes.c_int, [ctypes.POINTER(DeviceInfo)]),
     ("hist_u8", ctypes.c_int, [_VP, ctypes.c_size_t, _VP, ctypes.c_int, ctypes.POINTER(Pattern), _VP]),
     ("hist_u8_u64", ctypes.c_int, [_VP, ctypes.c_size_t, _VP, ctypes.c_int, ctypes.POINTER(Pattern), _VP]),
+    ("hist_u8_noalloc", ctypes.c_int, [_VP, ctypes.c_size_t, _VP, ctypes.c_int, ctypes.POINTER(Pattern), _VP]),
     ("hist_pattern_init", ctypes.c_int, [ctypes.POINTER(Pattern), ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32]),
     ("hist_pattern_validate", ctypes.c_int, [ctypes.POINTER(Pattern)]),
     ("hist_pattern_update", ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.c_uint32, _VP, _VP]),
@@ -281,6 +282,17 @@ def hist_u8(d_in, d_out, mode: int = MODE_AUTO, pattern: Optional[Pattern] = Non
     st = load().hist_u8(_ptr(d_in), nb, _ptr(d_out), int(mode), ctypes.byref(pattern) if pattern is not None else None,
                         _stream(stream))
     _check(st, "hist_u8")
+
+
+def hist_u8_noalloc(d_in, d_out, mode: int = MODE_AUTO, pattern: Optional[Pattern] = None, stream=None,
+                    n: Optional[int] = None):
+    """hist_u8 on the library's fixed per-device scratch array: allocates no device memory.
+    Calls that overlap on one device race (they share that array)."""
+    nb = _in_bytes(d_in, n)
+    _check_out(d_out, 256)
+    st = load().hist_u8_noalloc(_ptr(d_in), nb, _ptr(d_out), int(mode),
+                                ctypes.byref(pattern) if pattern is not None else None, _stream(stream))
+    _check(st, "hist_u8_noalloc")
 
 
 def hist_u8_u64(d_in, d_acc, mode: int = MODE_AUTO, pattern: Optional[Pattern] = None, stream=None,

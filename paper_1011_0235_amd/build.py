@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhistmi.so")
-SOURCES = ["kernels.hip", "api.cpp", "plan.cpp", "server.cpp", "ingest.cpp"]
+SOURCES = ["kernels.hip", "noalloc.hip", "api.cpp", "plan.cpp", "server.cpp", "ingest.cpp"]
 ARCH = "gfx950"
 
 

@@ -920,9 +920,11 @@ hist_status_t hist_diag_read(hist_diag_t *out) {
   TRY(get_dev(&d));
   uint32_t h[64];
   TRY_HIP(hipMemcpy(h, d->diag, sizeof(h), hipMemcpyDeviceToHost));
-  out->invalid_patterns = h[0];
-  out->wait_timeouts = h[1];
-  out->merge_timeouts = h[2];
+  uint32_t na[3];
+  TRY(noalloc_diag(na));   // launches of hist_u8_noalloc keep their own counters
+  out->invalid_patterns = (uint64_t)h[0] + na[0];
+  out->wait_timeouts = (uint64_t)h[1] + na[1];
+  out->merge_timeouts = (uint64_t)h[2] + na[2];
   return HIST_OK;
 }
 

@@ -20,6 +20,8 @@ hipError_t launch_read_probe(const void *d_in, uint64_t nvec, uint64_t *d_sum, u
 hipError_t set_kernel_attrs(uint32_t max_dyn_lds);
 hipError_t occupancy(uint32_t lds_bytes, int *blocks_per_cu);
 uint32_t ctl_bytes();   // control block at the end of the dynamic LDS
+// noalloc.hip: diagnostics counters of hist_u8_noalloc launches on the current device
+hist_status_t noalloc_diag(uint32_t out[3]);
 
 namespace rt {
 
