@@ -207,7 +207,10 @@ typedef struct {
  * may go to different HIP streams: a chunk waits on the device for the decision it runs
  * with, so consecutive launches may overlap (the tail of one filling the device while the
  * next starts) and the results do not depend on timing.  At most two launches of one stream
- * are in flight: a push makes its HIP stream wait for the launch two before it.
+ * are in flight: a push makes its HIP stream wait for the launch two before it.  A HIP
+ * stream given to a push must stay valid until the next hist_stream_read (or
+ * hist_stream_read_alarms, hist_stream_destroy) returns: those wait for it, and a later
+ * push on another HIP stream may queue an event on it.
  */
 hist_status_t hist_stream_create(hist_stream_t **st, const hist_stream_config_t *cfg);
 
@@ -251,6 +254,17 @@ hist_status_t hist_stream_read(hist_stream_t *st, hist_stream_snapshot_t *snap, 
  * entries of chunks not yet pushed are 0).  HIST_EINVAL if the stream has alarms off or
  * h_alarm_trace is NULL with trace_len > 0. */
 hist_status_t hist_stream_read_alarms(hist_stream_t *st, uint8_t *h_alarm_trace, uint32_t trace_len, void *stream);
+
+/* Per-chunk timeline of the device, for the chunks of the trace (the per-chunk breakdown of
+ * a stream's time behind Sec. III.B's pipelining: how long each chunk waits for its decision
+ * and how long it takes).  Synchronous like hist_stream_read.  h_times_ns: HOST
+ * uint64[trace_len][2]; entry k = {the time the first workgroup began counting chunk k
+ * (after its decision arrived), the time chunk k's finalizer was done (its decision
+ * published; with W > 1 or change detection: its histogram handed to the in-order
+ * sequencer)}, in nanoseconds of the device's constant-rate wall clock (differences are
+ * meaningful, the origin is not).  0 for chunks beyond trace_cap or not yet run.
+ * HIST_EINVAL if h_times_ns is NULL with trace_len > 0. */
+hist_status_t hist_stream_read_times(hist_stream_t *st, uint64_t *h_times_ns, uint32_t trace_len, void *stream);
 
 /* Synchronous; waits for the device before freeing. */
 hist_status_t hist_stream_destroy(hist_stream_t *st);

@@ -119,6 +119,7 @@ _SIGS = [
     ("hist_stream_push_many", ctypes.c_int, [_VP, ctypes.POINTER(_VP), c_u64p, ctypes.c_uint32, ctypes.c_int, _VP, _VP]),
     ("hist_stream_read", ctypes.c_int, [_VP, ctypes.POINTER(StreamSnapshot), c_u8p, c_u32p, ctypes.c_uint32, _VP]),
     ("hist_stream_read_alarms", ctypes.c_int, [_VP, c_u8p, ctypes.c_uint32, _VP]),
+    ("hist_stream_read_times", ctypes.c_int, [_VP, c_u64p, ctypes.c_uint32, _VP]),
     ("hist_stream_destroy", ctypes.c_int, [_VP]),
     ("hist_batch", ctypes.c_int, [ctypes.POINTER(_VP), c_u64p, ctypes.c_uint32, _VP, ctypes.c_int,
                                   ctypes.POINTER(Pattern), _VP]),
@@ -423,6 +424,14 @@ class Stream:
         out = np.zeros(max(trace_len, 1), dtype=np.uint8)
         _check(load().hist_stream_read_alarms(self._h, out.ctypes.data_as(c_u8p), int(trace_len), _stream(stream)),
                "hist_stream_read_alarms")
+        return out[:trace_len]
+
+    def read_times(self, trace_len: int, stream=None) -> np.ndarray:
+        """Device timeline of the traced chunks: uint64[trace_len, 2] ns = (first workgroup began
+        counting chunk k, chunk k's finalizer done); 0 where not traced or not run."""
+        out = np.zeros((max(trace_len, 1), 2), dtype=np.uint64)
+        _check(load().hist_stream_read_times(self._h, out.ctypes.data_as(c_u64p), int(trace_len), _stream(stream)),
+               "hist_stream_read_times")
         return out[:trace_len]
 
     def close(self):

@@ -98,10 +98,8 @@ void free_scratch(Scratch *sc) {
   if (sc->seg_done) (void)hipFree(sc->seg_done);
   if (sc->partial) (void)hipFree(sc->partial);
   if (sc->desc_buf) (void)hipFree(sc->desc_buf);
-  for (auto &e : sc->cache) {
+  for (auto &e : sc->cache)
     if (e.dev) (void)hipFree(e.dev);
-    if (e.ev) (void)hipEventDestroy(e.ev);
-  }
   for (int k = 0; k < 2; ++k) {
     if (sc->stage[k]) (void)hipHostFree(sc->stage[k]);
     if (sc->ev[k]) (void)hipEventDestroy(sc->ev[k]);
@@ -130,7 +128,8 @@ hist_status_t get_scratch(DevCtx *d, hipStream_t s, size_t nseg, uint32_t copies
 // Make the descriptors `host` available on the device and point sc->desc at them.  A set
 // identical to one of the last few uploaded is reused as is; otherwise the least recently
 // used cache entry is refilled through pinned staging (two buffers, each reused only after
-// its previous copy finished).
+// its previous copy finished).  The refill is a copy on `s`, the only HIP stream whose
+// launches read this Scratch, so it runs after every launch that read the old contents.
 hist_status_t upload_desc(Scratch *sc, const void *host, size_t bytes, hipStream_t s) {
   ++sc->tick;
   for (int i = 0; i < 4; ++i) {
@@ -146,10 +145,11 @@ hist_status_t upload_desc(Scratch *sc, const void *host, size_t bytes, hipStream
   for (int i = 1; i < 4; ++i)
     if (sc->cache[i].used < sc->cache[vi].used) vi = i;
   Scratch::Cached *victim = &sc->cache[vi];
-  if (victim->ev) TRY_HIP(hipEventSynchronize(victim->ev));   // launches still reading it are done
-  else TRY_HIP(hipEventCreateWithFlags(&victim->ev, hipEventDisableTiming));
   if (victim->cap < bytes) {
-    if (victim->dev) TRY_HIP(hipFree(victim->dev));
+    if (victim->dev) {
+      TRY_HIP(hipStreamSynchronize(s));   // launches still reading the old buffer are done
+      TRY_HIP(hipFree(victim->dev));
+    }
     victim->dev = nullptr;
     victim->cap = 0;
     victim->blob.clear();
@@ -177,11 +177,6 @@ hist_status_t upload_desc(Scratch *sc, const void *host, size_t bytes, hipStream
   victim->used = sc->tick;
   sc->desc = victim->dev;
   sc->cur = vi;
-  return HIST_OK;
-}
-
-hist_status_t desc_used(Scratch *sc, hipStream_t s) {
-  if (sc->cur >= 0) TRY_HIP(hipEventRecord(sc->cache[sc->cur].ev, s));
   return HIST_OK;
 }
 
@@ -294,7 +289,7 @@ uint32_t blocks_per_cu(uint32_t family, uint32_t lds) {
   return std::max<uint32_t>(1, std::min<uint32_t>(g_tune[family].bpc, resident_per_cu(lds)));
 }
 
-hist_status_t run_single(DevCtx *d, Params &P, hipStream_t s) {
+hist_status_t run_single(DevCtx *d, Params &P, hipStream_t s, Scratch *own, hipEvent_t done) {
   const uint64_t n = P.seg0.size;
   const uint32_t lds = lds_bytes(P);
   const uint32_t fam = P.st ? (uint32_t)KIND_UNIFORM : P.kind;
@@ -302,8 +297,9 @@ hist_status_t run_single(DevCtx *d, Params &P, hipStream_t s) {
   const uint64_t tile = std::max<uint64_t>(16384, ceil_div(ceil_div(n, G), 16384) * 16384);
   const uint32_t ntiles = (uint32_t)std::max<uint64_t>(1, ceil_div(n, tile));
   const uint32_t copies = std::min<uint32_t>(g_single_copies, pow2ceil32(ntiles));
-  Scratch *sc;
-  TRY(get_scratch(d, s, 1, copies, 0, &sc));
+  Scratch *sc = own;
+  if (!sc) TRY(get_scratch(d, s, 1, copies, 0, &sc));
+  else TRY(alloc_scratch(sc, 1, copies, 0, s));
   P.seg0.tile0 = 0;
   P.seg0.ntiles = ntiles;
   P.nseg = 1;
@@ -316,11 +312,11 @@ hist_status_t run_single(DevCtx *d, Params &P, hipStream_t s) {
   P.partial = sc->partial;
   P.diag = d->diag;
   const LaunchShape sh{ntiles, lds, 4};
-  return dev_err(launch_hist(P, sh, s));
+  return dev_err(launch_hist(P, sh, s, done));
 }
 
 hist_status_t run_multi(DevCtx *d, Params &P, const MultiPlan &mp, uint32_t copies, hipStream_t s, Scratch *own,
-                        bool dynamic, bool upload) {
+                        bool dynamic, bool upload, hipEvent_t done) {
   Scratch *sc = own;
   if (!sc) TRY(get_scratch(d, s, mp.nseg, copies, 0, &sc));
   else TRY(alloc_scratch(sc, mp.nseg, copies, upload ? 0 : mp.blob.size(), s));
@@ -338,8 +334,7 @@ hist_status_t run_multi(DevCtx *d, Params &P, const MultiPlan &mp, uint32_t copi
   P.partial = sc->partial;
   P.diag = d->diag;
   const LaunchShape sh{mp.grid, lds_bytes(P), 4};
-  TRY(dev_err(launch_hist(P, sh, s)));
-  return upload ? desc_used(sc, s) : HIST_OK;
+  return dev_err(launch_hist(P, sh, s, done));
 }
 
 hist_status_t stream_state_alloc(uint32_t count, uint32_t W, uint32_t theta, uint32_t S, uint32_t rmax, uint32_t lag,
@@ -361,7 +356,8 @@ hist_status_t stream_state_alloc(uint32_t count, uint32_t W, uint32_t theta, uin
             hipMalloc(&sa->d_ring, (size_t)count * R * 257 * 8) == hipSuccess &&
             hipMalloc(&sa->d_slots, (size_t)count * nslot * sizeof(Decision)) == hipSuccess &&
             hipMalloc(&sa->d_mode_trace, (size_t)count * tc * 2) == hipSuccess &&
-            hipMalloc(&sa->d_pat_trace, (size_t)count * tc * 256 * 4) == hipSuccess;
+            hipMalloc(&sa->d_pat_trace, (size_t)count * tc * 256 * 4) == hipSuccess &&
+            hipMalloc(&sa->d_time_trace, (size_t)count * tc * 2 * 8) == hipSuccess;
   if (!ok) {
     stream_state_free(sa);
     return HIST_ENOMEM;
@@ -391,7 +387,8 @@ hist_status_t stream_state_alloc(uint32_t count, uint32_t W, uint32_t theta, uin
        hipMemset(sa->d_ring, 0, (size_t)count * R * 257 * 8) == hipSuccess &&
        hipMemset(sa->d_slots, 0, (size_t)count * nslot * sizeof(Decision)) == hipSuccess &&
        hipMemset(sa->d_mode_trace, 0, (size_t)count * tc * 2) == hipSuccess &&
-       hipMemset(sa->d_pat_trace, 0, (size_t)count * tc * 256 * 4) == hipSuccess;
+       hipMemset(sa->d_pat_trace, 0, (size_t)count * tc * 256 * 4) == hipSuccess &&
+       hipMemset(sa->d_time_trace, 0xFF, (size_t)count * tc * 2 * 8) == hipSuccess;
   if (!ok) {
     stream_state_free(sa);
     return HIST_EDEVICE;
@@ -405,6 +402,7 @@ void stream_state_free(StreamAlloc *sa) {
   if (sa->d_slots) (void)hipFree(sa->d_slots);
   if (sa->d_mode_trace) (void)hipFree(sa->d_mode_trace);
   if (sa->d_pat_trace) (void)hipFree(sa->d_pat_trace);
+  if (sa->d_time_trace) (void)hipFree(sa->d_time_trace);
   *sa = StreamAlloc();
 }
 
@@ -424,10 +422,18 @@ struct hist_stream {
   std::vector<uint64_t> recent;
   // Launches of one stream may run on different HIP streams and overlap; the device makes
   // each chunk wait for its decision.  At most two launches are in flight: before a launch,
-  // the HIP stream waits for the launch two before it (events recorded after each launch).
+  // the HIP stream waits for the launch two before it.  Slot i describes one of the last
+  // two launches: the HIP stream it went to, and whether ev[i] has been recorded on that
+  // HIP stream since (so that it completes with or after the launch).  Events are recorded
+  // only when a launch on another HIP stream has to wait: an event packet between two
+  // kernels costs the device a few microseconds, and a launch on the same HIP stream is
+  // ordered anyway (two HIP streams used in turn never need one).
   hipEvent_t ev[2] = {nullptr, nullptr};
   bool ev_used[2] = {false, false};
+  bool ev_rec[2] = {false, false};
+  hipStream_t ev_on[2] = {nullptr, nullptr};
   uint32_t evi = 0;
+  std::vector<hipStream_t> used;   // HIP streams with launches of this stream since the last read
 };
 
 // When is the decision after a chunk a function of the chunk sizes alone?  With W = 1 and no
@@ -446,17 +452,38 @@ static bool decisions_known(const hist_stream_config_t &c) {
   }
 }
 
-// Before a launch: wait for the launch two before it (at most two in flight), or, with
-// `serialize`, for both earlier ones (no overlap).
-static hist_status_t stream_launch_begin(hist_stream *st, hipStream_t s, bool serialize = false) {
-  if (st->ev_used[st->evi]) TRY_HIP(hipStreamWaitEvent(s, st->ev[st->evi], 0));
-  if (serialize && st->ev_used[st->evi ^ 1u]) TRY_HIP(hipStreamWaitEvent(s, st->ev[st->evi ^ 1u], 0));
+// Make `s` wait for the launch in slot i, unless that launch went to `s` itself (then it is
+// ordered before anything queued on `s` now).  Its event is recorded on its HIP stream now
+// if it was not yet: that covers the launch and whatever was queued after it there.
+static hist_status_t wait_slot(hist_stream *st, uint32_t i, hipStream_t s) {
+  if (!st->ev_used[i] || st->ev_on[i] == s) return HIST_OK;
+  if (!st->ev_rec[i]) {
+    TRY_HIP(hipEventRecord(st->ev[i], st->ev_on[i]));
+    st->ev_rec[i] = true;
+  }
+  TRY_HIP(hipStreamWaitEvent(s, st->ev[i], 0));
   return HIST_OK;
 }
-static hist_status_t stream_launch_end(hist_stream *st, hipStream_t s) {
-  TRY_HIP(hipEventRecord(st->ev[st->evi], s));
+// Before a launch: wait for the launch two before it (at most two in flight), or, with
+// `serialize`, for both earlier ones (no overlap).
+static hist_status_t stream_launch_begin(hist_stream *st, hipStream_t s, bool serialize) {
+  TRY(wait_slot(st, st->evi, s));
+  if (serialize) TRY(wait_slot(st, st->evi ^ 1u, s));
+  return HIST_OK;
+}
+static void stream_launch_end(hist_stream *st, hipStream_t s) {
   st->ev_used[st->evi] = true;
+  st->ev_rec[st->evi] = false;
+  st->ev_on[st->evi] = s;
   st->evi ^= 1u;
+  if (std::find(st->used.begin(), st->used.end(), s) == st->used.end()) st->used.push_back(s);
+}
+// Wait on the host for every launch of the stream (synchronous reads).
+static hist_status_t stream_sync(hist_stream *st, hipStream_t s) {
+  TRY_HIP(hipStreamSynchronize(s));
+  for (hipStream_t u : st->used)
+    if (u != s) TRY_HIP(hipStreamSynchronize(u));
+  st->used.clear();
   return HIST_OK;
 }
 
@@ -729,6 +756,7 @@ static void stream_params(const hist_stream *st, Params *P) {
   P->rmax = st->cfg.rmax;
   P->R = st->sa.R;
   P->trace_cap = st->cfg.trace_cap;
+  P->time_trace = st->sa.d_time_trace;
 }
 
 hist_status_t hist_stream_push(hist_stream_t *st, const void *d_chunk, size_t n, hist_mode_t mode, uint32_t *d_out_k,
@@ -829,7 +857,7 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
     const uint32_t copies = std::min<uint32_t>(64, pow2ceil32(std::max<uint32_t>(1, g_tune[fam].copies)));
     TRY(stream_launch_begin(st, s, serialize));
     TRY(run_multi(d, P, mp, copies, s, nullptr, !(known || ahead), true));
-    TRY(stream_launch_end(st, s));
+    stream_launch_end(st, s);
     for (uint32_t j = 0; j < m; ++j) st->recent[(st->pushed + j) % ring] = h_sizes[first + j];
     st->pushed += m;
   }
@@ -839,9 +867,7 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
 hist_status_t hist_stream_read(hist_stream_t *st, hist_stream_snapshot_t *snap, uint8_t *h_mode_trace,
                                uint32_t *h_pattern_trace, uint32_t trace_len, void *stream) {
   if (!st) return HIST_EINVAL;
-  TRY_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
-  for (int i = 0; i < 2; ++i)   // launches of this stream on other HIP streams
-    if (st->ev_used[i]) TRY_HIP(hipEventSynchronize(st->ev[i]));
+  TRY(stream_sync(st, static_cast<hipStream_t>(stream)));
   bool timed_out = false;
   if (snap) {
     StreamDev h;
@@ -891,14 +917,28 @@ hist_status_t hist_stream_read(hist_stream_t *st, hist_stream_snapshot_t *snap, 
 
 hist_status_t hist_stream_read_alarms(hist_stream_t *st, uint8_t *h_alarm_trace, uint32_t trace_len, void *stream) {
   if (!st || st->cfg.alarm_pct == 0 || (!h_alarm_trace && trace_len > 0)) return HIST_EINVAL;
-  TRY_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
-  for (int i = 0; i < 2; ++i)   // launches of this stream on other HIP streams
-    if (st->ev_used[i]) TRY_HIP(hipEventSynchronize(st->ev[i]));
+  TRY(stream_sync(st, static_cast<hipStream_t>(stream)));
   const uint32_t n = std::min<uint32_t>(trace_len, st->cfg.trace_cap);
   if (n)   // the alarm trace follows the mode trace (one stream, trace_cap entries each)
     TRY_HIP(hipMemcpy(h_alarm_trace, st->sa.d_mode_trace + std::max<uint32_t>(st->cfg.trace_cap, 1), n,
                       hipMemcpyDeviceToHost));
   if (trace_len > n) std::memset(h_alarm_trace + n, 0, trace_len - n);
+  return HIST_OK;
+}
+
+hist_status_t hist_stream_read_times(hist_stream_t *st, uint64_t *h_times_ns, uint32_t trace_len, void *stream) {
+  if (!st || (!h_times_ns && trace_len > 0)) return HIST_EINVAL;
+  TRY(stream_sync(st, static_cast<hipStream_t>(stream)));
+  const uint32_t n = std::min<uint32_t>(trace_len, st->cfg.trace_cap);
+  std::vector<uint64_t> ticks((size_t)n * 2);
+  if (n) TRY_HIP(hipMemcpy(ticks.data(), st->sa.d_time_trace, ticks.size() * 8, hipMemcpyDeviceToHost));
+  int dev = 0, khz = 0;
+  TRY_HIP(hipGetDevice(&dev));
+  TRY_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+  if (khz <= 0) return HIST_EDEVICE;
+  for (size_t i = 0; i < ticks.size(); ++i)   // ticks of a 1 kHz * khz clock -> ns; unwritten -> 0
+    h_times_ns[i] = ticks[i] == ~0ull ? 0 : (uint64_t)((long double)ticks[i] * 1.0e6L / (long double)khz);
+  for (size_t i = ticks.size(); i < (size_t)trace_len * 2; ++i) h_times_ns[i] = 0;
   return HIST_OK;
 }
 

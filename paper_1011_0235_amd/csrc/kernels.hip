@@ -27,6 +27,7 @@
 //                   serialised same-address atomics of peaked data.
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include "histmi_dev.h"
 
@@ -651,6 +652,9 @@ __device__ __forceinline__ uint32_t begin_segment(uint32_t *lds, const Params &P
         } else {
           kd = (mode == HIST_MODE_WAVEAGG) ? KIND_WAVE_AGG : KIND_WAVE;
         }
+        if (traced)   // the earliest start of this chunk's counting, over its workgroups
+          __hip_atomic_fetch_min(gmem(&P.time_trace[2u * (uint64_t)k]), (uint64_t)wall_clock64(), __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
         c.tag = tag;
         c.kind = kd;
         c.lg = lg;
@@ -1061,13 +1065,22 @@ __device__ __forceinline__ void stream_epilogue(const Params &P, Ctl &c, uint32_
     const uint32_t word = decide_pattern(P, c, h, bytes, &kind_lg);
     Decision *d = &P.slots[(uint64_t)k % P.nslot];
     st_agent(&d->hist[t], h);
+    // the time the decision is ready, taken before it is published: a chunk that waits for
+    // it begins counting later than this
+    const uint64_t ready = wall_clock64();
     publish_decision(P, d, (uint64_t)k, mode, kind_lg, word);
-    if (t == 0) __hip_atomic_fetch_add(&st->done, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (t == 0) {
+      __hip_atomic_fetch_add(&st->done, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if ((uint64_t)k < P.trace_cap) st_agent(&P.time_trace[2u * (uint64_t)k + 1u], ready);
+    }
     return;
   }
   const uint32_t slot = (uint32_t)((uint64_t)k % P.R);
   st_agent(&st->ring[(size_t)slot * 256u + t], ((uint64_t)(uint32_t)(k + 1) << 32) | h);
-  if (t == 0) st_agent(&st->ring_n[slot], ((uint64_t)((uint32_t)(k + 1) & kSizeGenMask) << kSizeBits) | bytes);
+  if (t == 0) {
+    st_agent(&st->ring_n[slot], ((uint64_t)((uint32_t)(k + 1) & kSizeGenMask) << kSizeBits) | bytes);
+    if ((uint64_t)k < P.trace_cap) st_agent(&P.time_trace[2u * (uint64_t)k + 1u], (uint64_t)wall_clock64());
+  }
   order_global();     // every entry is in before the CAS below (so a failing CAS means the
   __syncthreads();    // sequencer's last look will find them)
   if (P.alarm_pct || P.criterion != HIST_CRIT_MAXBIN)
@@ -1369,8 +1382,13 @@ __global__ void __launch_bounds__(kBlock) read_probe_kernel(gu32x4 *v, uint64_t 
 
 uint32_t ctl_bytes() { return (uint32_t)((sizeof(Ctl) + 15) & ~(size_t)15); }
 
-hipError_t launch_hist(const Params &P, const LaunchShape &sh, hipStream_t s) {
-  hipLaunchKernelGGL(hist_main<4>, dim3(sh.grid), dim3(kBlock), sh.lds_bytes, s, P);
+hipError_t launch_hist(const Params &P, const LaunchShape &sh, hipStream_t s, hipEvent_t done) {
+  if (done) {
+    // the event completes with the kernel's own dispatch: no marker packet between launches
+    hipExtLaunchKernelGGL(hist_main<4>, dim3(sh.grid), dim3(kBlock), sh.lds_bytes, s, nullptr, done, 0u, P);
+  } else {
+    hipLaunchKernelGGL(hist_main<4>, dim3(sh.grid), dim3(kBlock), sh.lds_bytes, s, P);
+  }
   return hipGetLastError();
 }
 

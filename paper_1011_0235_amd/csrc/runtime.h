@@ -14,7 +14,8 @@
 namespace histmi {
 
 // kernels.hip
-hipError_t launch_hist(const Params &P, const LaunchShape &sh, hipStream_t s);
+// `done`, if not null, completes when the kernel does (recorded by the dispatch itself).
+hipError_t launch_hist(const Params &P, const LaunchShape &sh, hipStream_t s, hipEvent_t done = nullptr);
 hipError_t launch_pattern_update(const uint64_t *h, uint32_t S, uint32_t rmax, hist_pattern_t *out, hipStream_t s);
 hipError_t launch_read_probe(const void *d_in, uint64_t nvec, uint64_t *d_sum, uint32_t grid, hipStream_t s);
 hipError_t set_kernel_attrs(uint32_t max_dyn_lds);
@@ -86,20 +87,19 @@ struct Scratch {
   hipEvent_t ev[2] = {nullptr, nullptr};
   int turn = 0;
   // recently uploaded descriptor sets, each in its own device buffer (an identical set is
-  // reused without a copy); `desc` points at the one the next launch uses
+  // reused without a copy); `desc` points at the one the next launch uses.  A Scratch serves
+  // launches on one HIP stream only, so a refill (a copy on that stream) never overtakes a
+  // launch still reading the entry.
   struct Cached {
     std::vector<uint8_t> blob;
     uint8_t *dev = nullptr;
     size_t cap = 0;
     uint64_t used = 0;
-    hipEvent_t ev = nullptr;      // recorded after the last launch that read this entry
   };
   Cached cache[4];
   int cur = -1;                   // cache entry `desc` points at (-1: desc_buf)
   uint64_t tick = 0;
 };
-// After a launch that read sc->desc: mark the cache entry as in use until `s` gets there.
-hist_status_t desc_used(Scratch *sc, hipStream_t s);
 void free_scratch(Scratch *sc);
 
 struct DevCtx {
@@ -125,8 +125,9 @@ uint32_t lds_bytes(const Params &P);
 uint32_t resident_per_cu(uint32_t lds);
 uint32_t blocks_per_cu(uint32_t family, uint32_t lds);
 
-// One segment cut into one tile per workgroup.
-hist_status_t run_single(DevCtx *d, Params &P, hipStream_t s);
+// One segment cut into one tile per workgroup.  own: a scratch that only launches on `s`
+// use, or nullptr for the HIP stream's own; done: as for launch_hist.
+hist_status_t run_single(DevCtx *d, Params &P, hipStream_t s, Scratch *own = nullptr, hipEvent_t done = nullptr);
 
 // Segments + tile map + per-workgroup bounds in one host buffer.
 struct MultiPlan {
@@ -147,9 +148,10 @@ hist_status_t plan_multi(std::vector<SegDesc> &segs, uint64_t tile, uint32_t max
 // one workgroup counts in 4-5 us, so a segment's start is charged 64 KiB on the axis the
 // shares are cut from.
 hist_status_t plan_split(std::vector<SegDesc> &segs, uint64_t tile, uint32_t max_grid, MultiPlan *mp);
-// own: a dedicated scratch (already sized, descriptors already on the device) or nullptr.
+// own: a dedicated scratch (already sized, descriptors already on the device) or nullptr;
+// either way one that only launches on `s` use.  done: as for launch_hist.
 hist_status_t run_multi(DevCtx *d, Params &P, const MultiPlan &mp, uint32_t copies, hipStream_t s, Scratch *own,
-                        bool dynamic, bool upload);
+                        bool dynamic, bool upload, hipEvent_t done = nullptr);
 
 // Device-resident stream states: allocation and release.
 struct StreamAlloc {
@@ -159,6 +161,7 @@ struct StreamAlloc {
   Decision *d_slots = nullptr;
   uint8_t *d_mode_trace = nullptr;    // [count][trace_cap] modes, then [count][trace_cap] alarms
   uint32_t *d_pat_trace = nullptr;
+  uint64_t *d_time_trace = nullptr;   // [count][trace_cap][2], all ones until written
 };
 hist_status_t stream_state_alloc(uint32_t count, uint32_t W, uint32_t theta, uint32_t S, uint32_t rmax, uint32_t lag,
                                  uint32_t nslot, uint32_t trace_cap, uint32_t alarm_pct, StreamAlloc *sa);

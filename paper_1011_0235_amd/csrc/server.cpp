@@ -130,15 +130,21 @@ bool hist_server::launch(Slot &sl, std::vector<uint64_t> &batch) {
       segs[j].stream_idx = r.sid;
     }
   }
+  hipStream_t s = hs[sl.hs];
+  if (segs.size() == 1) {
+    // a lone request spreads over the whole grid with no descriptors to upload (the
+    // launch carries it), so nothing but the kernel is queued; sl.ev completes with it
+    P.seg0 = segs[0];
+    return run_single(d, P, s, &sl.sc, sl.ev) == HIST_OK;
+  }
   const uint32_t fam = KIND_UNIFORM;
   const uint64_t tile = (uint64_t)g_tune[fam].tile_kib * 1024;
   const uint32_t maxg = (uint32_t)d->cus * blocks_per_cu(fam, lds_bytes(P));
   MultiPlan mp;
   if (plan_split(segs, tile, maxg, &mp) != HIST_OK) return false;
   const uint32_t copies = std::min<uint32_t>(64, pow2ceil32(std::max<uint32_t>(1, g_tune[fam].copies)));
-  hipStream_t s = hs[sl.hs];
-  if (run_multi(d, P, mp, copies, s, &sl.sc, false, true) != HIST_OK) return false;
-  return hipEventRecord(sl.ev, s) == hipSuccess;
+  // sl.ev completes with the launch (the slot's scratch only ever serves this HIP stream)
+  return run_multi(d, P, mp, copies, s, &sl.sc, false, true, sl.ev) == HIST_OK;
 }
 
 void hist_server::run() {

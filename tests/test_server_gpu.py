@@ -158,3 +158,75 @@ def test_server_decisions_stay_exact_under_degenerate_streams(hm):
         assert np.array_equal(o[i], ref[kinds[i]]), i
     assert hm.diag().wait_timeouts == 0
     sv.close()
+
+
+def drifting_pools_on_device(n_streams, pool_bytes, piece, seed):
+    """Per-stream pools of config-5 shape, generated on the device: consecutive pieces of a
+    clipped Normal whose mean walks (step sigma 4, start U[40, 215]) and whose sigma is
+    U[6, 40] per piece."""
+    g = np.random.default_rng(seed)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    out = []
+    for _ in range(n_streams):
+        p = torch.empty(pool_bytes, dtype=torch.uint8, device="cuda")
+        mu = float(g.uniform(40, 215))
+        for s in range(0, pool_bytes, piece):
+            e = min(pool_bytes, s + piece)
+            mu = float(np.clip(mu + 4.0 * g.standard_normal(), 0.0, 255.0))
+            sigma = float(g.uniform(6.0, 40.0))
+            z = torch.randn(e - s, device="cuda", generator=gen) * sigma + mu
+            p[s:e] = z.round_().clamp_(0, 255).to(torch.uint8)
+        out.append(p)
+    return out
+
+
+@pytest.fixture(scope="module")
+def config5_workload(hm):
+    """Device pools, requests and the oracle's histogram of every request (made once)."""
+    n_streams, pool = 64, 64 << 20
+    dp = drifting_pools_on_device(n_streams, pool, 4 << 20, G.ROOT_SEED + 55)
+    reqs = G.serve_requests(600.0, 0.5, n_streams=n_streams, pool_bytes=pool, item=77)
+    exp = np.zeros((len(reqs), 256), dtype=np.int64)
+    for sid in range(n_streams):
+        idx = [i for i, r in enumerate(reqs) if r.stream_id == sid]
+        if idx:
+            host = dp[sid].cpu().numpy()
+            exp[idx] = O.hist_many(host, [reqs[i].offset for i in idx], [reqs[i].size for i in idx]).astype(np.int64)
+    yield n_streams, dp, reqs, exp
+    del dp
+
+
+@pytest.mark.parametrize("theta,S,rmax,max_batch", [(0, 8192, 32, 64), (45, 960, 8, 64), (45, 960, 8, 1)])
+def test_config5_sizes_every_request_exact(hm, config5_workload, theta, S, rmax, max_batch):
+    """Requests of the served workload's shape: sizes log-uniform in [4 KiB, 64 MiB], 64 stream
+    ids, each a slice of its stream's drifting pool of 64 MiB; the first half arrives as a
+    Poisson stream (mostly one request per micro-batch), the rest at once.  Every request's
+    histogram and every stream id's running histogram equal the oracle's."""
+    n_streams, dp, reqs, exp = config5_workload
+    assert len(reqs) > 200
+    sv = hm.Server(hbm_budget_bytes=1 << 30, max_slots=256, n_stream_ids=n_streams, n_hip_streams=4,
+                   max_batch=max_batch, mode=hm.MODE_AUTO, theta_pct=theta, S=S, rmax=rmax)
+    out = torch.full((len(reqs), 256), -1, dtype=torch.int32, device="cuda")
+    tickets = []
+    import time
+    t0 = time.perf_counter()
+    half = len(reqs) // 2
+    for i, r in enumerate(reqs):
+        if i < half:
+            while time.perf_counter() - t0 < r.t_arrival:
+                pass
+        tickets.append(sv.submit(r.stream_id, int(dp[r.stream_id].data_ptr()) + r.offset, d_out=out[i], n=r.size))
+    sv.drain()
+    for i, tk in enumerate(tickets):
+        res = sv.poll(tk)
+        assert res.status == hm.OK and res.bytes == reqs[i].size, i
+    got = out.cpu().numpy().astype(np.int64)
+    bad = [i for i in range(len(reqs)) if not np.array_equal(got[i], exp[i])]
+    assert not bad, bad[:10]
+    for sid in range(n_streams):
+        want = exp[[i for i, r in enumerate(reqs) if r.stream_id == sid]].sum(axis=0)
+        assert np.array_equal(sv.stream_acc(sid).astype(np.int64), want), sid
+    st = sv.stats()
+    assert st.completed == len(reqs) and st.canceled == 0
+    sv.close()

@@ -669,3 +669,34 @@ def test_decision_waits_that_give_up(hm, W, alarm):
     if alarm:
         assert [int(x) for x in al] == ref["alarms"]
         assert int(snap.alarms) == sum(ref["alarms"])
+
+
+@pytest.mark.parametrize("W,theta,lag", [(1, 45, 0), (1, 45, 1), (1, 0, 0), (4, 45, 0)])
+def test_time_trace(hm, W, theta, lag):
+    """The per-chunk device timeline: every traced chunk that ran has a start and an end, the
+    end after the start; with decisions that depend on the data at lag 0 a chunk begins
+    counting only once the chunk before it has its decision (up to the clock's sampling
+    skew); untraced chunks read 0.  The traces and histograms stay exact."""
+    chunks = single_stream_chunks(256 << 10, 20)
+    cap = 16
+    st = hm.Stream(W=W, theta_pct=theta, S=960, rmax=8, lag=lag, trace_cap=cap)
+    arena = dev(np.concatenate(chunks))
+    base = int(arena.data_ptr())
+    bufs = [(base + k * (256 << 10), 256 << 10) for k in range(len(chunks))]
+    outs = torch.zeros((len(chunks), 256), dtype=torch.int32, device="cuda")
+    st.push_many(bufs[:11], d_out=outs[:11])
+    st.push_many(bufs[11:], d_out=outs[11:])
+    tt = st.read_times(len(chunks) + 2)
+    snap, modes, pats = st.read(cap)
+    st.close()
+    ref = O.stream_reference(chunks, W=W, theta_pct=theta, S=960, rmax=8, lag=lag)
+    assert np.array_equal(outs.cpu().numpy().astype(np.int64), ref["hists"].astype(np.int64))
+    assert [int(m) for m in modes] == ref["modes"][:cap]
+    assert tt.shape == (len(chunks) + 2, 2)
+    assert (tt[:cap] > 0).all()
+    assert (tt[cap:] == 0).all()
+    assert (tt[:cap, 1] >= tt[:cap, 0]).all()
+    if W == 1 and theta and lag == 0:
+        skew = 2000   # ns
+        for k in range(1, cap):
+            assert int(tt[k, 0]) + skew >= int(tt[k - 1, 1]), k
