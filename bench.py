@@ -147,7 +147,7 @@ def bench_config2(hm, O, chunks, exp, bufs, run_stream, stream):
                            ("forced_wavehist", hm.MODE_WAVEHIST)):
             st = hm.Stream(W=1, theta_pct=theta, S=S, rmax=rmax, lag=lag, trace_cap=0)
             d0 = hm.diag()
-            tms, _ = run_stream(st, 8, 3, per_launch_events=False, n_hip=2, mode=mode)
+            tms = run_stream(st, 8, 3, n_hip=2, mode=mode)
             d1 = hm.diag()
             st.close()
             row[name + "_GBps"] = round(nbytes * 8 / (tms * 1e-3) / 1e9, 1)
@@ -278,22 +278,21 @@ def bench_xray(hm, G, O, torch, dev, hip_streams, S, rmax, lag, plag, theta, fra
         reps = 4
         for r in range(2):   # untimed: the launch shapes, descriptors and clocks settle
             st.push_many(bufs, mode=mode, d_out=outs[r & 1], stream=hip_streams[r & 1])
+        # timed as the headline: a start event on the first launch's HIP stream, the later of
+        # the two HIP streams' end events
         e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        cur = torch.cuda.current_stream()
         torch.cuda.synchronize()
-        e0.record(cur)
-        for h in hip_streams:
-            h.wait_event(e0)
+        e0.record(hip_streams[0])
+        hip_streams[1].wait_event(e0)
         for r in range(reps):
             st.push_many(bufs, mode=mode, d_out=outs[r & 1], stream=hip_streams[r & 1])
+        ends = []
         for h in hip_streams:
-            ev = torch.cuda.Event()
+            ev = torch.cuda.Event(enable_timing=True)
             ev.record(h)
-            cur.wait_event(ev)
-        e1.record(cur)
+            ends.append(ev)
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
+        ms = max(e0.elapsed_time(ev) for ev in ends) / reps
         st.close()
         n_ahist = sum(1 for m in ref["modes"] if m == hm.MODE_AHIST)
         switches = sum(1 for a, b in zip(ref["modes"], ref["modes"][1:]) if a != b)
@@ -599,47 +598,37 @@ def main():
     # once; each chunk waits on the device for the decision it runs with).
     hip_streams = [torch.cuda.Stream(), torch.cuda.Stream()]
 
-    def run_stream(st, steps, warmup, per_launch_events=True, n_hip=2, mode=None):
+    def run_stream(st, steps, warmup, n_hip=2, mode=None):
+        """Time `steps` pushes of the whole stream after `warmup` untimed ones, alternating
+        n_hip HIP streams.  The region starts with an event on the first timed launch's HIP
+        stream (the other one waits for it before its first timed launch) and ends with the
+        later of the two streams' end events: nothing but kernels between the launches."""
         mode = hm.MODE_AUTO if mode is None else mode
         for i in range(warmup):
             st.push_many(bufs[i % N_ARENAS], mode=mode, d_out=outs[i & 1], stream=hip_streams[(i & 1) % n_hip])
         torch.cuda.synchronize()
-        ends = []
+        used = [hip_streams[((warmup + i) & 1) % n_hip] for i in range(min(steps, n_hip))]
         t_start = torch.cuda.Event(enable_timing=True)
-        t_end = torch.cuda.Event(enable_timing=True)
-        t_start.record(stream)
-        for h in hip_streams:
+        t_start.record(used[0])
+        for h in used[1:]:
             h.wait_event(t_start)
         for i in range(steps):
             j = warmup + i   # arenas, outputs and HIP streams rotate as in the warm-up
-            hs = hip_streams[(j & 1) % n_hip]
-            st.push_many(bufs[j % N_ARENAS], mode=mode, d_out=outs[j & 1], stream=hs)
-            if per_launch_events:
-                e = torch.cuda.Event(enable_timing=True)
-                e.record(hs)   # on the stream the launch went to
-                ends.append(e)
-        for h in hip_streams:
-            ev = torch.cuda.Event()
-            ev.record(h)
-            stream.wait_event(ev)
-        t_end.record(stream)
+            st.push_many(bufs[j % N_ARENAS], mode=mode, d_out=outs[j & 1], stream=hip_streams[(j & 1) % n_hip])
+        t_end = []
+        for h in used:
+            e = torch.cuda.Event(enable_timing=True)
+            e.record(h)
+            t_end.append(e)
         torch.cuda.synchronize()
-        total_ms = t_start.elapsed_time(t_end)
-        # a launch's share of the device in steady state: the interval between its completion
-        # and the previous launch's (launches overlap, so start-to-end spans would count the
-        # overlap twice; the first timed launch, which starts alone, is left out)
-        if len(ends) > 1:
-            launch_ms = [ends[i - 1].elapsed_time(ends[i]) for i in range(1, len(ends))]
-        else:
-            launch_ms = [t_start.elapsed_time(e) for e in ends]
-        return total_ms, launch_ms
+        return max(t_start.elapsed_time(e) for e in t_end)
 
     # ---- headline (no event between the timed launches: each would add a packet, and a few
     # microseconds, between kernels)
     st = hm.Stream(W=1, theta_pct=theta, S=S, rmax=rmax, lag=lag, trace_cap=0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    total_ms, _ = run_stream(st, args.steps, args.warmup, per_launch_events=False)
+    total_ms = run_stream(st, args.steps, args.warmup)
     wall = time.perf_counter() - t0
     ms_per_step = total_ms / args.steps
     value = nbytes * args.steps / (total_ms * 1e-3) / 1e9
@@ -762,7 +751,7 @@ def main():
             st = hm.Stream(W=w_, theta_pct=th, S=s_, rmax=r_, lag=l, trace_cap=0, alarm_pct=al, criterion=cr,
                            kappa_pct=kp)
             d0 = hm.diag()
-            tms, _ = run_stream(st, 8, 3, per_launch_events=False, n_hip=nh)
+            tms = run_stream(st, 8, 3, n_hip=nh)
             d1 = hm.diag()
             row = {"GB/s": round(nbytes * 8 / (tms * 1e-3) / 1e9, 1), "ms_per_step": round(tms / 8, 4)}
             # bounded waits that ran out (a decision or a merge): none is expected

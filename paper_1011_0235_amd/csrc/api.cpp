@@ -291,11 +291,12 @@ uint32_t blocks_per_cu(uint32_t family, uint32_t lds) {
 
 hist_status_t run_single(DevCtx *d, Params &P, hipStream_t s, Scratch *own, hipEvent_t done) {
   const uint64_t n = P.seg0.size;
-  const uint32_t lds = lds_bytes(P);
   const uint32_t fam = P.st ? (uint32_t)KIND_UNIFORM : P.kind;
+  const uint32_t lds = lds_bytes(P);
   const uint32_t G = (uint32_t)d->cus * blocks_per_cu(fam, lds);
-  const uint64_t tile = std::max<uint64_t>(16384, ceil_div(ceil_div(n, G), 16384) * 16384);
-  const uint32_t ntiles = (uint32_t)std::max<uint64_t>(1, ceil_div(n, tile));
+  // the buffer is shared out in 16 KiB steps to whichever workgroup asks next: one
+  // workgroup per step at most, else the whole grid
+  const uint32_t ntiles = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(G, ceil_div(n, 16384)));
   const uint32_t copies = std::min<uint32_t>(g_single_copies, pow2ceil32(ntiles));
   Scratch *sc = own;
   if (!sc) TRY(get_scratch(d, s, 1, copies, 0, &sc));
@@ -324,6 +325,7 @@ hist_status_t run_multi(DevCtx *d, Params &P, const MultiPlan &mp, uint32_t copi
   P.segs = reinterpret_cast<const SegDesc *>(sc->desc);
   P.recs = reinterpret_cast<const TileRec *>(sc->desc + mp.seg_bytes);
   P.bounds = reinterpret_cast<const uint32_t *>(sc->desc + mp.seg_bytes + mp.rec_bytes);
+  P.starts = mp.start_off ? reinterpret_cast<const WgStart *>(sc->desc + mp.start_off) : nullptr;
   P.nseg = mp.nseg;
   P.single = 0;
   P.ntiles = mp.ntiles;
@@ -434,6 +436,13 @@ struct hist_stream {
   hipStream_t ev_on[2] = {nullptr, nullptr};
   uint32_t evi = 0;
   std::vector<hipStream_t> used;   // HIP streams with launches of this stream since the last read
+  // Waiting for the launch two before splits the launches into two chains (odd and even);
+  // chunks that wait for decisions tie the chains together on the device, but chunks whose
+  // decisions the host knows do not, so one chain could run ahead of the other, further
+  // than the decision ring holds.  Such streams therefore order a launch after every
+  // earlier one once the chunks pushed since the last such point would pass
+  // kMaxChunksPerLaunch: at most 2 x kMaxChunksPerLaunch chunks are ever in flight.
+  uint64_t since_join = 0;
 };
 
 // When is the decision after a chunk a function of the chunk sizes alone?  With W = 1 and no
@@ -465,7 +474,8 @@ static hist_status_t wait_slot(hist_stream *st, uint32_t i, hipStream_t s) {
   return HIST_OK;
 }
 // Before a launch: wait for the launch two before it (at most two in flight), or, with
-// `serialize`, for both earlier ones (no overlap).
+// `serialize`, for both earlier ones (no overlap; every earlier launch is then done, since
+// each waited for the one two before it).
 static hist_status_t stream_launch_begin(hist_stream *st, hipStream_t s, bool serialize) {
   TRY(wait_slot(st, st->evi, s));
   if (serialize) TRY(wait_slot(st, st->evi ^ 1u, s));
@@ -855,7 +865,9 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
     else
       TRY(plan_multi(segs, tile, maxg, &mp));
     const uint32_t copies = std::min<uint32_t>(64, pow2ceil32(std::max<uint32_t>(1, g_tune[fam].copies)));
-    TRY(stream_launch_begin(st, s, serialize));
+    const bool join = known && st->since_join + m > kMaxChunksPerLaunch;
+    TRY(stream_launch_begin(st, s, serialize || join));
+    st->since_join = join ? m : st->since_join + m;
     TRY(run_multi(d, P, mp, copies, s, nullptr, !(known || ahead), true));
     stream_launch_end(st, s);
     for (uint32_t j = 0; j < m; ++j) st->recent[(st->pushed + j) % ring] = h_sizes[first + j];

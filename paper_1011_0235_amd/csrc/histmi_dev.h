@@ -106,11 +106,23 @@ struct TileRec {
   uint32_t seg;          // index into Params::segs
 };
 
+// Where a workgroup of a static launch starts: its tile range, its first tile and that
+// tile's segment, in one record, so that starting costs one memory round trip instead of
+// three dependent ones (tile range, then tile, then segment).
+struct WgStart {
+  uint32_t tile, tile_end;   // tiles [tile, tile_end) (empty when equal)
+  TileRec first;             // tile `tile` (zero if none)
+  SegDesc seg;               // its segment's descriptor
+};
+constexpr uint32_t kStartWords = sizeof(WgStart) / 4;
+static_assert(sizeof(WgStart) % 4 == 0 && kStartWords <= 64, "one word per lane of the first wavefront");
+
 struct Params {
   const SegDesc *segs;       // device array of nseg descriptors (unused when single)
   SegDesc seg0;              // the descriptor when single
   const TileRec *recs;       // [ntiles] tiles in launch order (unused when single)
   const uint32_t *bounds;    // [grid + 1] static launches: workgroup g takes tiles [bounds[g], bounds[g+1])
+  const WgStart *starts;     // [grid] static launches: each workgroup's start record
   uint32_t nseg;
   uint32_t ntiles;
   uint32_t single;           // 1: one buffer described by seg0, spread over the whole grid

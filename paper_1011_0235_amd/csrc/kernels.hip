@@ -61,6 +61,7 @@ struct Ctl {
   SegDesc sd[2];           // the current segment's descriptor (and the next one's, being staged)
   TileRec nrec[2];         // the next tile's record, by tile parity
   uint32_t ntile[2];       // the next tile's index, by tile parity
+  uint32_t start[6];       // static launches: tile range and first tile of this workgroup
   uint32_t red32[kWaves];
   uint64_t red64[kWaves];
   uint32_t cls_cnt[kWaves][8];
@@ -1102,19 +1103,26 @@ __device__ __forceinline__ void stream_epilogue(const Params &P, Ctl &c, uint32_
 // Counts only grow and the exact total is known, so a matching sum means every
 // contribution is in -- no per-flush acknowledgement wait is needed.
 __device__ __forceinline__ uint32_t flush_issue(uint32_t *lds, const Params &P, Ctl &c, uint32_t s, uint32_t kind,
-                                                uint32_t lg, uint32_t nt, bool synced) {
+                                                uint32_t lg, uint32_t nt, bool synced, bool ticket = true) {
   const uint32_t t = threadIdx.x;
   if (!synced) __syncthreads();   // the caller's barrier already ended every add otherwise
   const uint32_t h = table_bin(lds, c, kind, lg);
   const uint32_t copies = 1u << P.clog2;
   uint32_t *part = P.partial + ((size_t)s << (P.clog2 + 8));
-  if (h) __hip_atomic_fetch_add(&part[((blockIdx.x & (copies - 1u)) << 8) | t], h, __ATOMIC_RELAXED,
-                                __HIP_MEMORY_SCOPE_AGENT);
+  // bins t and t + 1 (t even) go in one 64-bit atomic: half as many atomics, which the
+  // memory side performs one queue at a time when the whole grid flushes together.  Each
+  // 32-bit half only ever holds a count of this segment (< 2^32), so no carry crosses.
+  const uint32_t hn = __shfl_xor(h, 1, 64);
+  const uint64_t pair = (uint64_t)h | ((uint64_t)hn << 32);
+  if (!(t & 1u) && pair)
+    __hip_atomic_fetch_add(reinterpret_cast<uint64_t *>(&part[((blockIdx.x & (copies - 1u)) << 8) | t]), pair,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 #ifdef HISTMI_STRICT_FENCES
   __threadfence();
 #endif
   uint32_t before = 0;
-  if (t == 0) before = __hip_atomic_fetch_add(&P.seg_done[s], nt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (ticket && t == 0)
+    before = __hip_atomic_fetch_add(&P.seg_done[s], nt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return before;
 }
 
@@ -1205,10 +1213,25 @@ __device__ __forceinline__ void single_path(uint32_t *lds, const Params &P, Ctl 
   else if (kind == KIND_WAVE_AGG) run_strided<KIND_WAVE_AGG, U>(lds, make_adder<KIND_WAVE_AGG>(lds, P, c), sd.ptr, sd.size);
   else if (kind == KIND_UNIFORM) run_strided<KIND_UNIFORM, U>(lds, make_adder<KIND_UNIFORM>(lds, P, c), sd.ptr, sd.size);
   else run_strided<KIND_LOOKUP, U>(lds, make_adder<KIND_LOOKUP>(lds, P, c), sd.ptr, sd.size);
-  const uint32_t before = flush_issue(lds, P, c, 0, kind, lg, 1, false);
-  if (t == 0) c.flag = (before + 1 == sd.ntiles) ? 1u : 0u;
+  // The ticket that elects the finalizer goes through one counter per group of workgroups
+  // (blockIdx mod 8, which is also the XCD a workgroup runs on): atomics on one address are
+  // performed one after another, about 10 ns each, and the whole grid finishing together
+  // would queue several microseconds on a single counter.  The last workgroup of each group
+  // then takes a ticket of the segment's counter, and the last of those finalizes.
+  flush_issue(lds, P, c, 0, kind, lg, 0, false, false);
+  if (t == 0) {
+    const uint32_t G = gridDim.x, g = blockIdx.x & 7u, groups = G < 8u ? G : 8u;
+    const uint32_t in_group = (G - g + 7u) >> 3;
+    uint32_t last = 0;
+    if (__hip_atomic_fetch_add(&P.ctr[8 + g], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u == in_group)
+      last = __hip_atomic_fetch_add(&P.seg_done[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u == groups;
+    c.flag = last;
+  }
   __syncthreads();
-  if (c.flag) finalize_segment(P, c, 0, sd);
+  if (c.flag) {
+    if (t < 8) st_agent(&P.ctr[8 + t], 0u);   // every workgroup has taken its group ticket
+    finalize_segment(P, c, 0, sd);
+  }
 }
 
 // The segment descriptor is staged through LDS (c.sd[]) rather than held in registers: lanes
@@ -1235,14 +1258,27 @@ template <int U>
 __device__ __forceinline__ void multi_path(uint32_t *lds, const Params &P, Ctl &c) {
   const uint32_t t = threadIdx.x;
   uint32_t tile, tile_end = P.ntiles;
+  uint32_t first_lo = 0, first_hi = 0, first_len = 0, first_seg = 0;   // static: the first tile
   if (P.dynamic) {
     if (t == 0) c.next_tile = atomicAdd(&P.ctr[0], 1u);
     __syncthreads();
     tile = c.next_tile;
     __syncthreads();
   } else {
-    tile = P.bounds[blockIdx.x];
-    tile_end = P.bounds[blockIdx.x + 1];
+    // one memory round trip brings the workgroup's tile range, its first tile and that
+    // tile's segment descriptor (one word per lane of the first wavefront)
+    if (t < kStartWords) {
+      const uint32_t w = reinterpret_cast<const uint32_t *>(P.starts + blockIdx.x)[t];
+      if (t < 6) c.start[t] = w;
+      else reinterpret_cast<uint32_t *>(&c.sd[0])[t - 6] = w;
+    }
+    __syncthreads();
+    tile = __builtin_amdgcn_readfirstlane(c.start[0]);   // uniform: keep it in scalar registers
+    tile_end = __builtin_amdgcn_readfirstlane(c.start[1]);
+    first_lo = __builtin_amdgcn_readfirstlane(c.start[2]);
+    first_hi = __builtin_amdgcn_readfirstlane(c.start[3]);
+    first_len = __builtin_amdgcn_readfirstlane(c.start[4]);
+    first_seg = __builtin_amdgcn_readfirstlane(c.start[5]);
   }
   const uint32_t rot = blockIdx.x * 7u;
   Pipe<U> a;
@@ -1251,13 +1287,20 @@ __device__ __forceinline__ void multi_path(uint32_t *lds, const Params &P, Ctl &
   uint32_t sp = 0;    // c.sd[sp] describes the current segment
   uint32_t par = 0;   // parity of the tile step (c.ntile / c.nrec slot)
   if (tile < tile_end) {
-    const TileRec r0 = P.recs[tile];
-    const uint32_t w = seg_word(P, r0.seg);
-    const uint64_t hint = tag_prefetch(P, r0.seg);
-    rg = prime_range<U>(a, r0.addr, r0.len, rot);
-    cur = r0.seg;
-    seg_stage(c, sp, w);
-    __syncthreads();
+    uint64_t hint;
+    if (P.dynamic) {
+      const TileRec r0 = P.recs[tile];
+      const uint32_t w = seg_word(P, r0.seg);
+      hint = tag_prefetch(P, r0.seg);
+      rg = prime_range<U>(a, r0.addr, r0.len, rot);
+      cur = r0.seg;
+      seg_stage(c, sp, w);
+      __syncthreads();
+    } else {
+      rg = prime_range<U>(a, (uint64_t)first_lo | ((uint64_t)first_hi << 32), first_len, rot);
+      cur = first_seg;
+      hint = 0;   // loaded where it is used: a prefetch here costs the kernel its fourth wave per SIMD
+    }
     kind = begin_segment(lds, P, c, c.sd[sp], hint);
     lg = c.lg;
   }

@@ -108,11 +108,11 @@ extern "C" hist_status_t hist_u8_noalloc(const void *d_in, size_t n, uint32_t *d
   TRY(select_kind(mode, h_pat, &P));
   NoallocDev *nd;
   TRY(noalloc_dev(&nd));
-  // the launch shape of hist_u8 (run_single): one tile per workgroup, at least 16 KiB each
+  // the launch shape of hist_u8 (run_single): one workgroup per 16 KiB step at most, else
+  // the whole grid
   const uint32_t lds = lds_bytes(P);
   const uint32_t G = (uint32_t)nd->cus * blocks_per_cu(P.kind, lds);
-  const uint64_t tile = std::max<uint64_t>(16384, ceil_div(ceil_div(n, G), 16384) * 16384);
-  const uint32_t ntiles = (uint32_t)std::max<uint64_t>(1, ceil_div(n, tile));
+  const uint32_t ntiles = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(G, ceil_div(n, 16384)));
   const uint32_t copies = std::min<uint32_t>(g_single_copies, pow2ceil32(ntiles));
   if (copies > kNoallocCopies) return HIST_ENOMEM;   // more scratch than the array holds
   hipStream_t s = static_cast<hipStream_t>(stream);

@@ -51,7 +51,9 @@ hist_status_t plan_split(std::vector<SegDesc> &segs, uint64_t tile, uint32_t max
   mp->grid = G;
   mp->seg_bytes = ((size_t)n * sizeof(SegDesc) + 15) & ~(size_t)15;
   mp->rec_bytes = (size_t)ntiles * sizeof(TileRec);
-  mp->blob.assign(mp->seg_bytes + mp->rec_bytes + ((size_t)G + 1) * 4, 0);
+  const size_t bounds_bytes = (((size_t)G + 1) * 4 + 15) & ~(size_t)15;
+  mp->start_off = mp->seg_bytes + mp->rec_bytes + bounds_bytes;
+  mp->blob.assign(mp->start_off + (size_t)G * sizeof(WgStart), 0);
   std::memcpy(mp->blob.data(), segs.data(), (size_t)n * sizeof(SegDesc));
   std::memcpy(mp->blob.data() + mp->seg_bytes, recs.data(), mp->rec_bytes);
   uint32_t *bounds = reinterpret_cast<uint32_t *>(mp->blob.data() + mp->seg_bytes + mp->rec_bytes);
@@ -60,6 +62,15 @@ hist_status_t plan_split(std::vector<SegDesc> &segs, uint64_t tile, uint32_t max
   for (uint32_t w = 0; w <= G; ++w) {
     while (i < ntiles && owner[i] < w) ++i;
     bounds[w] = (w == G) ? ntiles : i;
+  }
+  WgStart *starts = reinterpret_cast<WgStart *>(mp->blob.data() + mp->start_off);
+  for (uint32_t w = 0; w < G; ++w) {
+    starts[w].tile = bounds[w];
+    starts[w].tile_end = bounds[w + 1];
+    if (bounds[w] < bounds[w + 1]) {
+      starts[w].first = recs[bounds[w]];
+      starts[w].seg = segs[recs[bounds[w]].seg];
+    }
   }
   return HIST_OK;
 }

@@ -131,12 +131,13 @@ hist_status_t run_single(DevCtx *d, Params &P, hipStream_t s, Scratch *own = nul
 
 // Segments + tile map + per-workgroup bounds in one host buffer.
 struct MultiPlan {
-  std::vector<uint8_t> blob;   // SegDesc[n] | TileRec[ntiles] | uint32 bounds[grid + 1]
+  std::vector<uint8_t> blob;   // SegDesc[n] | TileRec[ntiles] | uint32 bounds[grid + 1] | WgStart[grid] (static)
   uint32_t nseg = 0;
   uint32_t ntiles = 0;
   uint32_t grid = 0;
   size_t seg_bytes = 0;
   size_t rec_bytes = 0;
+  size_t start_off = 0;        // offset of the WgStart section (static plans), 0 if none
 };
 // segs: ptr/size/out/acc/chunk/stream_idx filled; tile0/ntiles are filled here.
 // Launches whose chunks may wait: tiles of at most `tile` bytes, in segment order, handed out

@@ -50,6 +50,18 @@ static double split_case(const std::vector<uint64_t> &sizes, uint32_t maxg, uint
   const TileRec *r = reinterpret_cast<const TileRec *>(mp.blob.data() + mp.seg_bytes);
   const uint32_t *b = reinterpret_cast<const uint32_t *>(mp.blob.data() + mp.seg_bytes + mp.rec_bytes);
   if (mp.grid < 1 || mp.grid > maxg || b[0] != 0 || b[mp.grid] != mp.ntiles) return 0;
+  // each workgroup's start record: its range, its first tile and that tile's segment
+  if (mp.start_off < mp.seg_bytes + mp.rec_bytes + (mp.grid + 1) * 4 || mp.start_off % 8 ||
+      mp.blob.size() != mp.start_off + (size_t)mp.grid * sizeof(WgStart))
+    return 0;
+  const WgStart *st = reinterpret_cast<const WgStart *>(mp.blob.data() + mp.start_off);
+  const SegDesc *sd = reinterpret_cast<const SegDesc *>(mp.blob.data());
+  for (uint32_t w = 0; w < mp.grid; ++w) {
+    if (st[w].tile != b[w] || st[w].tile_end != b[w + 1]) return 0;
+    if (b[w] < b[w + 1] && (std::memcmp(&st[w].first, &r[b[w]], sizeof(TileRec)) != 0 ||
+                            std::memcmp(&st[w].seg, &sd[r[b[w]].seg], sizeof(SegDesc)) != 0))
+      return 0;
+  }
   uint64_t mx = 0, sum = 0;
   for (uint32_t w = 0; w < mp.grid; ++w) {
     if (b[w] > b[w + 1]) return 0;
