@@ -145,12 +145,20 @@ def bench_config2(hm, O, chunks, exp, bufs, run_stream, stream):
         row = {}
         for name, mode in (("auto", hm.MODE_AUTO), ("forced_ahist", hm.MODE_AHIST),
                            ("forced_wavehist", hm.MODE_WAVEHIST)):
-            st = hm.Stream(W=1, theta_pct=theta, S=S, rmax=rmax, lag=lag, trace_cap=0)
+            # every chunk of the 3 + 8 pushes is traced: the device timeline of the 8 timed
+            # ones shows the per-chunk time and the rate of the shader's cycle counter inside
+            # the finalizers (which falls with the engine clock)
+            st = hm.Stream(W=1, theta_pct=theta, S=S, rmax=rmax, lag=lag, trace_cap=11 * n)
             d0 = hm.diag()
             tms = run_stream(st, 8, 3, n_hip=2, mode=mode)
             d1 = hm.diag()
+            tt = st.read_times(11 * n).astype(np.int64)[3 * n:]
             st.close()
             row[name + "_GBps"] = round(nbytes * 8 / (tms * 1e-3) / 1e9, 1)
+            dt = np.diff(tt[:, 1]) / 1e3
+            row[name + "_us_per_chunk_p50_p90_max"] = [round(float(x), 2) for x in
+                                                        (np.median(dt), np.percentile(dt, 90), dt.max())]
+            row[name + "_cycle_counter_MHz_p10_p50_p90"] = [int(x) for x in np.percentile(tt[:, 2], [10, 50, 90])]
             if d1.wait_timeouts != d0.wait_timeouts:
                 row[name + "_wait_timeouts"] = int(d1.wait_timeouts - d0.wait_timeouts)
         st = hm.Stream(W=1, theta_pct=theta, S=S, rmax=rmax, lag=lag, trace_cap=n)
@@ -169,6 +177,7 @@ def bench_config2(hm, O, chunks, exp, bufs, run_stream, stream):
         gbps = [round(c.size / (u * 1e-6) / 1e9, 1) for c, u in zip(chunks[1:], per_chunk_us)]
         row["traced_push"] = {
             "us_per_chunk_p10_p50_p90": [round(float(x), 2) for x in np.percentile(per_chunk_us, [10, 50, 90])],
+            "cycle_counter_MHz_p10_p50_p90": [int(x) for x in np.percentile(tt[:, 2], [10, 50, 90])],
             "count_us_p50": round(float(np.median(count_us)), 2),
             "per_chunk_GBps": gbps,
             "mode_trace": "".join("A" if m == hm.MODE_AHIST else "W" for m in ref["modes"]),
@@ -391,17 +400,18 @@ def bench_ingest(hm, G, O, torch, dev):
         b = 1 + int(np.argmin(times[1:]))
         seg = tt[b * nch:(b + 1) * nch]
         gaps = (seg[1:, 0] - seg[:-1, 1]) / 1e3
-        return times[b], ok, float(gaps.max()), int(np.argmax(gaps)) + 1
+        return times[b], ok, float(gaps.max()), int(np.argmax(gaps)) + 1, int(np.median(seg[:, 2]))
 
     fig = {}
     for W in (1, 32, 128, 256):
         row = {}
         for K in ((1, 2, 4, 8, 16, 32, 64, 128, 256) if W == 1 else (1, 16, 256)):
             ing = hm.Ingest(n_hip_streams=K, slot_bytes=n)
-            t, ok, gap_us, gap_k = ingest_pass(ing, W)
+            t, ok, gap_us, gap_k, mhz = ingest_pass(ing, W)
             ing.close()
             row[K] = {"pct_of_sequential": round(100 * t / t_seq, 1), "GB/s": round(nb / t / 1e9, 2),
-                      "parity_exact": ok, "max_gap_us": round(gap_us, 1), "max_gap_before_chunk": gap_k}
+                      "parity_exact": ok, "max_gap_us": round(gap_us, 1), "max_gap_before_chunk": gap_k,
+                      "cycle_counter_MHz_p50": mhz}
         fig["W%d" % W] = row
     res["pipelined"] = fig
     res["wait_timeouts"] = int(hm.diag().wait_timeouts)   # in-kernel decision waits that gave up (0 expected)

@@ -258,12 +258,13 @@ hist_status_t hist_stream_read_alarms(hist_stream_t *st, uint8_t *h_alarm_trace,
 /* Per-chunk timeline of the device, for the chunks of the trace (the per-chunk breakdown of
  * a stream's time behind Sec. III.B's pipelining: how long each chunk waits for its decision
  * and how long it takes).  Synchronous like hist_stream_read.  h_times_ns: HOST
- * uint64[trace_len][2]; entry k = {the time the first workgroup began counting chunk k
- * (after its decision arrived), the time chunk k's finalizer was done (its decision
- * published; with W > 1 or change detection: its histogram handed to the in-order
- * sequencer)}, in nanoseconds of the device's constant-rate wall clock (differences are
- * meaningful, the origin is not).  0 for chunks beyond trace_cap or not yet run.
- * HIST_EINVAL if h_times_ns is NULL with trace_len > 0. */
+ * uint64[trace_len][3]; entry k = {the time the first workgroup began counting chunk k
+ * (after its decision arrived), the time chunk k's decision was ready (with W > 1 or change
+ * detection: its histogram handed to the in-order sequencer), the rate of the shader's
+ * cycle counter (s_memtime) in ticks per microsecond measured inside chunk k's finalizer,
+ * which follows the engine clock}; times in nanoseconds of the device's constant-rate
+ * wall clock (differences are meaningful, the origin is not).  0 for chunks beyond
+ * trace_cap or not yet run.  HIST_EINVAL if h_times_ns is NULL with trace_len > 0. */
 hist_status_t hist_stream_read_times(hist_stream_t *st, uint64_t *h_times_ns, uint32_t trace_len, void *stream);
 
 /* Synchronous; waits for the device before freeing. */

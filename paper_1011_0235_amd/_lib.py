@@ -427,9 +427,10 @@ class Stream:
         return out[:trace_len]
 
     def read_times(self, trace_len: int, stream=None) -> np.ndarray:
-        """Device timeline of the traced chunks: uint64[trace_len, 2] ns = (first workgroup began
-        counting chunk k, chunk k's finalizer done); 0 where not traced or not run."""
-        out = np.zeros((max(trace_len, 1), 2), dtype=np.uint64)
+        """Device timeline of the traced chunks: uint64[trace_len, 3] = (ns when the first
+        workgroup began counting chunk k, ns when its decision was ready, the shader cycle
+        counter's rate in ticks per us inside its finalizer); 0 where not traced or not run."""
+        out = np.zeros((max(trace_len, 1), 3), dtype=np.uint64)
         _check(load().hist_stream_read_times(self._h, out.ctypes.data_as(c_u64p), int(trace_len), _stream(stream)),
                "hist_stream_read_times")
         return out[:trace_len]

@@ -359,7 +359,7 @@ hist_status_t stream_state_alloc(uint32_t count, uint32_t W, uint32_t theta, uin
             hipMalloc(&sa->d_slots, (size_t)count * nslot * sizeof(Decision)) == hipSuccess &&
             hipMalloc(&sa->d_mode_trace, (size_t)count * tc * 2) == hipSuccess &&
             hipMalloc(&sa->d_pat_trace, (size_t)count * tc * 256 * 4) == hipSuccess &&
-            hipMalloc(&sa->d_time_trace, (size_t)count * tc * 2 * 8) == hipSuccess;
+            hipMalloc(&sa->d_time_trace, (size_t)count * tc * 3 * 8) == hipSuccess;
   if (!ok) {
     stream_state_free(sa);
     return HIST_ENOMEM;
@@ -390,7 +390,7 @@ hist_status_t stream_state_alloc(uint32_t count, uint32_t W, uint32_t theta, uin
        hipMemset(sa->d_slots, 0, (size_t)count * nslot * sizeof(Decision)) == hipSuccess &&
        hipMemset(sa->d_mode_trace, 0, (size_t)count * tc * 2) == hipSuccess &&
        hipMemset(sa->d_pat_trace, 0, (size_t)count * tc * 256 * 4) == hipSuccess &&
-       hipMemset(sa->d_time_trace, 0xFF, (size_t)count * tc * 2 * 8) == hipSuccess;
+       hipMemset(sa->d_time_trace, 0xFF, (size_t)count * tc * 3 * 8) == hipSuccess;
   if (!ok) {
     stream_state_free(sa);
     return HIST_EDEVICE;
@@ -942,15 +942,19 @@ hist_status_t hist_stream_read_times(hist_stream_t *st, uint64_t *h_times_ns, ui
   if (!st || (!h_times_ns && trace_len > 0)) return HIST_EINVAL;
   TRY(stream_sync(st, static_cast<hipStream_t>(stream)));
   const uint32_t n = std::min<uint32_t>(trace_len, st->cfg.trace_cap);
-  std::vector<uint64_t> ticks((size_t)n * 2);
-  if (n) TRY_HIP(hipMemcpy(ticks.data(), st->sa.d_time_trace, ticks.size() * 8, hipMemcpyDeviceToHost));
+  std::vector<uint64_t> raw((size_t)n * 3);
+  if (n) TRY_HIP(hipMemcpy(raw.data(), st->sa.d_time_trace, raw.size() * 8, hipMemcpyDeviceToHost));
   int dev = 0, khz = 0;
   TRY_HIP(hipGetDevice(&dev));
   TRY_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
   if (khz <= 0) return HIST_EDEVICE;
-  for (size_t i = 0; i < ticks.size(); ++i)   // ticks of a 1 kHz * khz clock -> ns; unwritten -> 0
-    h_times_ns[i] = ticks[i] == ~0ull ? 0 : (uint64_t)((long double)ticks[i] * 1.0e6L / (long double)khz);
-  for (size_t i = ticks.size(); i < (size_t)trace_len * 2; ++i) h_times_ns[i] = 0;
+  for (size_t i = 0; i < raw.size(); ++i) {   // unwritten entries (all ones) -> 0
+    const uint64_t x = raw[i];
+    if (x == ~0ull) h_times_ns[i] = 0;
+    else if (i % 3 == 2) h_times_ns[i] = x;   // MHz as measured
+    else h_times_ns[i] = (uint64_t)((long double)x * 1.0e6L / (long double)khz);   // ticks -> ns
+  }
+  for (size_t i = raw.size(); i < (size_t)trace_len * 3; ++i) h_times_ns[i] = 0;
   return HIST_OK;
 }
 

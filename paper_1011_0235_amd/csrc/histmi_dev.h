@@ -157,9 +157,10 @@ struct Params {
   uint32_t kappa;            // collision-index threshold, percent
   uint64_t trace_cap;
   Decision *slots;           // the stream's decision ring
-  uint64_t *time_trace;      // [trace_cap][2] device wall-clock ticks per traced chunk: when its
-                             // first workgroup began counting it (atomic min), and when its
-                             // finalizer was done (decision published; W > 1: histogram in the ring)
+  uint64_t *time_trace;      // [trace_cap][3] per traced chunk: device wall-clock ticks when its
+                             // first workgroup began counting it (atomic min) and when its
+                             // finalizer was done (decision ready; W > 1: histogram in the ring),
+                             // and the cycle counter's rate (ticks per us) inside that finalizer
   // bounded waits: polls of a decision tag, and re-reads of a segment's partial copies,
   // before they give up (counted in the diagnostics and the stream's state)
   uint32_t wait_polls;

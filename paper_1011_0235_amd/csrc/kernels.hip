@@ -654,7 +654,7 @@ __device__ __forceinline__ uint32_t begin_segment(uint32_t *lds, const Params &P
           kd = (mode == HIST_MODE_WAVEAGG) ? KIND_WAVE_AGG : KIND_WAVE;
         }
         if (traced)   // the earliest start of this chunk's counting, over its workgroups
-          __hip_atomic_fetch_min(gmem(&P.time_trace[2u * (uint64_t)k]), (uint64_t)wall_clock64(), __ATOMIC_RELAXED,
+          __hip_atomic_fetch_min(gmem(&P.time_trace[3u * (uint64_t)k]), (uint64_t)wall_clock64(), __ATOMIC_RELAXED,
                                  __HIP_MEMORY_SCOPE_AGENT);
         c.tag = tag;
         c.kind = kd;
@@ -1028,6 +1028,12 @@ __device__ __forceinline__ void sequence_stream(const Params &P, Ctl &c, StreamD
   }
 }
 
+// Rate of the shader's cycle counter in ticks per microsecond between two readings of it
+// (s0, s1) and of the constant 100 MHz clock (w0, w1) taken in one workgroup.
+__device__ __forceinline__ uint64_t clock_mhz(uint64_t s0, uint64_t w0, uint64_t s1, uint64_t w1) {
+  return w1 > w0 ? (s1 - s0) * 100u / (w1 - w0) : 0u;
+}
+
 // Stream epilogue for chunk k of `bytes` bytes with histogram h (thread t holds bin t):
 // Accumulator, the trace of what chunk k ran with, then the moving window, degeneracy switch
 // and rule P (Sec. III.B, Sec. III.C).  With a window of one chunk (W = 1) the decision after
@@ -1038,8 +1044,12 @@ __device__ __forceinline__ void stream_epilogue(const Params &P, Ctl &c, uint32_
                                                 uint64_t bytes) {
   const uint32_t t = threadIdx.x;
   StreamDev *st = P.st + sidx;
+  const bool traced = (uint64_t)k < P.trace_cap;
+  // the shader's cycle counter and the constant-rate clock, read twice within this
+  // workgroup: their ratio follows the engine clock while the epilogue ran (traced chunks)
+  const uint64_t sclk0 = traced ? (uint64_t)clock64() : 0, wall0 = traced ? (uint64_t)wall_clock64() : 0;
   __hip_atomic_fetch_add(gmem(&st->acc[t]), (uint64_t)h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if ((uint64_t)k < P.trace_cap) {
+  if (traced) {
     st_agent(&st->pat_trace[(size_t)k * 256u + t], c.words[t]);
     if (t == 0) *gmem(&st->mode_trace[k]) = (uint8_t)c.used_mode;
   }
@@ -1072,7 +1082,10 @@ __device__ __forceinline__ void stream_epilogue(const Params &P, Ctl &c, uint32_
     publish_decision(P, d, (uint64_t)k, mode, kind_lg, word);
     if (t == 0) {
       __hip_atomic_fetch_add(&st->done, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if ((uint64_t)k < P.trace_cap) st_agent(&P.time_trace[2u * (uint64_t)k + 1u], ready);
+      if (traced) {
+        st_agent(&P.time_trace[3u * (uint64_t)k + 1u], ready);
+        st_agent(&P.time_trace[3u * (uint64_t)k + 2u], clock_mhz(sclk0, wall0, (uint64_t)clock64(), ready));
+      }
     }
     return;
   }
@@ -1080,7 +1093,11 @@ __device__ __forceinline__ void stream_epilogue(const Params &P, Ctl &c, uint32_
   st_agent(&st->ring[(size_t)slot * 256u + t], ((uint64_t)(uint32_t)(k + 1) << 32) | h);
   if (t == 0) {
     st_agent(&st->ring_n[slot], ((uint64_t)((uint32_t)(k + 1) & kSizeGenMask) << kSizeBits) | bytes);
-    if ((uint64_t)k < P.trace_cap) st_agent(&P.time_trace[2u * (uint64_t)k + 1u], (uint64_t)wall_clock64());
+    if (traced) {
+      const uint64_t w = wall_clock64();
+      st_agent(&P.time_trace[3u * (uint64_t)k + 1u], w);
+      st_agent(&P.time_trace[3u * (uint64_t)k + 2u], clock_mhz(sclk0, wall0, (uint64_t)clock64(), w));
+    }
   }
   order_global();     // every entry is in before the CAS below (so a failing CAS means the
   __syncthreads();    // sequencer's last look will find them)

@@ -162,7 +162,7 @@ struct StreamAlloc {
   Decision *d_slots = nullptr;
   uint8_t *d_mode_trace = nullptr;    // [count][trace_cap] modes, then [count][trace_cap] alarms
   uint32_t *d_pat_trace = nullptr;
-  uint64_t *d_time_trace = nullptr;   // [count][trace_cap][2], all ones until written
+  uint64_t *d_time_trace = nullptr;   // [count][trace_cap][3], all ones until written
 };
 hist_status_t stream_state_alloc(uint32_t count, uint32_t W, uint32_t theta, uint32_t S, uint32_t rmax, uint32_t lag,
                                  uint32_t nslot, uint32_t trace_cap, uint32_t alarm_pct, StreamAlloc *sa);

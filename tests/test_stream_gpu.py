@@ -673,8 +673,8 @@ def test_decision_waits_that_give_up(hm, W, alarm):
 
 @pytest.mark.parametrize("W,theta,lag", [(1, 45, 0), (1, 45, 1), (1, 0, 0), (4, 45, 0)])
 def test_time_trace(hm, W, theta, lag):
-    """The per-chunk device timeline: every traced chunk that ran has a start and an end, the
-    end after the start; with decisions that depend on the data at lag 0 a chunk begins
+    """The per-chunk device timeline: every traced chunk that ran has a start, a later end and
+    a plausible cycle-counter rate; with decisions that depend on the data at lag 0 a chunk begins
     counting only once the chunk before it has its decision (up to the clock's sampling
     skew); untraced chunks read 0.  The traces and histograms stay exact."""
     chunks = single_stream_chunks(256 << 10, 20)
@@ -692,10 +692,11 @@ def test_time_trace(hm, W, theta, lag):
     ref = O.stream_reference(chunks, W=W, theta_pct=theta, S=960, rmax=8, lag=lag)
     assert np.array_equal(outs.cpu().numpy().astype(np.int64), ref["hists"].astype(np.int64))
     assert [int(m) for m in modes] == ref["modes"][:cap]
-    assert tt.shape == (len(chunks) + 2, 2)
+    assert tt.shape == (len(chunks) + 2, 3)
     assert (tt[:cap] > 0).all()
     assert (tt[cap:] == 0).all()
     assert (tt[:cap, 1] >= tt[:cap, 0]).all()
+    assert ((tt[:cap, 2] >= 50) & (tt[:cap, 2] <= 10000)).all(), tt[:cap, 2]   # cycle counter, ticks/us
     if W == 1 and theta and lag == 0:
         skew = 2000   # ns
         for k in range(1, cap):
