@@ -84,6 +84,107 @@ static bool multi_case(const std::vector<uint64_t> &sizes, uint32_t maxg, uint64
          mp.grid <= std::max<uint32_t>(1, maxg);
 }
 
+// ---- forward progress of launches whose chunks wait for decisions (a model on the real plan)
+//
+// The kernel's rules, as the model takes them: a launch's tiles are handed out in order by
+// one counter to whichever of its workgroups asks; a workgroup holds one tile at a time,
+// waits (spinning, keeping its slot) until the decision its chunk runs with exists, counts,
+// and asks again until the counter runs out, then leaves.  Chunk s of the stream runs with
+// the decision made after chunk s - 1 - lag; that decision exists once every tile of that
+// chunk is counted (W = 1; with a window, once every chunk up to it is -- `window` below).
+// Two launches of the stream may be in flight and compete for the device's workgroup slots
+// in any order; each launch's grid is the planner's.  `slots` is what the device holds.
+struct Sim {
+  std::vector<uint32_t> tile_seg;     // per launch-global tile: its chunk (stream index)
+  std::vector<uint32_t> launch_of;    // per tile: 0 or 1
+};
+
+// Returns true if both launches finish; false if every resident workgroup waits on a
+// decision that needs a tile no running workgroup can reach (a deadlock).  With
+// `later_first` the dispatcher places every workgroup of the later launch before any of the
+// earlier one's (as when the earlier launch's queue is still held by its own wait for the
+// launch before it); otherwise it mixes them at random.
+static bool simulate(const std::vector<uint64_t> &chunk_bytes, uint64_t tile, uint32_t grid_cap, uint32_t slots,
+                     uint32_t lag, bool window, bool later_first, std::mt19937_64 &g) {
+  const uint32_t m = (uint32_t)chunk_bytes.size();
+  struct L {
+    MultiPlan mp;
+    std::vector<SegDesc> segs;
+    uint32_t next = 0, started = 0, left = 0;
+  } ln[2];
+  for (int l = 0; l < 2; ++l) {
+    ln[l].segs = segments(chunk_bytes);
+    if (plan_multi(ln[l].segs, tile, grid_cap, &ln[l].mp) != HIST_OK) return false;
+    ln[l].left = ln[l].mp.grid;
+  }
+  const uint32_t nchunk = 2 * m;
+  std::vector<uint32_t> tiles_left(nchunk);
+  for (int l = 0; l < 2; ++l)
+    for (uint32_t j = 0; j < m; ++j) tiles_left[l * m + j] = ln[l].segs[j].ntiles;
+  auto chunk_done = [&](int64_t s) { return s < 0 || tiles_left[(size_t)s] == 0; };
+  auto decided = [&](int64_t s) {   // the decision made after chunk s exists
+    if (s < 0) return true;
+    if (!window) return chunk_done(s);
+    for (int64_t q = 0; q <= s; ++q)
+      if (!chunk_done(q)) return false;
+    return true;
+  };
+  struct WG {
+    int l;
+    uint32_t tile;   // held tile, or ~0u before the first request
+    int work;        // remaining work units of the held tile once it runs
+  };
+  std::vector<WG> res;   // resident workgroups
+  uint32_t done_tiles = 0, total = ln[0].mp.ntiles + ln[1].mp.ntiles;
+  std::vector<std::vector<uint32_t>> seg_of(2);
+  for (int l = 0; l < 2; ++l) {
+    const TileRec *r = reinterpret_cast<const TileRec *>(ln[l].mp.blob.data() + ln[l].mp.seg_bytes);
+    for (uint32_t i = 0; i < ln[l].mp.ntiles; ++i) seg_of[l].push_back(r[i].seg);
+  }
+  for (long steps = 0; steps < 100000000L; ++steps) {
+    if (done_tiles == total && res.empty() && ln[0].started == ln[0].mp.grid && ln[1].started == ln[1].mp.grid)
+      return true;
+    // the dispatcher places a pending workgroup of either launch in any order
+    while (res.size() < slots && (ln[0].started < ln[0].mp.grid || ln[1].started < ln[1].mp.grid)) {
+      int l = later_first ? 1 : (int)(g() & 1);
+      if (ln[l].started == ln[l].mp.grid) l ^= 1;
+      ++ln[l].started;
+      res.push_back(WG{l, ~0u, 0});
+    }
+    // some resident workgroup that can move makes its next move (tried in a random order)
+    bool moved = false;
+    std::vector<size_t> order(res.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::shuffle(order.begin(), order.end(), g);
+    for (size_t i : order) {
+      WG &w = res[i];
+      L &x = ln[w.l];
+      if (w.tile == ~0u) {   // ask for a tile
+        if (x.next >= x.mp.ntiles) {
+          res.erase(res.begin() + (long)i);   // out of tiles: leaves, freeing its slot
+          moved = true;
+          break;
+        }
+        w.tile = x.next++;
+        w.work = 1 + (int)(g() % 5);
+        moved = true;
+        break;
+      }
+      const int64_t s = (int64_t)w.l * m + seg_of[w.l][w.tile];
+      if (!decided(s - 1 - (int64_t)lag)) continue;   // still waiting for its decision
+      if (--w.work == 0) {
+        --tiles_left[(size_t)s];
+        ++done_tiles;
+        w.tile = ~0u;
+      }
+      moved = true;
+      break;
+    }
+    if (!moved) return false;   // every resident workgroup waits: deadlock
+  }
+  return false;
+}
+
 int main() {
   int bad = 0;
   // the single-stream workload: 66 chunks of 4 MiB over 512 workgroups
@@ -109,6 +210,28 @@ int main() {
       std::printf("invalid plan at case %d\n", it);
       bad = 1;
     }
+  }
+  // forward progress: with each launch's grid at most half of the device's slots (the rule
+  // for launches that may wait), two launches of a stream always finish, whatever order the
+  // dispatcher places their workgroups in and however fast each one counts; with grids that
+  // fill the device, the later launch's waiting workgroups can hold every slot
+  {
+    std::mt19937_64 gs(20261203);
+    int ok_half = 0, stalls_full = 0;
+    const std::vector<uint64_t> chunks(24, 256u << 10);
+    for (int it = 0; it < 300 && !bad; ++it) {
+      const uint32_t slots = 16 + (uint32_t)(gs() % 48), lag = (uint32_t)(gs() % 4);
+      const bool window = (gs() & 1) != 0, later_first = (gs() & 1) != 0;
+      if (simulate(chunks, 16384, slots / 2, slots, lag, window, later_first, gs)) ++ok_half;
+      else {
+        std::printf("stall with half-capacity grids at case %d\n", it);
+        bad = 1;
+      }
+      if (!simulate(chunks, 16384, slots, slots, lag, window, later_first, gs)) ++stalls_full;
+    }
+    std::printf("progress model: %d of 300 runs finished at half capacity; %d of 300 stalled at full\n", ok_half,
+                stalls_full);
+    if (stalls_full == 0) bad = 1;   // the model must be able to show the hazard the rule avoids
   }
   std::printf(bad ? "FAILED\n" : "all plans valid\n");
   return bad;

@@ -1,6 +1,10 @@
 """The host's tile planners, checked without a GPU: tests/plan_check.cpp is compiled against
 the library's own planner source and run over the single-stream workload, equal frames,
-empty and tiny segments, and 3000 random chunk mixes (sizes, grid limits, tile limits)."""
+empty and tiny segments, and 3000 random chunk mixes (sizes, grid limits, tile limits).  It
+also runs a model of two launches of a stream whose chunks wait for decisions, on the
+planner's own tiles: with each grid at most half the device's workgroup slots they always
+finish, whatever order the dispatcher places workgroups in; with full grids the model
+shows the deadlock that rule avoids."""
 
 import os
 import shutil
@@ -26,3 +30,4 @@ def test_planners_cover_and_balance(tmp_path):
     assert "all plans valid" in out.stdout
     head = float(out.stdout.split("headline balance")[1].split()[0])
     assert 1.0 <= head <= 1.03
+    assert "300 of 300 runs finished at half capacity" in out.stdout
