@@ -294,8 +294,8 @@ hist_status_t run_single(DevCtx *d, Params &P, hipStream_t s, Scratch *own, hipE
   const uint32_t fam = P.st ? (uint32_t)KIND_UNIFORM : P.kind;
   const uint32_t lds = lds_bytes(P);
   const uint32_t G = (uint32_t)d->cus * blocks_per_cu(fam, lds);
-  // the buffer is shared out in 16 KiB steps to whichever workgroup asks next: one
-  // workgroup per step at most, else the whole grid
+  // one workgroup per 16 KiB of the buffer, at most the whole grid (every workgroup strides
+  // over the buffer; the last one finalizes)
   const uint32_t ntiles = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(G, ceil_div(n, 16384)));
   const uint32_t copies = std::min<uint32_t>(g_single_copies, pow2ceil32(ntiles));
   Scratch *sc = own;

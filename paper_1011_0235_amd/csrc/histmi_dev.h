@@ -117,34 +117,52 @@ struct WgStart {
 constexpr uint32_t kStartWords = sizeof(WgStart) / 4;
 static_assert(sizeof(WgStart) % 4 == 0 && kStartWords <= 64, "one word per lane of the first wavefront");
 
+// Kernel arguments.  Every field a launch reads is in the first five 64-byte lines (the
+// kernel touches all five at entry, so that their scalar-cache misses overlap instead of
+// following one another); the 1 KiB of host pattern words, read only by lookup-table
+// launches, comes last.
 struct Params {
-  const SegDesc *segs;       // device array of nseg descriptors (unused when single)
-  SegDesc seg0;              // the descriptor when single
-  const TileRec *recs;       // [ntiles] tiles in launch order (unused when single)
-  const uint32_t *bounds;    // [grid + 1] static launches: workgroup g takes tiles [bounds[g], bounds[g+1])
-  const WgStart *starts;     // [grid] static launches: each workgroup's start record
-  uint32_t nseg;
-  uint32_t ntiles;
+  // line 0: the launch's shape and LDS layout (32-bit fields)
   uint32_t single;           // 1: one buffer described by seg0, spread over the whole grid
   uint32_t dynamic;          // 1: tiles handed out in order by an atomic counter; 0: static
+  uint32_t nseg;
+  uint32_t ntiles;
   uint32_t clog2;            // log2 of the partial copies per segment
-  uint32_t *ctr;             // [0] next tile, [1] workgroups finished (both reset by the last one)
-  uint32_t *seg_done;        // [nseg] tiles finished per segment (reset by the finalizer)
-  uint32_t *partial;         // [nseg][copies][256] partial counts (reset by the finalizer)
-  uint32_t *diag;            // device diagnostics counters
+  uint32_t table_words;      // LDS layout (in 32-bit words): counting table at word 0
+  uint32_t look_off;         // lane-replicated lookup table (byte addresses into the counting table)
+  uint32_t look_words;
   // non-stream segments: one kind for every segment
   uint32_t kind;             // Kind
   uint32_t uni_lg;           // KIND_UNIFORM: log2 r
   uint32_t pat_S;            // KIND_LOOKUP: pattern size; stream launches: counting-table capacity
   uint32_t look_rr_lg;       // log2 of the lookup replication (5 or 6)
-  uint32_t pat_words[256];
-  // stream chunks and server requests
-  StreamDev *st;             // array of stream states
+  uint32_t forced;           // stream chunks: 0 = decided per chunk, else HIST_MODE_AHIST / HIST_MODE_WAVEHIST
+  uint32_t ordered;          // 1 for an ordered stream launch (one stream, segment j is chunk chunk_base + j)
+  // bounded waits: polls of a decision tag, and re-reads of a segment's partial copies,
+  // before they give up (counted in the diagnostics and the stream's state)
+  uint32_t wait_polls;
+  uint32_t merge_polls;
+  // line 1
+  SegDesc seg0;              // the descriptor when single
+  // lines 1-3: device arrays
+  const SegDesc *segs;       // device array of nseg descriptors (unused when single)
+  const TileRec *recs;       // [ntiles] tiles in launch order (unused when single)
+  const uint32_t *bounds;    // [grid + 1] static launches: workgroup g takes tiles [bounds[g], bounds[g+1])
+  const WgStart *starts;     // [grid] static launches: each workgroup's start record
+  uint32_t *ctr;             // [0] next tile, [1] workgroups finished (both reset by the last one)
+  uint32_t *seg_done;        // [nseg] tiles finished per segment (reset by the finalizer)
+  uint32_t *partial;         // [nseg][copies][256] partial counts (reset by the finalizer)
+  uint32_t *diag;            // device diagnostics counters
+  StreamDev *st;             // stream chunks and server requests: array of stream states
+  Decision *slots;           // ordered launches: the stream's decision ring
+  uint64_t *time_trace;      // [trace_cap][3] per traced chunk: device wall-clock ticks when its
+                             // first workgroup began counting it (atomic min) and when its
+                             // finalizer was done (decision ready; W > 1: histogram in the ring),
+                             // and the cycle counter's rate (ticks per us) inside that finalizer
   uint64_t chunk_base;       // absolute index of relative chunk 0
-  uint32_t forced;           // 0 = decided per chunk, else HIST_MODE_AHIST / HIST_MODE_WAVEHIST
-  // ordered stream launches (one stream, segment j is chunk chunk_base + j): copies of the
-  // stream's constants, so that starting a chunk reads nothing but its decision's tag
-  uint32_t ordered;          // 1 for an ordered stream launch
+  uint64_t trace_cap;
+  // line 4: copies of an ordered stream's constants, so that starting a chunk reads nothing
+  // but its decision's tag
   uint32_t lag;
   uint32_t nslot;
   uint32_t W;                // moving-window length in chunks
@@ -155,21 +173,11 @@ struct Params {
   uint32_t alarm_pct;        // change detection threshold (0 = off); sequenced when W > 1 or on
   uint32_t criterion;        // HIST_CRIT_*
   uint32_t kappa;            // collision-index threshold, percent
-  uint64_t trace_cap;
-  Decision *slots;           // the stream's decision ring
-  uint64_t *time_trace;      // [trace_cap][3] per traced chunk: device wall-clock ticks when its
-                             // first workgroup began counting it (atomic min) and when its
-                             // finalizer was done (decision ready; W > 1: histogram in the ring),
-                             // and the cycle counter's rate (ticks per us) inside that finalizer
-  // bounded waits: polls of a decision tag, and re-reads of a segment's partial copies,
-  // before they give up (counted in the diagnostics and the stream's state)
-  uint32_t wait_polls;
-  uint32_t merge_polls;
-  // LDS layout (in 32-bit words)
-  uint32_t table_words;      // counting table at word 0
-  uint32_t look_off;         // lane-replicated lookup table (byte addresses into the counting table)
-  uint32_t look_words;
+  // read only by launches with a host pattern (KIND_LOOKUP)
+  uint32_t pat_words[256];
 };
+constexpr uint32_t kHotParamLines = 5;
+
 
 // Launch configuration chosen by the host.
 struct LaunchShape {

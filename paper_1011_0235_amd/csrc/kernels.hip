@@ -284,6 +284,13 @@ __device__ __forceinline__ void zero_words(uint32_t *lds, uint32_t words) {
   for (uint32_t i = threadIdx.x; i < (words >> 2); i += kBlock) p[i] = z;
 }
 
+// Clear the counting table once per workgroup; from then on table_bin leaves it zero.  Ends
+// with a barrier.
+__device__ __forceinline__ void zero_table(uint32_t *lds, const Params &P) {
+  zero_words(lds, P.table_words);
+  __syncthreads();
+}
+
 // Check c.words as a pattern of S sub-bins and at most rmax per value; choose the kind.
 // Returns KIND_UNIFORM (c.lg set) or KIND_LOOKUP for a valid pattern, KIND_WAVE otherwise.
 __device__ uint32_t classify_pattern(Ctl &c, uint32_t S, uint32_t rmax, uint32_t S_cap, uint32_t rmax_cap,
@@ -462,21 +469,19 @@ __device__ __forceinline__ void run_primed(const Adder<KIND> &ad, const Range &r
 
 // One buffer spread over the whole grid: workgroup g takes the 4 KiB blocks g, g + G,
 // g + 2G, ... of the aligned middle, U blocks per step (next step prefetched); workgroup 0
-// also takes the unaligned head and tail.
+// also takes the unaligned head and tail.  The counting table is cleared (zero_table, which
+// ends with a barrier) while the first step's loads are in flight.
 template <int KIND, int U>
-__device__ void run_strided(uint32_t *lds, const Adder<KIND> &ad, const uint8_t *p, uint64_t len) {
+__device__ void run_strided(uint32_t *lds, const Params &P, const Adder<KIND> &ad, const uint8_t *p, uint64_t len) {
   const uint32_t t = threadIdx.x, g = blockIdx.x, G = gridDim.x;
   const uintptr_t a0 = reinterpret_cast<uintptr_t>(p), a1 = a0 + len;
   const uintptr_t b0 = (a0 + 15u) & ~static_cast<uintptr_t>(15u), b1 = a1 & ~static_cast<uintptr_t>(15u);
   gu8 *pg = (gu8 *)p;
   if (b0 >= b1) {
+    zero_table(lds, P);
     if (g == 0)
       for (uint64_t i = t; i < len; i += kBlock) ad.add(pg[i]);
     return;
-  }
-  if (g == 0) {
-    if (t < b0 - a0) ad.add(pg[t]);
-    if (t < a1 - b1) ad.add(((gu8 *)b1)[t]);
   }
   gu32x4 *v = (gu32x4 *)b0;
   const uint64_t nv = (b1 - b0) >> 4;
@@ -485,9 +490,15 @@ __device__ void run_strided(uint32_t *lds, const Adder<KIND> &ad, const uint8_t 
   // vector (lane 255 of block U-1) is inside
   uint64_t base = (uint64_t)g * kBlock;
   const uint64_t span = (uint64_t)(U - 1) * stride + (kBlock - 1);
-  if (base + span < nv) {
-    Pipe<U> a, b;
-    a.load(v, base + t, stride);
+  const bool full = base + span < nv;   // uniform over the workgroup
+  Pipe<U> a, b;
+  if (full) a.load(v, base + t, stride);
+  zero_table(lds, P);
+  if (g == 0) {
+    if (t < b0 - a0) ad.add(pg[t]);
+    if (t < a1 - b1) ad.add(((gu8 *)b1)[t]);
+  }
+  if (full) {
     for (;;) {
       const uint64_t nb = base + (uint64_t)U * stride;
       const bool more = nb + span < nv;
@@ -1113,7 +1124,7 @@ __device__ __forceinline__ void stream_epilogue(const Params &P, Ctl &c, uint32_
 // agent-scope atomics, into one of the segment's partial copies; thread 0 then takes a
 // ticket (tiles done so far).  The caller reads the ticket when it next needs thread 0's
 // results anyway; the workgroup that completed the segment's last tile runs
-// finalize_segment.
+// finalize_segment.  A single-buffer launch takes no tickets: its last workgroup finalizes.
 //
 // finalize_segment does not rely on the other workgroups' atomics having landed before their
 // tickets: it re-reads the copies until the 256 totals add up to the segment's byte count.
@@ -1143,6 +1154,7 @@ __device__ __forceinline__ uint32_t flush_issue(uint32_t *lds, const Params &P, 
   return before;
 }
 
+template <uint32_t NF = 8>
 __device__ __forceinline__ void finalize_segment(const Params &P, Ctl &c, uint32_t s, const SegDesc &sd) {
   const uint32_t t = threadIdx.x;
   {
@@ -1153,9 +1165,19 @@ __device__ __forceinline__ void finalize_segment(const Params &P, Ctl &c, uint32
     uint32_t *part = P.partial + ((size_t)s << (P.clog2 + 8));
     uint32_t tot = 0;
     for (uint32_t tries = 0;; ++tries) {
-      // read the copies eight at a time (all eight agent-scope loads in flight)
+      // read the copies NF at a time (all NF agent-scope loads in flight; the single-buffer
+      // finalizer, which has no next tile's loads in registers, takes all 16 of its copies
+      // in one memory round trip)
       tot = 0;
-      if (copies >= 8) {
+      if (copies >= NF) {
+        for (uint32_t q = 0; q < copies; q += NF) {
+          uint32_t x[NF];
+#pragma unroll
+          for (uint32_t u = 0; u < NF; ++u) x[u] = ld_agent(&part[((q + u) << 8) | t]);
+#pragma unroll
+          for (uint32_t u = 0; u < NF; ++u) tot += x[u];
+        }
+      } else if (copies >= 8) {
         for (uint32_t q = 0; q < copies; q += 8) {
           uint32_t x[8];
 #pragma unroll
@@ -1226,29 +1248,17 @@ __device__ __forceinline__ void single_path(uint32_t *lds, const Params &P, Ctl 
   const SegDesc sd = P.seg0;
   const uint32_t kind = begin_segment(lds, P, c, sd, tag_prefetch(P, 0));
   const uint32_t lg = c.lg;
-  if (kind == KIND_WAVE) run_strided<KIND_WAVE, U>(lds, make_adder<KIND_WAVE>(lds, P, c), sd.ptr, sd.size);
-  else if (kind == KIND_WAVE_AGG) run_strided<KIND_WAVE_AGG, U>(lds, make_adder<KIND_WAVE_AGG>(lds, P, c), sd.ptr, sd.size);
-  else if (kind == KIND_UNIFORM) run_strided<KIND_UNIFORM, U>(lds, make_adder<KIND_UNIFORM>(lds, P, c), sd.ptr, sd.size);
-  else run_strided<KIND_LOOKUP, U>(lds, make_adder<KIND_LOOKUP>(lds, P, c), sd.ptr, sd.size);
-  // The ticket that elects the finalizer goes through one counter per group of workgroups
-  // (blockIdx mod 8, which is also the XCD a workgroup runs on): atomics on one address are
-  // performed one after another, about 10 ns each, and the whole grid finishing together
-  // would queue several microseconds on a single counter.  The last workgroup of each group
-  // then takes a ticket of the segment's counter, and the last of those finalizes.
+  if (kind == KIND_WAVE) run_strided<KIND_WAVE, U>(lds, P, make_adder<KIND_WAVE>(lds, P, c), sd.ptr, sd.size);
+  else if (kind == KIND_WAVE_AGG) run_strided<KIND_WAVE_AGG, U>(lds, P, make_adder<KIND_WAVE_AGG>(lds, P, c), sd.ptr, sd.size);
+  else if (kind == KIND_UNIFORM) run_strided<KIND_UNIFORM, U>(lds, P, make_adder<KIND_UNIFORM>(lds, P, c), sd.ptr, sd.size);
+  else run_strided<KIND_LOOKUP, U>(lds, P, make_adder<KIND_LOOKUP>(lds, P, c), sd.ptr, sd.size);
+  // No ticket elects the finalizer: the grid's last workgroup (the last dispatched, so
+  // about the last to finish counting) finalizes once its own counts are flushed.  Its merge
+  // re-reads the copies until they hold all n bytes, so it needs nothing from the others
+  // but their atomics, and the others wait for nothing: the chain after the last count is
+  // its atomics landing plus one re-read, not two returning atomics and then the read.
   flush_issue(lds, P, c, 0, kind, lg, 0, false, false);
-  if (t == 0) {
-    const uint32_t G = gridDim.x, g = blockIdx.x & 7u, groups = G < 8u ? G : 8u;
-    const uint32_t in_group = (G - g + 7u) >> 3;
-    uint32_t last = 0;
-    if (__hip_atomic_fetch_add(&P.ctr[8 + g], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u == in_group)
-      last = __hip_atomic_fetch_add(&P.seg_done[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u == groups;
-    c.flag = last;
-  }
-  __syncthreads();
-  if (c.flag) {
-    if (t < 8) st_agent(&P.ctr[8 + t], 0u);   // every workgroup has taken its group ticket
-    finalize_segment(P, c, 0, sd);
-  }
+  if (blockIdx.x + 1u == gridDim.x) finalize_segment<16>(P, c, 0, sd);
 }
 
 // The segment descriptor is staged through LDS (c.sd[]) rather than held in registers: lanes
@@ -1276,16 +1286,23 @@ __device__ __forceinline__ void multi_path(uint32_t *lds, const Params &P, Ctl &
   const uint32_t t = threadIdx.x;
   uint32_t tile, tile_end = P.ntiles;
   uint32_t first_lo = 0, first_hi = 0, first_len = 0, first_seg = 0;   // static: the first tile
+  // the first tile's round trip (a counter ticket, or the start record) is in flight while
+  // the counting table is cleared
   if (P.dynamic) {
-    if (t == 0) c.next_tile = atomicAdd(&P.ctr[0], 1u);
+    uint32_t first = 0;
+    if (t == 0) first = atomicAdd(&P.ctr[0], 1u);
+    zero_table(lds, P);
+    if (t == 0) c.next_tile = first;
     __syncthreads();
     tile = c.next_tile;
     __syncthreads();
   } else {
     // one memory round trip brings the workgroup's tile range, its first tile and that
     // tile's segment descriptor (one word per lane of the first wavefront)
+    uint32_t w = 0;
+    if (t < kStartWords) w = reinterpret_cast<const uint32_t *>(P.starts + blockIdx.x)[t];
+    zero_table(lds, P);
     if (t < kStartWords) {
-      const uint32_t w = reinterpret_cast<const uint32_t *>(P.starts + blockIdx.x)[t];
       if (t < 6) c.start[t] = w;
       else reinterpret_cast<uint32_t *>(&c.sd[0])[t - 6] = w;
     }
@@ -1385,14 +1402,25 @@ __device__ __forceinline__ void multi_path(uint32_t *lds, const Params &P, Ctl &
   }
 }
 
+// Load one word of each hot line of the kernel arguments at entry: the five scalar-cache
+// misses then overlap, and every later read of an argument hits (otherwise each branch's
+// first argument read waits for its own miss, one after another).  The words are read
+// through the argument segment's base (Params is the kernel's only argument, at offset 0)
+// and only fed to an empty asm, so no argument value is kept live from here.
+__device__ __forceinline__ void touch_params() {
+  static_assert(offsetof(Params, pat_words) <= 64 * kHotParamLines, "the hot fields fill the first lines");
+  typedef const uint32_t __attribute__((address_space(4))) karg_word;
+  const karg_word *k = (const karg_word *)__builtin_amdgcn_kernarg_segment_ptr();
+  asm volatile("" ::"s"(k[0]), "s"(k[16]), "s"(k[32]), "s"(k[48]), "s"(k[64]));
+}
+
 template <int U>
 __global__ void __launch_bounds__(kBlock) hist_main(const Params P) {
   // one dynamic LDS block: the counting table at address 0 (so table addresses need no
   // base offset), the lookup table after it, the control block at the end
   extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+  touch_params();
   Ctl &c = *reinterpret_cast<Ctl *>(lds + P.table_words + P.look_words);
-  zero_words(lds, P.table_words);   // from here on table_bin leaves the table zero
-  __syncthreads();
   if (P.single) single_path<U>(lds, P, c);
   else multi_path<U>(lds, P, c);
 }
