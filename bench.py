@@ -761,9 +761,10 @@ def main():
             st = hm.Stream(W=w_, theta_pct=th, S=s_, rmax=r_, lag=l, trace_cap=0, alarm_pct=al, criterion=cr,
                            kappa_pct=kp)
             d0 = hm.diag()
-            tms = run_stream(st, 8, 3, n_hip=nh)
+            ksteps = 16
+            tms = run_stream(st, ksteps, 4, n_hip=nh)
             d1 = hm.diag()
-            row = {"GB/s": round(nbytes * 8 / (tms * 1e-3) / 1e9, 1), "ms_per_step": round(tms / 8, 4)}
+            row = {"GB/s": round(nbytes * ksteps / (tms * 1e-3) / 1e9, 1), "ms_per_step": round(tms / ksteps, 4)}
             # bounded waits that ran out (a decision or a merge): none is expected
             if d1.wait_timeouts != d0.wait_timeouts or d1.merge_timeouts != d0.merge_timeouts:
                 row["wait_timeouts"] = int(d1.wait_timeouts - d0.wait_timeouts)

@@ -173,6 +173,11 @@ struct Params {
   uint32_t alarm_pct;        // change detection threshold (0 = off); sequenced when W > 1 or on
   uint32_t criterion;        // HIST_CRIT_*
   uint32_t kappa;            // collision-index threshold, percent
+  // single-buffer launches: when set, the finalizer stores done_seq here (pinned host memory,
+  // system scope) once the histogram and every state update are visible to the host and to
+  // other engines, so the host sees completion without an event
+  uint32_t done_seq;
+  uint32_t *host_done;
   // read only by launches with a host pattern (KIND_LOOKUP)
   uint32_t pat_words[256];
 };

@@ -1258,7 +1258,16 @@ __device__ __forceinline__ void single_path(uint32_t *lds, const Params &P, Ctl 
   // but their atomics, and the others wait for nothing: the chain after the last count is
   // its atomics landing plus one re-read, not two returning atomics and then the read.
   flush_issue(lds, P, c, 0, kind, lg, 0, false, false);
-  if (blockIdx.x + 1u == gridDim.x) finalize_segment<16>(P, c, 0, sd);
+  if (blockIdx.x + 1u == gridDim.x) {
+    finalize_segment<16>(P, c, 0, sd);
+    if (P.host_done) {
+      // every thread's output and state writes reach memory that the host and the copy
+      // engines read, then one store tells the host (the kernel has nothing left to do)
+      __threadfence_system();
+      __syncthreads();
+      if (t == 0) __hip_atomic_store(P.host_done, P.done_seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+  }
 }
 
 // The segment descriptor is staged through LDS (c.sd[]) rather than held in registers: lanes

@@ -2,8 +2,9 @@
 //
 // Host side: a queue of submitted requests, a scheduler thread, and a pool of micro-batch
 // slots (two per HIP stream), each with its own device scratch so slots can run at once.
-// The scheduler repeatedly (1) retires finished micro-batches (hipEventQuery), freeing their
-// budget and slots, and (2) admits queued requests in arrival order while the budget and the
+// The scheduler repeatedly (1) retires finished micro-batches (a lone request's kernel sets a
+// word of pinned host memory when its histogram is out; a batch of several completes an
+// event, hipEventQuery), freeing their budget and slots, and (2) admits queued requests in arrival order while the budget and the
 // slot limit allow, launching each admitted group as one persistent multi-segment kernel.
 // Between rounds it spins (no timed sleep: a sleep of a few microseconds is rounded up to
 // the kernel's timer slack, tens of microseconds, which would set the latency floor) while
@@ -55,6 +56,14 @@ struct Req {
 struct Slot {
   Scratch sc;
   hipEvent_t ev = nullptr;
+  // a lone request's launch reports completion through a word of pinned host memory that
+  // its finalizer sets to `seq` (no event, no HIP call to notice it); batches of several
+  // requests complete `ev`
+  volatile uint32_t *done_host = nullptr;
+  uint32_t *done_dev = nullptr;
+  uint32_t seq = 0;
+  bool by_word = false;
+  uint64_t t_check = 0;       // last time a wait on the word asked the HIP stream for errors
   bool busy = false;
   int hs = 0;
   uint64_t bytes = 0;
@@ -64,6 +73,7 @@ struct Slot {
 constexpr size_t kQueueCap = 1u << 20;      // not-yet-admitted requests
 constexpr size_t kFinishedCap = 1u << 20;   // finished requests kept for poll / wait
 constexpr uint64_t kIdleSpinNs = 2000000;   // the scheduler spins this long after its last activity
+constexpr uint64_t kCheckNs = 100000;       // a launch not done yet: its HIP stream is asked for errors this often
 
 inline void cpu_relax() { __builtin_ia32_pause(); }
 
@@ -76,6 +86,7 @@ struct hist_server {
   StreamAlloc sa;
   std::vector<hipStream_t> hs;
   std::vector<Slot> slots;
+  uint32_t *done_words = nullptr;           // pinned host memory: one 64-byte line per slot
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<uint64_t> pending;
@@ -92,6 +103,7 @@ struct hist_server {
 
   void run();
   bool launch(Slot &sl, std::vector<uint64_t> &batch);
+  hipError_t query(Slot &sl);
   void finish(uint64_t tk, int32_t status, uint64_t t);
 };
 
@@ -135,8 +147,13 @@ bool hist_server::launch(Slot &sl, std::vector<uint64_t> &batch) {
     // a lone request spreads over the whole grid with no descriptors to upload (the
     // launch carries it), so nothing but the kernel is queued; sl.ev completes with it
     P.seg0 = segs[0];
-    return run_single(d, P, s, &sl.sc, sl.ev) == HIST_OK;
+    P.done_seq = ++sl.seq;
+    P.host_done = sl.done_dev;
+    sl.by_word = true;
+    sl.t_check = now_ns();
+    return run_single(d, P, s, &sl.sc) == HIST_OK;
   }
+  sl.by_word = false;
   const uint32_t fam = KIND_UNIFORM;
   const uint64_t tile = (uint64_t)g_tune[fam].tile_kib * 1024;
   const uint32_t maxg = (uint32_t)d->cus * blocks_per_cu(fam, lds_bytes(P));
@@ -147,6 +164,23 @@ bool hist_server::launch(Slot &sl, std::vector<uint64_t> &batch) {
   return run_multi(d, P, mp, copies, s, &sl.sc, false, true, sl.ev) == HIST_OK;
 }
 
+// State of the slot's launch: hipSuccess once done, hipErrorNotReady while it runs, or the
+// HIP error that ended it.  A launch that reports through the host word is done when the
+// word holds its sequence number; while it is not, the HIP stream is asked now and then, so
+// a launch that failed on the device is noticed too (its stream reports the error; a stream
+// with nothing left to run and the word still short would be a lost report).
+hipError_t hist_server::query(Slot &sl) {
+  if (!sl.by_word) return hipEventQuery(sl.ev);
+  if (*sl.done_host == sl.seq) return hipSuccess;
+  const uint64_t t = now_ns();
+  if (t - sl.t_check < kCheckNs) return hipErrorNotReady;
+  sl.t_check = t;
+  const hipError_t e = hipStreamQuery(hs[sl.hs]);
+  if (e == hipErrorNotReady) return e;
+  if (*sl.done_host == sl.seq) return hipSuccess;   // the launch ended after writing the word
+  return e == hipSuccess ? hipErrorUnknown : e;
+}
+
 void hist_server::run() {
   (void)hipSetDevice(dev);
   std::unique_lock<std::mutex> lk(mu);
@@ -155,7 +189,7 @@ void hist_server::run() {
     // 1. retire finished micro-batches
     for (Slot &sl : slots) {
       if (!sl.busy) continue;
-      const hipError_t e = hipEventQuery(sl.ev);
+      const hipError_t e = query(sl);
       if (e == hipErrorNotReady) continue;
       const uint64_t t = now_ns();
       for (uint64_t tk : sl.tickets) finish(tk, e == hipSuccess ? HIST_OK : HIST_EDEVICE, t);
@@ -221,7 +255,7 @@ void hist_server::run() {
     for (uint32_t spins = 0;; ++spins) {
       bool done = false;
       for (Slot &sl : slots)
-        if (sl.busy && hipEventQuery(sl.ev) != hipErrorNotReady) {
+        if (sl.busy && query(sl) != hipErrorNotReady) {
           done = true;
           break;
         }
@@ -265,8 +299,22 @@ hist_status_t hist_server_create(hist_server_t **out, const hist_server_config_t
     }
   }
   sv->slots.resize((size_t)c.n_hip_streams * 2);
+  if (hipHostMalloc(reinterpret_cast<void **>(&sv->done_words), sv->slots.size() * 64, hipHostMallocCoherent) !=
+      hipSuccess) {
+    sv->done_words = nullptr;
+    hist_server_destroy(sv);
+    return HIST_ENOMEM;
+  }
+  std::memset(sv->done_words, 0, sv->slots.size() * 64);
   for (size_t i = 0; i < sv->slots.size(); ++i) {
     sv->slots[i].hs = (int)(i % c.n_hip_streams);
+    sv->slots[i].done_host = sv->done_words + i * 16;
+    void *dp = nullptr;
+    if (hipHostGetDevicePointer(&dp, sv->done_words + i * 16, 0) != hipSuccess) {
+      hist_server_destroy(sv);
+      return HIST_EDEVICE;
+    }
+    sv->slots[i].done_dev = static_cast<uint32_t *>(dp);
     if (hipEventCreateWithFlags(&sv->slots[i].ev, hipEventDisableTiming) != hipSuccess) {
       hist_server_destroy(sv);
       return HIST_EDEVICE;
@@ -388,12 +436,17 @@ hist_status_t hist_server_destroy(hist_server_t *sv) {
   sv->cv_work.notify_all();
   sv->cv_done.notify_all();
   if (sv->th.joinable()) sv->th.join();   // the thread exits once every admitted batch retired
+  // a launch that reported through its host word may still be ending: let every HIP stream
+  // drain before its scratch and the words are freed
+  for (hipStream_t h : sv->hs)
+    if (h) (void)hipStreamSynchronize(h);
   for (Slot &sl : sv->slots) {
     free_scratch(&sl.sc);
     if (sl.ev) (void)hipEventDestroy(sl.ev);
   }
   for (hipStream_t h : sv->hs)
     if (h) (void)hipStreamDestroy(h);
+  if (sv->done_words) (void)hipHostFree(sv->done_words);
   stream_state_free(&sv->sa);
   delete sv;
   return HIST_OK;
