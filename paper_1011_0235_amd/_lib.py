@@ -180,6 +180,13 @@ def load(path: Optional[str] = None, apply_tuning: bool = True):
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise RuntimeError("libhistmi.so is not built (%s); run python paper_1011_0235_amd/build.py" % p)
+    # PyTorch ships its own HIP runtime.  Imported first, it provides the runtime this library
+    # then binds to (same soname), so both share one; loaded the other way round, the
+    # process gets ROCm's runtime under PyTorch's name and device calls fail.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(p)
     for name, res, args in _SIGS:
         fn = getattr(lib, name)
