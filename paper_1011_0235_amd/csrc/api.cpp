@@ -445,20 +445,30 @@ struct hist_stream {
   uint64_t since_join = 0;
 };
 
-// When is the decision after a chunk a function of the chunk sizes alone?  With W = 1 and no
-// change detection (so chunks are not sequenced), a budget that gives every value rmax
-// sub-bins (rule P's first case: the pattern is the uniform table whatever the histogram),
-// and a switching test that fires for any non-empty window (theta or kappa 0): then the
-// decision after chunk j is (AHist if chunk j holds a byte, else the per-wavefront kernel;
-// the uniform table).  The host hands such decisions to the chunks that run with them, so
-// they start without waiting; the device still makes and publishes the same decisions.
-static bool decisions_known(const hist_stream_config_t &c) {
-  if (c.W != 1 || c.alarm_pct != 0 || 256ull * c.rmax > c.S) return false;
+// Whether every decision is a function of the chunk sizes alone: a budget that gives every
+// value rmax sub-bins (rule P's first case: the pattern is the uniform table whatever the
+// histogram) and a switching test that fires for any non-empty window (theta or kappa 0).
+// The decision after chunk j is then AHist if the window up to chunk j holds a byte, else
+// the per-wavefront kernel, with the uniform table either way.
+static bool decisions_uniform(const hist_stream_config_t &c) {
+  if (256ull * c.rmax > c.S) return false;
   switch (c.criterion) {
   case HIST_CRIT_MAXBIN: return c.theta_pct == 0;
   case HIST_CRIT_COLLISION: return c.kappa_pct == 0;
   default: return c.theta_pct == 0 || c.kappa_pct == 0;
   }
+}
+
+// The host hands each chunk its decision (the chunk then starts without waiting; the device
+// still makes and publishes the same decisions) when the decisions are uniform as above and
+// the chunks are not sequenced (W = 1, no change detection).  Sequenced streams could be told
+// their decisions too, but there the finalizers' in-order sequencing, not the decision waits,
+// sets the pace, and a static plan (which known decisions allow) leaves a workgroup that
+// sequences for a while with the rest of its share still to count: measured no faster
+// (W = 32, lag 31: 3.79 TB/s against 3.70 with device decisions) or slower (W = 32, lag 65:
+// 3.82 against 4.99).
+static bool decisions_known(const hist_stream_config_t &c) {
+  return c.W == 1 && c.alarm_pct == 0 && decisions_uniform(c);
 }
 
 // Make `s` wait for the launch in slot i, unless that launch went to `s` itself (then it is
@@ -733,7 +743,7 @@ hist_status_t hist_stream_create(hist_stream_t **out, const hist_stream_config_t
   // in flight span at most 2 * kMaxChunksPerLaunch chunks, plus the lag + 1 decisions made
   // before them
   st->nslot = c.lag + 2 + 2 * kMaxChunksPerLaunch;
-  st->recent.assign((size_t)c.lag + 1, 0);
+  st->recent.assign((size_t)c.lag + c.W, 0);   // sizes of the last lag + W chunks
   hist_status_t r =
       stream_state_alloc(1, c.W, c.theta_pct, c.S, c.rmax, c.lag, st->nslot, c.trace_cap, c.alarm_pct, &st->sa);
   for (int i = 0; i < 2 && r == HIST_OK; ++i)
@@ -827,8 +837,21 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
       tile = std::min<uint64_t>(tile, std::max<uint64_t>(16384, ceil_div(std::min(fill, several), 16384) * 16384));
     }
     std::vector<SegDesc> segs(m);
-    const uint32_t ring = st->cfg.lag + 1;
+    const uint32_t ring = st->cfg.lag + st->cfg.W;
     const uint32_t lgmax = log2u(st->cfg.rmax);
+    // known decisions: chunk k runs with the decision made after chunk src = k - 1 - lag,
+    // AHist with the uniform table iff one of chunks src - W + 1 .. src holds a byte;
+    // nz[q - lo] counts the non-empty chunks in [lo, q)
+    const int64_t k0 = (int64_t)st->pushed, W = (int64_t)st->cfg.W, lag = (int64_t)st->cfg.lag;
+    const int64_t lo = std::max<int64_t>(0, k0 - lag - W);
+    std::vector<uint32_t> nz;
+    if (known) {
+      nz.assign((size_t)(k0 + m - lo + 1), 0);
+      for (int64_t q = lo; q < k0 + (int64_t)m; ++q) {
+        const uint64_t n = q >= k0 ? h_sizes[first + (uint32_t)(q - k0)] : st->recent[(uint64_t)q % ring];
+        nz[(size_t)(q - lo + 1)] = nz[(size_t)(q - lo)] + (n > 0 ? 1u : 0u);
+      }
+    }
     for (uint32_t j = 0; j < m; ++j) {
       std::memset(&segs[j], 0, sizeof(SegDesc));
       segs[j].ptr = static_cast<const uint8_t *>(h_ptrs[first + j]);
@@ -837,14 +860,12 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
       segs[j].chunk = (int64_t)j;
       segs[j].stream_idx = 0;
       if (known) {
-        // chunk k runs with the decision made after chunk k - 1 - lag
-        const int64_t src = (int64_t)(st->pushed + j) - 1 - (int64_t)st->cfg.lag;
+        const int64_t src = k0 + (int64_t)j - 1 - lag;
         if (src < 0) {
           segs[j].known = kKnown | kKnownCold | ((uint32_t)HIST_MODE_WAVEHIST << 16) | ((uint32_t)KIND_UNIFORM << 8);
         } else {
-          const uint64_t n = (uint64_t)src >= st->pushed ? h_sizes[first + (uint32_t)((uint64_t)src - st->pushed)]
-                                                         : st->recent[(uint64_t)src % ring];
-          const uint32_t md = n > 0 ? HIST_MODE_AHIST : HIST_MODE_WAVEHIST;
+          const int64_t a = std::max<int64_t>(src - W + 1, lo);
+          const uint32_t md = nz[(size_t)(src - lo + 1)] > nz[(size_t)(a - lo)] ? HIST_MODE_AHIST : HIST_MODE_WAVEHIST;
           segs[j].known = kKnown | (md << 16) | ((uint32_t)KIND_UNIFORM << 8) | lgmax;
         }
       }
@@ -860,10 +881,23 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
     // its chunks wait only on launches that run on their own, never on each other, so equal
     // shares are safe too (with the residency cap of launches that wait, set above).
     const bool ahead = !known && m <= st->cfg.lag + 1;
-    if (known || ahead)
+    if (known || ahead) {
       TRY(plan_split(segs, (uint64_t)g_tune[fam].tile_kib * 1024, maxg, &mp));
-    else
-      TRY(plan_multi(segs, tile, maxg, &mp));
+    } else {
+      // Chunks 0 .. m - 2 - lag of this launch make the decisions of its later chunks.  Where
+      // those decisions depend on the data, their tiles are cut small (a 64th of a chunk), so
+      // that each of them is spread over many workgroups and done soon after its tiles are
+      // taken: with whole-grid-sized tiles the first chunks finish only when the grid's first
+      // tiles all do, while the tiles of the chunks waiting on them have long been taken and
+      // their workgroups spin.  Each small tile costs a flush, though; where every decision is
+      // the uniform table (a window stream with the tuned switch) the waits are short anyway
+      // and the extra flushes cost more than they save, so those keep the larger tiles.
+      const uint32_t producers = (m > st->cfg.lag + 1 && !decisions_uniform(st->cfg)) ? m - 1 - st->cfg.lag : 0u;
+      uint64_t per_chunk = 0;
+      for (uint32_t j = 0; j < m; ++j) per_chunk += h_sizes[first + j];
+      per_chunk = std::max<uint64_t>(1, per_chunk / m);
+      TRY(plan_multi(segs, tile, maxg, &mp, producers, std::max<uint64_t>(16384, per_chunk / 64)));
+    }
     const uint32_t copies = std::min<uint32_t>(64, pow2ceil32(std::max<uint32_t>(1, g_tune[fam].copies)));
     const bool join = known && st->since_join + m > kMaxChunksPerLaunch;
     TRY(stream_launch_begin(st, s, serialize || join));

@@ -516,7 +516,9 @@ __device__ void run_strided(uint32_t *lds, const Params &P, const Adder<KIND> &a
 // Sum this thread's bin (value t) out of the table, clearing each sub-bin as it is read.
 // Every sub-bin the adds can touch belongs to exactly one value, so after all threads have
 // done this the whole counting table is zero again and the next segment needs no clearing
-// pass (the table is cleared once when the workgroup starts).
+// pass (the table is cleared once when the workgroup starts).  A workgroup's last flush
+// (CLEAR false) leaves the table as it is.
+template <bool CLEAR = true>
 __device__ uint32_t table_bin(uint32_t *lds, const Ctl &c, uint32_t kind, uint32_t lg) {
   const uint32_t t = threadIdx.x;
   uint32_t h = 0;
@@ -524,7 +526,7 @@ __device__ uint32_t table_bin(uint32_t *lds, const Ctl &c, uint32_t kind, uint32
 #pragma unroll
     for (uint32_t w = 0; w < kWaves; ++w) {
       h += lds[(w << 8) | t];
-      lds[(w << 8) | t] = 0u;
+      if (CLEAR) lds[(w << 8) | t] = 0u;
     }
   } else if (kind == KIND_UNIFORM && lg >= 4) {
     // value t's r sub-bins are one row of r / 4 16-byte quads: read four quads at a time
@@ -543,7 +545,7 @@ __device__ uint32_t table_bin(uint32_t *lds, const Ctl &c, uint32_t kind, uint32
 #pragma unroll
       for (uint32_t u = 0; u < 4; ++u) {
         h += x[u][0] + x[u][1] + x[u][2] + x[u][3];
-        row[(k0 + u + rot) & (nq - 1u)] = z;
+        if (CLEAR) row[(k0 + u + rot) & (nq - 1u)] = z;
       }
     }
   } else if (kind == KIND_UNIFORM) {
@@ -551,7 +553,7 @@ __device__ uint32_t table_bin(uint32_t *lds, const Ctl &c, uint32_t kind, uint32
     for (uint32_t j = 0; j < r; ++j) {
       const uint32_t i = (t << lg) | ((j + t) & (r - 1u));
       h += lds[i];
-      lds[i] = 0u;
+      if (CLEAR) lds[i] = 0u;
     }
   } else {
     // any pattern: eight reads in flight at a time, then clear
@@ -565,7 +567,7 @@ __device__ uint32_t table_bin(uint32_t *lds, const Ctl &c, uint32_t kind, uint32
       for (uint32_t u = 0; u < 8; ++u) {
         if (j0 + u < r) {
           h += x[u];
-          lds[base + j0 + u] = 0u;
+          if (CLEAR) lds[base + j0 + u] = 0u;
         }
       }
     }
@@ -680,7 +682,7 @@ __device__ __forceinline__ uint32_t begin_segment(uint32_t *lds, const Params &P
       if (kind == KIND_LOOKUP || traced) {
         if (tag_gen(c.tag) == 0) {
           c.words[t] = t;
-        } else if (sd.known) {   // a known decision's pattern is the uniform table
+        } else if ((tag_kind_lg(c.tag) >> 8) == KIND_UNIFORM) {   // the words follow from the tag
           const uint32_t lg = tag_kind_lg(c.tag) & 0xFFu;
           c.words[t] = (t << lg) | (lg << 16);
         } else {
@@ -751,14 +753,15 @@ __device__ __forceinline__ uint32_t decide_pattern(const Params &P, Ctl &c, uint
 }
 
 // Publish the decision made after chunk j into slot d (all threads call).  The chunk that
-// runs with it (j + 1 + lag) reads the pattern words only for a lookup table or for its
-// trace; otherwise the tag alone carries the decision and is stored at once, with nothing to
-// wait for.  When the words are needed they are stored and acknowledged before the tag.
+// runs with it (j + 1 + lag) reads the pattern words only for a lookup table; a uniform
+// table's words follow from the tag (value v at v << lg), also for the chunk's trace, so the
+// tag alone carries the decision and is stored at once, with nothing to wait for.  When the
+// words are needed they are stored and acknowledged before the tag.
 __device__ __forceinline__ void publish_decision(const Params &P, Decision *d, uint64_t j, uint32_t mode,
                                                  uint32_t kind_lg, uint32_t word) {
   const uint32_t t = threadIdx.x;
   const uint64_t tag = make_tag(j + 1, mode, kind_lg);
-  const bool words_needed = (kind_lg >> 8) == KIND_LOOKUP || j + 1 + P.lag < P.trace_cap;
+  const bool words_needed = (kind_lg >> 8) == KIND_LOOKUP;
   if (!words_needed) {
     if (t == 0) st_agent(&d->tag, tag);
     return;
@@ -971,6 +974,28 @@ __device__ __forceinline__ void sequence_stream(const Params &P, Ctl &c, StreamD
       // chunks j .. j + cnt - 1 are there (all four wavefronts saw every entry)
       const uint32_t cnt = (uint32_t)__builtin_ctz((fl & 0xFFu) | (1u << B));
       uint32_t alarm = 0;
+      // A batch whose decisions are all the uniform table (the budget holds rmax sub-bins for
+      // every value), with no change detection and no collision criterion, differs from chunk to chunk only in the mode, which the hot flags carry: the window
+      // moves by cnt chunks and thread 0 stores cnt tags in a short loop.  The general path
+      // below decides chunk by chunk in unrolled code that runs from a cold instruction cache
+      // (about 0.25 us a chunk, as much as the batch's load round trip for six chunks).
+      if (!EXTRA && 256u * P.rmax <= P.S) {
+#pragma unroll
+        for (uint32_t b = 0; b < B; ++b)
+          if (b < cnt) mw += (uint64_t)(uint32_t)e[b] - (j + b >= W ? (uint64_t)(uint32_t)eo[b] : 0u);
+#pragma unroll 1
+        for (uint32_t b = 0; b < cnt; ++b)
+          N += (lane_u64(nv, b) & kSizeMask) - (j + b >= W ? (lane_u64(nov, b) & kSizeMask) : 0u);
+        if (t == 0) {
+          const uint32_t kind_lg = ((uint32_t)KIND_UNIFORM << 8) | (uint32_t)__builtin_ctz(P.rmax);
+#pragma unroll 1
+          for (uint32_t b = 0; b < cnt; ++b) {
+            const uint32_t mode = ((fl >> (16 + b)) & 1u) ? (uint32_t)HIST_MODE_AHIST : (uint32_t)HIST_MODE_WAVEHIST;
+            const uint32_t d = dj + b >= nslot ? dj + b - nslot : dj + b;
+            st_agent(&slots[d].tag, make_tag(j + b + 1, mode, kind_lg));
+          }
+        }
+      } else
 #pragma unroll
       for (uint32_t b = 0; b < B; ++b) {
         if (b >= cnt) break;
@@ -1130,11 +1155,12 @@ __device__ __forceinline__ void stream_epilogue(const Params &P, Ctl &c, uint32_
 // tickets: it re-reads the copies until the 256 totals add up to the segment's byte count.
 // Counts only grow and the exact total is known, so a matching sum means every
 // contribution is in -- no per-flush acknowledgement wait is needed.
+template <bool CLEAR = true>
 __device__ __forceinline__ uint32_t flush_issue(uint32_t *lds, const Params &P, Ctl &c, uint32_t s, uint32_t kind,
                                                 uint32_t lg, uint32_t nt, bool synced, bool ticket = true) {
   const uint32_t t = threadIdx.x;
   if (!synced) __syncthreads();   // the caller's barrier already ended every add otherwise
-  const uint32_t h = table_bin(lds, c, kind, lg);
+  const uint32_t h = table_bin<CLEAR>(lds, c, kind, lg);
   const uint32_t copies = 1u << P.clog2;
   uint32_t *part = P.partial + ((size_t)s << (P.clog2 + 8));
   // bins t and t + 1 (t even) go in one 64-bit atomic: half as many atomics, which the
@@ -1257,7 +1283,7 @@ __device__ __forceinline__ void single_path(uint32_t *lds, const Params &P, Ctl 
   // re-reads the copies until they hold all n bytes, so it needs nothing from the others
   // but their atomics, and the others wait for nothing: the chain after the last count is
   // its atomics landing plus one re-read, not two returning atomics and then the read.
-  flush_issue(lds, P, c, 0, kind, lg, 0, false, false);
+  flush_issue<false>(lds, P, c, 0, kind, lg, 0, false, false);   // its only flush: the table stays as it is
   if (blockIdx.x + 1u == gridDim.x) {
     finalize_segment<16>(P, c, 0, sd);
     if (P.host_done) {

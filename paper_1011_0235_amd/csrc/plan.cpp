@@ -75,10 +75,12 @@ hist_status_t plan_split(std::vector<SegDesc> &segs, uint64_t tile, uint32_t max
   return HIST_OK;
 }
 
-hist_status_t plan_multi(std::vector<SegDesc> &segs, uint64_t tile, uint32_t max_grid, MultiPlan *mp) {
+hist_status_t plan_multi(std::vector<SegDesc> &segs, uint64_t tile, uint32_t max_grid, MultiPlan *mp,
+                         uint32_t n_small, uint64_t small_tile) {
   constexpr uint64_t kQuantum = 16384;
   const uint32_t n = (uint32_t)segs.size();
   tile = std::max<uint64_t>(kQuantum, std::min<uint64_t>(tile, 1ull << 30));
+  small_tile = small_tile ? std::max<uint64_t>(kQuantum, std::min<uint64_t>(small_tile, tile)) : tile;
   uint64_t total = 0;
   for (uint32_t j = 0; j < n; ++j) {
     if (segs[j].size > kMaxSegBytes) return HIST_EOVERFLOW;
@@ -91,8 +93,9 @@ hist_status_t plan_multi(std::vector<SegDesc> &segs, uint64_t tile, uint32_t max
     segs[j].tile0 = (uint32_t)recs.size();
     const uint64_t sz = segs[j].size;
     uint64_t off = 0;
+    const uint64_t tj = j < n_small ? small_tile : tile;
     do {   // an empty segment still gets one (empty) tile, so that it is finalized
-      const uint64_t len = std::min<uint64_t>(tile, sz - off);
+      const uint64_t len = std::min<uint64_t>(tj, sz - off);
       recs.push_back(TileRec{reinterpret_cast<uint64_t>(segs[j].ptr) + off, (uint32_t)len, j});
       off += len;
       if (recs.size() >= 0x7FFFFFFFull) return HIST_EOVERFLOW;

@@ -142,7 +142,10 @@ struct MultiPlan {
 // segs: ptr/size/out/acc/chunk/stream_idx filled; tile0/ntiles are filled here.
 // Launches whose chunks may wait: tiles of at most `tile` bytes, in segment order, handed out
 // by the launch's counter.
-hist_status_t plan_multi(std::vector<SegDesc> &segs, uint64_t tile, uint32_t max_grid, MultiPlan *mp);
+// Tiles in segment order for a launch that hands them out dynamically; the first n_small
+// segments are cut into tiles of at most small_tile bytes (0: all tiles up to `tile`).
+hist_status_t plan_multi(std::vector<SegDesc> &segs, uint64_t tile, uint32_t max_grid, MultiPlan *mp,
+                         uint32_t n_small = 0, uint64_t small_tile = 0);
 // Static launches that never wait: one equal share of the launch's bytes per workgroup,
 // cut at 16 KiB steps from each segment's start into tiles of at most `tile` bytes.  Each
 // segment also costs its workgroups a switch (flush, merge, next descriptor), about what

@@ -317,6 +317,21 @@ def test_window_sizes_around_sequencer_batch(hm, W, S, rmax, theta, lag):
     st.close()
 
 
+@pytest.mark.parametrize("W,lag", [(3, 1), (4, 0), (2, 6)])
+def test_window_decisions_known_to_the_host(hm, W, lag):
+    # with the uniform switch (theta 0, S >= 256 rmax) the host hands every chunk its
+    # decision (AHist iff a chunk of the window held a byte) and nothing waits; runs of empty
+    # chunks longer than the window give the per-wavefront decisions, and the traces must
+    # still equal the rule's
+    g = np.random.default_rng(77 + W + lag)
+    chunks = []
+    for k in range(90):
+        n = 0 if (k // 6) % 3 == 1 else int(g.integers(1, 150_000))
+        chunks.append(G.clipped_normal_bytes(n, float(g.uniform(20, 235)), float(g.uniform(2, 40)), g))
+    ref = check(hm, chunks, W=W, theta=0, S=8192, rmax=32, lag=lag, many=True)
+    assert len(set(ref["modes"])) == 2   # both decisions occur
+
+
 @pytest.mark.parametrize("W", [32, 256])
 def test_full_size_moving_window_overlapping(hm, W):
     # the bench's moving-window streams: 66 x 4 MiB pushed three times over two HIP streams at
