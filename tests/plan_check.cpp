@@ -77,11 +77,19 @@ static double split_case(const std::vector<uint64_t> &sizes, uint32_t maxg, uint
   return sum ? (double)mx * mp.grid / (double)sum : 1.0;
 }
 
-static bool multi_case(const std::vector<uint64_t> &sizes, uint32_t maxg, uint64_t tile) {
+static bool multi_case(const std::vector<uint64_t> &sizes, uint32_t maxg, uint64_t tile, uint32_t n_small = 0,
+                       uint64_t small_tile = 0) {
   std::vector<SegDesc> segs = segments(sizes);
   MultiPlan mp;
-  return plan_multi(segs, tile, maxg, &mp) == HIST_OK && covered(segs, mp, tile) && mp.grid >= 1 &&
-         mp.grid <= std::max<uint32_t>(1, maxg);
+  if (plan_multi(segs, tile, maxg, &mp, n_small, small_tile) != HIST_OK || !covered(segs, mp, tile) || mp.grid < 1 ||
+      mp.grid > std::max<uint32_t>(1, maxg))
+    return false;
+  // the first n_small segments' tiles are at most small_tile (at least 16 KiB) long
+  const TileRec *r = reinterpret_cast<const TileRec *>(mp.blob.data() + mp.seg_bytes);
+  const uint64_t lim = std::max<uint64_t>(16384, std::min<uint64_t>(small_tile, std::max<uint64_t>(16384, tile)));
+  for (uint32_t i = 0; i < mp.ntiles; ++i)
+    if (small_tile && r[i].seg < n_small && r[i].len > lim) return false;
+  return true;
 }
 
 // ---- forward progress of launches whose chunks wait for decisions (a model on the real plan)
@@ -105,7 +113,8 @@ struct Sim {
 // earlier one's (as when the earlier launch's queue is still held by its own wait for the
 // launch before it); otherwise it mixes them at random.
 static bool simulate(const std::vector<uint64_t> &chunk_bytes, uint64_t tile, uint32_t grid_cap, uint32_t slots,
-                     uint32_t lag, bool window, bool later_first, std::mt19937_64 &g) {
+                     uint32_t lag, bool window, bool later_first, std::mt19937_64 &g, uint32_t n_small = 0,
+                     uint64_t small_tile = 0) {
   const uint32_t m = (uint32_t)chunk_bytes.size();
   struct L {
     MultiPlan mp;
@@ -114,7 +123,7 @@ static bool simulate(const std::vector<uint64_t> &chunk_bytes, uint64_t tile, ui
   } ln[2];
   for (int l = 0; l < 2; ++l) {
     ln[l].segs = segments(chunk_bytes);
-    if (plan_multi(ln[l].segs, tile, grid_cap, &ln[l].mp) != HIST_OK) return false;
+    if (plan_multi(ln[l].segs, tile, grid_cap, &ln[l].mp, n_small, small_tile) != HIST_OK) return false;
     ln[l].left = ln[l].mp.grid;
   }
   const uint32_t nchunk = 2 * m;
@@ -206,7 +215,9 @@ int main() {
     }
     const uint32_t maxg = 1 + (uint32_t)(g() % 1200);
     const uint64_t tile = 16384ull * (1 + g() % 128);
-    if (split_case(s, maxg, tile) == 0 || !multi_case(s, maxg, tile)) {
+    const uint32_t n_small = (uint32_t)(g() % (s.size() + 1));
+    if (split_case(s, maxg, tile) == 0 || !multi_case(s, maxg, tile) ||
+        !multi_case(s, maxg, tile, n_small, 16384ull * (1 + g() % 8))) {
       std::printf("invalid plan at case %d\n", it);
       bad = 1;
     }
@@ -222,12 +233,17 @@ int main() {
     for (int it = 0; it < 300 && !bad; ++it) {
       const uint32_t slots = 16 + (uint32_t)(gs() % 48), lag = (uint32_t)(gs() % 4);
       const bool window = (gs() & 1) != 0, later_first = (gs() & 1) != 0;
-      if (simulate(chunks, 16384, slots / 2, slots, lag, window, later_first, gs)) ++ok_half;
+      // tiles of 16-64 KiB; on half the runs the chunks that decide later chunks of the same
+      // launch are cut into the smallest tiles (the planner's producer prefix)
+      const uint64_t tile = 16384ull << (gs() % 3);
+      const uint32_t m = (uint32_t)chunks.size();
+      const uint32_t n_small = ((gs() & 1) != 0 && m > lag + 1) ? m - 1 - lag : 0u;
+      if (simulate(chunks, tile, slots / 2, slots, lag, window, later_first, gs, n_small, 16384)) ++ok_half;
       else {
         std::printf("stall with half-capacity grids at case %d\n", it);
         bad = 1;
       }
-      if (!simulate(chunks, 16384, slots, slots, lag, window, later_first, gs)) ++stalls_full;
+      if (!simulate(chunks, tile, slots, slots, lag, window, later_first, gs, n_small, 16384)) ++stalls_full;
     }
     std::printf("progress model: %d of 300 runs finished at half capacity; %d of 300 stalled at full\n", ok_half,
                 stalls_full);
