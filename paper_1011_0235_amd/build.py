@@ -8,6 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhistmi.so")
+LIB_TIMELINE = os.path.join(HERE, "libhistmi_timeline.so")
 SOURCES = ["kernels.hip", "noalloc.hip", "api.cpp", "plan.cpp", "server.cpp", "ingest.cpp"]
 ARCH = "gfx950"
 
@@ -25,7 +26,19 @@ def hip_flags():
     ]
 
 
+def _link(objs, out, verbose):
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = ["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+
+
 def build(verbose: bool = False) -> str:
+    """Build libhistmi.so and its diagnostic twin libhistmi_timeline.so (the same sources,
+    the kernel compiled with HISTMI_TIMELINE: per-workgroup event timestamps, see
+    include/histmi_timeline.h)."""
     objs = []
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
@@ -39,12 +52,13 @@ def build(verbose: bool = False) -> str:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
         objs.append(obj)
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = ["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
+    _link(objs, LIB, verbose)
+    tl_obj = os.path.join(bdir, "kernels_timeline.o")
+    cmd = ["hipcc"] + hip_flags() + ["-DHISTMI_TIMELINE", "-c", os.path.join(CSRC, "kernels.hip"), "-o", tl_obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    _link([tl_obj if o.endswith("kernels.hip.o") else o for o in objs], LIB_TIMELINE, verbose)
     return LIB
 
 

@@ -68,7 +68,37 @@ struct Ctl {
   uint32_t ehist[24];      // rule P: values per scale offset e
   uint32_t words[256];     // binning pattern words of the current segment
   uint32_t bitmap[512];    // overlap check of a pattern (up to HIST_S_MAX sub-bins)
+#ifdef HISTMI_TIMELINE
+  uint32_t tl_n;           // timeline records written by this workgroup
+#endif
 };
+
+// Per-workgroup timeline (diagnostic build only, -DHISTMI_TIMELINE: libhistmi_timeline.so).
+// Thread 0 of each of the first kTlWgs workgroups records up to kTlPer events, each one
+// word: phase << 56 | segment << 40 | the 100 MHz device clock (40 bits).  The recording
+// adds one store per event and changes no step of the path; the default build compiles it
+// out.  Phases: 0 entry, 2 segment set up (decision taken, table staged), 3 tile counted,
+// 4 flushed (and, in multi-segment launches, the finalizer verdict known), 5 finalizer
+// start, 6 merged, 7 finalizer done, 8 exit, 9 flush start (every wavefront's adds done),
+// 10 table summed, 11 atomics issued, 12 sequencer lock taken, 13 batch decided (segment
+// field: chunks), 14 lock released, 15 batch loaded (segment field: chunks present).
+#ifdef HISTMI_TIMELINE
+constexpr uint32_t kTlWgs = 2048, kTlPer = 256;
+__device__ uint64_t g_timeline[kTlWgs * kTlPer];
+#define TL(c_, ph_, seg_)                                                                              \
+  do {                                                                                                 \
+    if (threadIdx.x == 0) {                                                                            \
+      const uint32_t i_ = (c_).tl_n++;                                                                 \
+      if (i_ < kTlPer && blockIdx.x < kTlWgs)                                                          \
+        g_timeline[blockIdx.x * kTlPer + i_] = ((uint64_t)(ph_) << 56) | ((uint64_t)((seg_) & 0xFFFF) << 40) | \
+                                               ((uint64_t)wall_clock64() & ((1ull << 40) - 1));        \
+    }                                                                                                  \
+  } while (0)
+#else
+#define TL(c_, ph_, seg_) \
+  do {                    \
+  } while (0)
+#endif
 
 // ------------------------------------------------------------------ block helpers
 
@@ -887,6 +917,7 @@ __device__ __forceinline__ void sequence_stream(const Params &P, Ctl &c, StreamD
     const bool holder = c.flag != 0;
     __syncthreads();
     if (!holder) return;
+    TL(c, 12, 0);
     // the previous holder stored these before it released the lock (values every thread
     // shares are moved to scalar registers)
     uint64_t j = lane_u64(ld_agent(&st->done), 0);
@@ -973,6 +1004,7 @@ __device__ __forceinline__ void sequence_stream(const Params &P, Ctl &c, StreamD
         for (uint32_t i = 0; i < 4 * 3; ++i) (&c.coll[cprev][0][0])[i] = 0;
       // chunks j .. j + cnt - 1 are there (all four wavefronts saw every entry)
       const uint32_t cnt = (uint32_t)__builtin_ctz((fl & 0xFFu) | (1u << B));
+      TL(c, 15, cnt);
       uint32_t alarm = 0;
       // A batch whose decisions are all the uniform table (the budget holds rmax sub-bins for
       // every value), with no change detection and no collision criterion, differs from chunk to chunk only in the mode, which the hot flags carry: the window
@@ -1025,6 +1057,7 @@ __device__ __forceinline__ void sequence_stream(const Params &P, Ctl &c, StreamD
       sj = wrap(sj, cnt);
       so = wrap(so, cnt);
       dj = dj + cnt >= nslot ? dj + cnt - nslot : dj + cnt;
+      TL(c, 13, cnt);
       if (cnt < B) break;
     }
     if (alarm_on && pcnt) {
@@ -1055,6 +1088,7 @@ __device__ __forceinline__ void sequence_stream(const Params &P, Ctl &c, StreamD
     order_global();
     __syncthreads();
     if (t == 0) st_agent(&st->seq_lock, 0u);
+    TL(c, 14, 0);
     order_global();
     // look once more: a chunk that arrived while the lock was held
     const uint64_t e = ld_agent(&ring[(size_t)sj * 256u + t]);
@@ -1160,7 +1194,9 @@ __device__ __forceinline__ uint32_t flush_issue(uint32_t *lds, const Params &P, 
                                                 uint32_t lg, uint32_t nt, bool synced, bool ticket = true) {
   const uint32_t t = threadIdx.x;
   if (!synced) __syncthreads();   // the caller's barrier already ended every add otherwise
+  TL(c, 9, s);
   const uint32_t h = table_bin<CLEAR>(lds, c, kind, lg);
+  TL(c, 10, s);
   const uint32_t copies = 1u << P.clog2;
   uint32_t *part = P.partial + ((size_t)s << (P.clog2 + 8));
   // bins t and t + 1 (t even) go in one 64-bit atomic: half as many atomics, which the
@@ -1174,6 +1210,7 @@ __device__ __forceinline__ uint32_t flush_issue(uint32_t *lds, const Params &P, 
 #ifdef HISTMI_STRICT_FENCES
   __threadfence();
 #endif
+  TL(c, 11, s);
   uint32_t before = 0;
   if (ticket && t == 0)
     before = __hip_atomic_fetch_add(&P.seg_done[s], nt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1183,6 +1220,7 @@ __device__ __forceinline__ uint32_t flush_issue(uint32_t *lds, const Params &P, 
 template <uint32_t NF = 8>
 __device__ __forceinline__ void finalize_segment(const Params &P, Ctl &c, uint32_t s, const SegDesc &sd) {
   const uint32_t t = threadIdx.x;
+  TL(c, 5, s);
   {
 #ifdef HISTMI_STRICT_FENCES
     __threadfence();
@@ -1226,6 +1264,7 @@ __device__ __forceinline__ void finalize_segment(const Params &P, Ctl &c, uint32
       }
       __builtin_amdgcn_s_sleep(2);
     }
+    TL(c, 6, s);
     for (uint32_t q = 0; q < copies; ++q) st_agent(&part[(q << 8) | t], 0u);
     if (sd.out) *gmem(&sd.out[t]) = tot;
     if (sd.acc) __hip_atomic_fetch_add(gmem(&sd.acc[t]), (uint64_t)tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1233,6 +1272,7 @@ __device__ __forceinline__ void finalize_segment(const Params &P, Ctl &c, uint32
     else if (sd.chunk == kServerChunk) server_epilogue(P, c, sd.stream_idx, tot);
     if (t == 0) st_agent(&P.seg_done[s], 0u);
   }
+  TL(c, 7, s);
 }
 
 template <int KIND>
@@ -1273,17 +1313,20 @@ __device__ __forceinline__ void single_path(uint32_t *lds, const Params &P, Ctl 
   const uint32_t t = threadIdx.x;
   const SegDesc sd = P.seg0;
   const uint32_t kind = begin_segment(lds, P, c, sd, tag_prefetch(P, 0));
+  TL(c, 2, 0);
   const uint32_t lg = c.lg;
   if (kind == KIND_WAVE) run_strided<KIND_WAVE, U>(lds, P, make_adder<KIND_WAVE>(lds, P, c), sd.ptr, sd.size);
   else if (kind == KIND_WAVE_AGG) run_strided<KIND_WAVE_AGG, U>(lds, P, make_adder<KIND_WAVE_AGG>(lds, P, c), sd.ptr, sd.size);
   else if (kind == KIND_UNIFORM) run_strided<KIND_UNIFORM, U>(lds, P, make_adder<KIND_UNIFORM>(lds, P, c), sd.ptr, sd.size);
   else run_strided<KIND_LOOKUP, U>(lds, P, make_adder<KIND_LOOKUP>(lds, P, c), sd.ptr, sd.size);
+  TL(c, 3, 0);
   // No ticket elects the finalizer: the grid's last workgroup (the last dispatched, so
   // about the last to finish counting) finalizes once its own counts are flushed.  Its merge
   // re-reads the copies until they hold all n bytes, so it needs nothing from the others
   // but their atomics, and the others wait for nothing: the chain after the last count is
   // its atomics landing plus one re-read, not two returning atomics and then the read.
   flush_issue<false>(lds, P, c, 0, kind, lg, 0, false, false);   // its only flush: the table stays as it is
+  TL(c, 4, 0);
   if (blockIdx.x + 1u == gridDim.x) {
     finalize_segment<16>(P, c, 0, sd);
     if (P.host_done) {
@@ -1371,6 +1414,7 @@ __device__ __forceinline__ void multi_path(uint32_t *lds, const Params &P, Ctl &
       hint = 0;   // loaded where it is used: a prefetch here costs the kernel its fourth wave per SIMD
     }
     kind = begin_segment(lds, P, c, c.sd[sp], hint);
+    TL(c, 2, cur);
     lg = c.lg;
   }
   while (tile < tile_end) {
@@ -1387,6 +1431,7 @@ __device__ __forceinline__ void multi_path(uint32_t *lds, const Params &P, Ctl &
     else if (kind == KIND_WAVE_AGG) run_primed<KIND_WAVE_AGG, U>(make_adder<KIND_WAVE_AGG>(lds, P, c), rg, rot, a, mid);
     else if (kind == KIND_UNIFORM) run_primed<KIND_UNIFORM, U>(make_adder<KIND_UNIFORM>(lds, P, c), rg, rot, a, mid);
     else run_primed<KIND_LOOKUP, U>(make_adder<KIND_LOOKUP>(lds, P, c), rg, rot, a, mid);
+    TL(c, 3, cur);
     ++nt;
     // one barrier ends the tile: every add is done and the next tile is published (slot by
     // parity, so a wave still reading the previous step's slot is never overwritten)
@@ -1414,12 +1459,14 @@ __device__ __forceinline__ void multi_path(uint32_t *lds, const Params &P, Ctl &
       if (t == 0) c.flag = (before + nt == c.sd[sp].ntiles) ? 1u : 0u;
       if (has_nxt) seg_stage(c, sp ^ 1u, w);
       __syncthreads();
+      TL(c, 4, cur);
       if (c.flag) finalize_segment(P, c, cur, c.sd[sp]);
       if (has_nxt) {
         sp ^= 1u;
         cur = ns;
         nt = 0;
         kind = begin_segment(lds, P, c, c.sd[sp], hint);   // ends with the third barrier
+        TL(c, 2, cur);
         lg = c.lg;
       }
     }
@@ -1456,8 +1503,13 @@ __global__ void __launch_bounds__(kBlock) hist_main(const Params P) {
   extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
   touch_params();
   Ctl &c = *reinterpret_cast<Ctl *>(lds + P.table_words + P.look_words);
+#ifdef HISTMI_TIMELINE
+  if (threadIdx.x == 0) c.tl_n = 0;
+#endif
+  TL(c, 0, 0);
   if (P.single) single_path<U>(lds, P, c);
   else multi_path<U>(lds, P, c);
+  TL(c, 8, 0);
 }
 
 // Rule P as a stand-alone call: one workgroup reads a uint64[256] histogram and writes a
@@ -1536,3 +1588,26 @@ hipError_t occupancy(uint32_t lds_bytes, int *blocks_per_cu) {
 }
 
 }  // namespace histmi
+
+#ifdef HISTMI_TIMELINE
+// Diagnostic build only (see include/histmi_timeline.h).
+extern "C" hipError_t hist_timeline_shape(uint32_t *workgroups, uint32_t *per_workgroup) {
+  if (!workgroups || !per_workgroup) return hipErrorInvalidValue;
+  *workgroups = histmi::kTlWgs;
+  *per_workgroup = histmi::kTlPer;
+  return hipSuccess;
+}
+extern "C" hipError_t hist_timeline_read(uint64_t *host, size_t bytes) {
+  if (!host || bytes != sizeof(histmi::g_timeline)) return hipErrorInvalidValue;
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(histmi::g_timeline));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(host, p, bytes, hipMemcpyDeviceToHost);
+}
+extern "C" hipError_t hist_timeline_reset(void) {
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(histmi::g_timeline));
+  if (e != hipSuccess) return e;
+  return hipMemset(p, 0, sizeof(histmi::g_timeline));
+}
+#endif

@@ -44,6 +44,22 @@ def test_library_exports_every_declared_symbol(hm):
     assert sorted(hm.declared_symbols()) == header_symbols()
 
 
+def test_timeline_build_exports_its_calls(hm):
+    # the diagnostic twin (kernel compiled with HISTMI_TIMELINE) exports the same ABI plus
+    # the three calls include/histmi_timeline.h declares; the default library does not
+    tl_path = os.path.join(os.path.dirname(hm.LIB_PATH), "libhistmi_timeline.so")
+    assert os.path.exists(tl_path)
+    tl = ctypes.CDLL(tl_path)
+    text = open(os.path.join(ROOT, "include", "histmi_timeline.h")).read()
+    calls = sorted(set(re.findall(r"^int (hist_timeline_[a-z_]+)\(", text, re.M)))
+    assert calls == ["hist_timeline_read", "hist_timeline_reset", "hist_timeline_shape"]
+    for name in calls + header_symbols():
+        assert hasattr(tl, name), name
+    lib = ctypes.CDLL(hm.LIB_PATH)
+    for name in calls:
+        assert not hasattr(lib, name), name
+
+
 def test_strerror(hm):
     for st in (hm.OK, hm.EINVAL, hm.ENOMEM, hm.EOVERFLOW, hm.EBUSY, hm.EDEVICE, hm.ENOTSUP, hm.ETIMEDOUT,
                hm.ECANCELED):

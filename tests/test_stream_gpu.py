@@ -152,10 +152,11 @@ def test_push_and_push_many_agree_across_calls(hm):
 
 
 def test_full_size_single_stream(hm):
-    # the single stream at its real size: 66 chunks of 4 MiB, lag 0 and a pipelined lag
+    # the single stream at its real size: 66 chunks of 4 MiB, lags 0 and 1 (the scope's
+    # config-2 row, with the paper's budget) and pipelined lags
     chunks = single_stream_chunks(4 << 20)
     hists = [O.hist(c) for c in chunks]
-    for lag, S, rmax, theta in ((0, 960, 8, 45), (15, 8192, 32, 45), (7, 960, 8, 0)):
+    for lag, S, rmax, theta in ((0, 960, 8, 45), (1, 960, 8, 45), (15, 8192, 32, 45), (7, 960, 8, 0)):
         ref = O.stream_reference(None, W=1, theta_pct=theta, S=S, rmax=rmax, lag=lag, hists=hists)
         got, snap, modes, pats = run_stream(hm, chunks, 1, theta, S, rmax, lag, 0, True)
         assert np.array_equal(got, ref["hists"].astype(np.int64)), lag
