@@ -459,16 +459,18 @@ static bool decisions_uniform(const hist_stream_config_t &c) {
   }
 }
 
-// The host hands each chunk its decision (the chunk then starts without waiting; the device
-// still makes and publishes the same decisions) when the decisions are uniform as above and
-// the chunks are not sequenced (W = 1, no change detection).  Sequenced streams could be told
-// their decisions too, but there the finalizers' in-order sequencing, not the decision waits,
-// sets the pace, and a static plan (which known decisions allow) leaves a workgroup that
-// sequences for a while with the rest of its share still to count: measured no faster
-// (W = 32, lag 31: 3.79 TB/s against 3.70 with device decisions) or slower (W = 32, lag 65:
-// 3.82 against 4.99).
-static bool decisions_known(const hist_stream_config_t &c) {
-  return c.W == 1 && c.alarm_pct == 0 && decisions_uniform(c);
+// The host hands each chunk of a launch of m chunks its decision (the chunk then starts
+// without waiting; the device still makes and publishes the same decisions) when the
+// decisions are uniform as above, unless the chunks are sequenced (W > 1 or change detection)
+// and every decision of the launch comes from an earlier launch (lag + 1 >= m): such a
+// launch waits only on the launch before it and runs on equal byte shares, which measured
+// faster than known decisions (W = 32, lag 65: 4.96 TB/s against 3.87).  Sequenced launches
+// with known decisions hand their tiles out dynamically: a workgroup that sequences for a
+// while would otherwise leave the rest of a static share to count late (W = 32, lag 31: 3.89
+// TB/s known and dynamic, 3.79 known and static, 3.65 with the device's decisions).
+static bool decisions_known(const hist_stream_config_t &c, uint32_t m) {
+  const bool sequenced = c.W > 1 || c.alarm_pct != 0;
+  return decisions_uniform(c) && (!sequenced || m > c.lag + 1);
 }
 
 // Make `s` wait for the launch in slot i, unless that launch went to `s` itself (then it is
@@ -811,8 +813,9 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
     stream_layout(st->cfg.S, st->cfg.rmax, mode, &P);
     stream_params(st, &P);
     P.chunk_base = st->pushed;
-    const bool known = decisions_known(st->cfg);
-    const uint32_t fam = known ? kFamStreamKnown : kFamStream;
+    const bool known = decisions_known(st->cfg, m);
+    const bool sequenced = st->cfg.W > 1 || st->cfg.alarm_pct != 0;
+    const uint32_t fam = (known && !sequenced) ? kFamStreamKnown : kFamStream;
     // Chunks that wait for decisions spin on their CU.  Two launches of the stream may be in
     // flight, and the hardware dispatches both at once: if they could not all be resident
     // together, the later launch's waiting workgroups could hold the CUs that the earlier
@@ -827,12 +830,12 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
     // the largest tile; launches that may wait cut tiles small enough that the lag + 1 chunks
     // which may run at once still fill the grid
     uint64_t tile = (uint64_t)g_tune[fam].tile_kib * 1024;
-    if (!known) {
+    if (!known || sequenced) {
       uint64_t total = 0;
       for (uint32_t j = 0; j < m; ++j) total += h_sizes[first + j];
       const uint64_t per_chunk = std::max<uint64_t>(1, total / m);
       const uint64_t inflight = std::min<uint32_t>(st->cfg.lag + 1, m);
-      const uint64_t fill = ceil_div(per_chunk * inflight, maxg);     // lag + 1 chunks cover the grid
+      const uint64_t fill = known ? ~0ull : ceil_div(per_chunk * inflight, maxg);   // lag + 1 chunks cover the grid
       const uint64_t several = ceil_div(total, (uint64_t)maxg * g_tune[fam].tpw);   // tiles per workgroup
       tile = std::min<uint64_t>(tile, std::max<uint64_t>(16384, ceil_div(std::min(fill, several), 16384) * 16384));
     }
@@ -881,7 +884,8 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
     // its chunks wait only on launches that run on their own, never on each other, so equal
     // shares are safe too (with the residency cap of launches that wait, set above).
     const bool ahead = !known && m <= st->cfg.lag + 1;
-    if (known || ahead) {
+    const bool split = (known && !sequenced) || ahead;
+    if (split) {
       TRY(plan_split(segs, (uint64_t)g_tune[fam].tile_kib * 1024, maxg, &mp));
     } else {
       // Chunks 0 .. m - 2 - lag of this launch make the decisions of its later chunks.  Where
@@ -892,7 +896,7 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
       // their workgroups spin.  Each small tile costs a flush, though; where every decision is
       // the uniform table (a window stream with the tuned switch) the waits are short anyway
       // and the extra flushes cost more than they save, so those keep the larger tiles.
-      const uint32_t producers = (m > st->cfg.lag + 1 && !decisions_uniform(st->cfg)) ? m - 1 - st->cfg.lag : 0u;
+      const uint32_t producers = (m > st->cfg.lag + 1 && !known) ? m - 1 - st->cfg.lag : 0u;
       uint64_t per_chunk = 0;
       for (uint32_t j = 0; j < m; ++j) per_chunk += h_sizes[first + j];
       per_chunk = std::max<uint64_t>(1, per_chunk / m);
@@ -902,7 +906,7 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
     const bool join = known && st->since_join + m > kMaxChunksPerLaunch;
     TRY(stream_launch_begin(st, s, serialize || join));
     st->since_join = join ? m : st->since_join + m;
-    TRY(run_multi(d, P, mp, copies, s, nullptr, !(known || ahead), true));
+    TRY(run_multi(d, P, mp, copies, s, nullptr, !split, true));
     stream_launch_end(st, s);
     for (uint32_t j = 0; j < m; ++j) st->recent[(st->pushed + j) % ring] = h_sizes[first + j];
     st->pushed += m;
