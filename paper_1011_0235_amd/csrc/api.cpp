@@ -443,6 +443,11 @@ struct hist_stream {
   // earlier one once the chunks pushed since the last such point would pass
   // kMaxChunksPerLaunch: at most 2 x kMaxChunksPerLaunch chunks are ever in flight.
   uint64_t since_join = 0;
+  // A window stream with the uniform switch and no change detection does not walk its window
+  // in order (its chunks carry kUnwalked; the configuration fixes this for every launch):
+  // nothing in a launch needs the window, so the device's copy of it falls behind until
+  // window_rebuild_kernel sums it from the ring again, before a read.
+  bool window_stale = false;
 };
 
 // Whether every decision is a function of the chunk sizes alone: a budget that gives every
@@ -460,17 +465,18 @@ static bool decisions_uniform(const hist_stream_config_t &c) {
 }
 
 // The host hands each chunk of a launch of m chunks its decision (the chunk then starts
-// without waiting; the device still makes and publishes the same decisions) when the
-// decisions are uniform as above, unless the chunks are sequenced (W > 1 or change detection)
-// and every decision of the launch comes from an earlier launch (lag + 1 >= m): such a
-// launch waits only on the launch before it and runs on equal byte shares, which measured
-// faster than known decisions (W = 32, lag 65: 4.96 TB/s against 3.87).  Sequenced launches
-// with known decisions hand their tiles out dynamically: a workgroup that sequences for a
-// while would otherwise leave the rest of a static share to count late (W = 32, lag 31: 3.89
-// TB/s known and dynamic, 3.79 known and static, 3.65 with the device's decisions).
+// without waiting; the device still publishes the same decisions) when the decisions are
+// uniform as above.  A window stream (W > 1) without change detection then does not walk its
+// window in the launch either (see hist_stream::window_stale), so its launches run on equal
+// byte shares like those of W = 1.  With change detection the window is walked in order: the
+// host hands the decisions out only when some chunk of the launch waits for a decision made
+// in it (m > lag + 1), with tiles handed out dynamically so that a workgroup that walks for a
+// while leaves no static share behind (W = 32, lag 31: 3.89 TB/s so, 3.79 on a static plan,
+// 3.65 with the device's decisions); when every decision comes from an earlier launch, its
+// chunks wait only on that launch and run on equal shares, which measured faster than known
+// decisions there (W = 32, lag 65: 4.96 TB/s against 3.87).
 static bool decisions_known(const hist_stream_config_t &c, uint32_t m) {
-  const bool sequenced = c.W > 1 || c.alarm_pct != 0;
-  return decisions_uniform(c) && (!sequenced || m > c.lag + 1);
+  return decisions_uniform(c) && (c.alarm_pct == 0 || m > c.lag + 1);
 }
 
 // Make `s` wait for the launch in slot i, unless that launch went to `s` itself (then it is
@@ -815,7 +821,9 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
     P.chunk_base = st->pushed;
     const bool known = decisions_known(st->cfg, m);
     const bool sequenced = st->cfg.W > 1 || st->cfg.alarm_pct != 0;
-    const uint32_t fam = (known && !sequenced) ? kFamStreamKnown : kFamStream;
+    const bool unwalked = known && sequenced && st->cfg.alarm_pct == 0;
+    const bool walks = sequenced && !unwalked;
+    const uint32_t fam = (known && !walks) ? kFamStreamKnown : kFamStream;
     // Chunks that wait for decisions spin on their CU.  Two launches of the stream may be in
     // flight, and the hardware dispatches both at once: if they could not all be resident
     // together, the later launch's waiting workgroups could hold the CUs that the earlier
@@ -830,7 +838,7 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
     // the largest tile; launches that may wait cut tiles small enough that the lag + 1 chunks
     // which may run at once still fill the grid
     uint64_t tile = (uint64_t)g_tune[fam].tile_kib * 1024;
-    if (!known || sequenced) {
+    if (!known || walks) {
       uint64_t total = 0;
       for (uint32_t j = 0; j < m; ++j) total += h_sizes[first + j];
       const uint64_t per_chunk = std::max<uint64_t>(1, total / m);
@@ -871,6 +879,13 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
           const uint32_t md = nz[(size_t)(src - lo + 1)] > nz[(size_t)(a - lo)] ? HIST_MODE_AHIST : HIST_MODE_WAVEHIST;
           segs[j].known = kKnown | (md << 16) | ((uint32_t)KIND_UNIFORM << 8) | lgmax;
         }
+        if (unwalked) {
+          // the decision after this chunk, by the same rule: chunks q - W + 1 .. q
+          const int64_t q = k0 + (int64_t)j;
+          const int64_t a = std::max<int64_t>(q - W + 1, lo);
+          if (nz[(size_t)(q - lo + 1)] > nz[(size_t)(a - lo)]) segs[j].known |= kAfterAhist;
+          segs[j].known |= kUnwalked;
+        }
       }
     }
     MultiPlan mp;
@@ -884,7 +899,7 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
     // its chunks wait only on launches that run on their own, never on each other, so equal
     // shares are safe too (with the residency cap of launches that wait, set above).
     const bool ahead = !known && m <= st->cfg.lag + 1;
-    const bool split = (known && !sequenced) || ahead;
+    const bool split = (known && !walks) || ahead;
     if (split) {
       TRY(plan_split(segs, (uint64_t)g_tune[fam].tile_kib * 1024, maxg, &mp));
     } else {
@@ -908,6 +923,7 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
     st->since_join = join ? m : st->since_join + m;
     TRY(run_multi(d, P, mp, copies, s, nullptr, !split, true));
     stream_launch_end(st, s);
+    if (unwalked) st->window_stale = true;
     for (uint32_t j = 0; j < m; ++j) st->recent[(st->pushed + j) % ring] = h_sizes[first + j];
     st->pushed += m;
   }
@@ -918,6 +934,12 @@ hist_status_t hist_stream_read(hist_stream_t *st, hist_stream_snapshot_t *snap, 
                                uint32_t *h_pattern_trace, uint32_t trace_len, void *stream) {
   if (!st) return HIST_EINVAL;
   TRY(stream_sync(st, static_cast<hipStream_t>(stream)));
+  if (st->window_stale) {   // nothing of the stream is in flight now
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    TRY_HIP(launch_window_rebuild(st->sa.d_st, st->pushed, s));
+    TRY_HIP(hipStreamSynchronize(s));
+    st->window_stale = false;
+  }
   bool timed_out = false;
   if (snap) {
     StreamDev h;

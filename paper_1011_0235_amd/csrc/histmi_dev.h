@@ -90,12 +90,16 @@ struct SegDesc {
   uint32_t stream_idx;   // index into Params::st for stream chunks and server requests
   uint32_t known;        // ordered-stream chunk: the decision it runs with when the host can
                          // tell it in advance (kKnown | mode << 16 | kind_lg, plus kKnownCold
-                         // when there is no history yet), else 0: wait for the device's decision
+                         // when there is no history yet), else 0: wait for the device's decision.
+                         // kUnwalked: a window stream's chunk whose launch does not walk the
+                         // window in order; kAfterAhist then gives the decision after it.
 };
 
 constexpr int64_t kServerChunk = -2;
 constexpr uint32_t kKnown = 1u << 31;
 constexpr uint32_t kKnownCold = 1u << 30;
+constexpr uint32_t kUnwalked = 1u << 29;
+constexpr uint32_t kAfterAhist = 1u << 28;
 
 // One tile of a multi-segment launch, written by the host: its bytes and its segment.
 // Tiles never span segments; their sizes may differ (smaller tiles near the end of a

@@ -1109,9 +1109,12 @@ __device__ __forceinline__ uint64_t clock_mhz(uint64_t s0, uint64_t w0, uint64_t
 // and rule P (Sec. III.B, Sec. III.C).  With a window of one chunk (W = 1) the decision after
 // chunk k depends on h_k alone, so epilogues of different chunks run independently; with
 // W > 1, or with change detection (which needs the Accumulator in chunk order), the chunks
-// are sequenced (see sequence_stream).
+// are sequenced (see sequence_stream) -- unless the host knew every decision of the launch
+// and no change detection runs (`known` carries kUnwalked): the decision after chunk k then
+// depends only on which chunks of the window hold bytes, which the host passes in, and the
+// window itself is rebuilt from the ring when it is next read or walked.
 __device__ __forceinline__ void stream_epilogue(const Params &P, Ctl &c, uint32_t sidx, int64_t k, uint32_t h,
-                                                uint64_t bytes) {
+                                                uint64_t bytes, uint32_t known) {
   const uint32_t t = threadIdx.x;
   StreamDev *st = P.st + sidx;
   const bool traced = (uint64_t)k < P.trace_cap;
@@ -1168,6 +1171,15 @@ __device__ __forceinline__ void stream_epilogue(const Params &P, Ctl &c, uint32_
       st_agent(&P.time_trace[3u * (uint64_t)k + 1u], w);
       st_agent(&P.time_trace[3u * (uint64_t)k + 2u], clock_mhz(sclk0, wall0, (uint64_t)clock64(), w));
     }
+  }
+  if (known & kUnwalked) {
+    if (t == 0) {
+      const uint32_t mode = (known & kAfterAhist) ? HIST_MODE_AHIST : HIST_MODE_WAVEHIST;
+      const uint32_t kind_lg = ((uint32_t)KIND_UNIFORM << 8) | (uint32_t)__builtin_ctz(P.rmax);
+      st_agent(&P.slots[(uint64_t)k % P.nslot].tag, make_tag((uint64_t)k + 1, mode, kind_lg));
+      __hip_atomic_fetch_add(&st->done, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return;
   }
   order_global();     // every entry is in before the CAS below (so a failing CAS means the
   __syncthreads();    // sequencer's last look will find them)
@@ -1268,7 +1280,7 @@ __device__ __forceinline__ void finalize_segment(const Params &P, Ctl &c, uint32
     for (uint32_t q = 0; q < copies; ++q) st_agent(&part[(q << 8) | t], 0u);
     if (sd.out) *gmem(&sd.out[t]) = tot;
     if (sd.acc) __hip_atomic_fetch_add(gmem(&sd.acc[t]), (uint64_t)tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (sd.chunk >= 0) stream_epilogue(P, c, sd.stream_idx, (int64_t)P.chunk_base + sd.chunk, tot, sd.size);
+    if (sd.chunk >= 0) stream_epilogue(P, c, sd.stream_idx, (int64_t)P.chunk_base + sd.chunk, tot, sd.size, sd.known);
     else if (sd.chunk == kServerChunk) server_epilogue(P, c, sd.stream_idx, tot);
     if (t == 0) st_agent(&P.seg_done[s], 0u);
   }
@@ -1553,6 +1565,28 @@ __global__ void __launch_bounds__(kBlock) read_probe_kernel(gu32x4 *v, uint64_t 
   if (lane_id() == 0 && acc) atomicAdd(reinterpret_cast<unsigned long long *>(sum), (unsigned long long)acc);
 }
 
+// A window stream's window after launches that did not walk it in order (their chunks left
+// their histograms and sizes in the ring, see stream_epilogue): MW is the sum of the last W
+// chunks' histograms and N their bytes (Sec. III.B), and the walk resumes at chunk n.  One
+// workgroup, thread t holds bin t; it runs after those launches, so plain accesses suffice.
+__global__ void __launch_bounds__(kBlock) window_rebuild_kernel(StreamDev *st, uint64_t n) {
+  const uint32_t t = threadIdx.x;
+  const uint32_t W = st->W, R = st->R;
+  const uint64_t *ring = st->ring;
+  const uint64_t *ring_n = st->ring_n;
+  uint64_t mw = 0, N = 0;
+  for (uint64_t q = n > W ? n - W : 0; q < n; ++q) {
+    const uint32_t slot = (uint32_t)(q % R);
+    mw += (uint32_t)ring[(size_t)slot * 256u + t];
+    N += ring_n[slot] & kSizeMask;
+  }
+  st->mw[t] = mw;
+  if (t == 0) {
+    st->win_n = N;
+    st->done = n;
+  }
+}
+
 // ------------------------------------------------------------------ host-side launchers
 
 uint32_t ctl_bytes() { return (uint32_t)((sizeof(Ctl) + 15) & ~(size_t)15); }
@@ -1569,6 +1603,11 @@ hipError_t launch_hist(const Params &P, const LaunchShape &sh, hipStream_t s, hi
 
 hipError_t launch_pattern_update(const uint64_t *h, uint32_t S, uint32_t rmax, hist_pattern_t *out, hipStream_t s) {
   hipLaunchKernelGGL(pattern_update_kernel, dim3(1), dim3(kBlock), 0, s, h, S, rmax, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_window_rebuild(StreamDev *st, uint64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(window_rebuild_kernel, dim3(1), dim3(kBlock), 0, s, st, n);
   return hipGetLastError();
 }
 

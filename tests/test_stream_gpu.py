@@ -333,6 +333,57 @@ def test_window_decisions_known_to_the_host(hm, W, lag):
     assert len(set(ref["modes"])) == 2   # both decisions occur
 
 
+@pytest.mark.parametrize("W,lag,criterion,theta,kappa", [(8, 2, 0, 0, 0), (40, 0, 0, 0, 0), (5, 9, 1, 45, 0)])
+def test_window_read_between_pushes(hm, W, lag, criterion, theta, kappa):
+    # with the uniform switch a window stream's launches do not walk the window (every
+    # decision comes from the host); the window is summed from the ring when read.  Reads
+    # after pushes of one, a few and many chunks -- runs of empty chunks among them, the
+    # window only partly filled at first, pushes on two HIP streams -- must each give the
+    # rule's state after that many chunks, and the decision after the last one.
+    g = np.random.default_rng(900 + W + lag)
+    chunks = []
+    for k in range(120):
+        n = 0 if (k // 7) % 4 == 2 else int(g.integers(1, 90_000))
+        chunks.append(G.clipped_normal_bytes(n, float(g.uniform(10, 245)), float(g.uniform(1, 50)), g))
+    S, rmax = 8192, 32
+    offs = np.cumsum([0] + [(c.size + 255) // 256 * 256 for c in chunks])
+    arena = np.zeros(int(offs[-1]) + 256, dtype=np.uint8)
+    for o, c in zip(offs, chunks):
+        arena[o:o + c.size] = c
+    d = dev(arena)
+    bufs = [(int(d.data_ptr()) + int(o), c.size) for o, c in zip(offs, chunks)]
+    outs = torch.full((len(chunks), 256), -1, dtype=torch.int32, device="cuda")
+    st = hm.Stream(W=W, theta_pct=theta, S=S, rmax=rmax, lag=lag, trace_cap=len(chunks), criterion=criterion,
+                   kappa_pct=kappa)
+    hs = [torch.cuda.Stream(), torch.cuda.Stream()]
+    torch.cuda.synchronize()
+    n = 0
+    for i, m in enumerate([1, 4, 30, 1, 1, 12, 50, 21]):
+        st.push_many(bufs[n:n + m], d_out=outs[n:n + m], stream=hs[i & 1])
+        n += m
+        if i % 2 == 1 or n == len(chunks):
+            ref = O.stream_reference(chunks[:n], W=W, theta_pct=theta, S=S, rmax=rmax, lag=lag,
+                                     criterion=criterion, kappa_pct=kappa)
+            snap, modes, pats = st.read(n, stream=hs[i & 1])
+            tag = (W, lag, n)
+            assert int(snap.chunks) == n, tag
+            assert [int(x) for x in snap.acc] == ref["acc"], tag
+            assert [int(x) for x in snap.mw] == ref["mw"], tag
+            assert [int(x) for x in modes] == ref["modes"], tag
+            assert [list(map(int, p)) for p in pats] == ref["patterns"], tag
+            # both tests fire for any non-empty window here
+            want = O.MODE_AHIST if sum(ref["mw"]) > 0 else O.MODE_WAVEHIST
+            assert int(snap.next_mode) == want, tag
+            assert snap.next_pattern.words() == O.rule_p(ref["mw"], S, rmax), tag
+    assert n == len(chunks)
+    got = outs.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+    assert np.array_equal(got, ref["hists"].astype(np.int64))
+    assert len(set(ref["modes"])) == 2
+    dg = hm.diag()
+    assert dg.invalid_patterns == 0 and dg.wait_timeouts == 0 and dg.merge_timeouts == 0
+    st.close()
+
+
 @pytest.mark.parametrize("W", [32, 256])
 def test_full_size_moving_window_overlapping(hm, W):
     # the bench's moving-window streams: 66 x 4 MiB pushed three times over two HIP streams at
