@@ -782,16 +782,15 @@ def main():
             row = {"GB/s": round(nbytes * ksteps / (tms * 1e-3) / 1e9, 1), "ms_per_step": round(tms / ksteps, 4)}
             # with the uniform switch (a threshold of 0, a budget of rmax sub-bins for every
             # value) each decision is a function of the chunk sizes, which the host hands to
-            # the chunks (nothing waits); a window stream then does not walk its window in the
-            # launch (it is summed from the ring when read).  With change detection the window
-            # is walked, and pushes that take every decision from earlier pushes
-            # (lag + 1 >= 66) wait on the push before, which measured faster.  Otherwise
-            # chunks wait for the device's decisions.
+            # the chunks (nothing waits).  A window stream then does not walk its window in the
+            # counting launch: without change detection it is summed from the ring when read,
+            # with it a one-workgroup launch after each push walks the chunks in order.
+            # Otherwise chunks wait for the device's decisions.
             uniform = 256 * r_ <= s_ and ((cr == hm.CRIT_MAXBIN and th == 0) or (cr == hm.CRIT_COLLISION and kp == 0)
                                           or (cr == hm.CRIT_BOTH and (th == 0 or kp == 0)))
-            host = uniform and (al == 0 or nchunk > l + 1)
-            row["decisions"] = "device" if not host else (
-                "host (uniform switch), window summed on read" if w_ > 1 and al == 0 else "host (uniform switch)")
+            row["decisions"] = "device" if not uniform else (
+                "host (uniform switch), walked after each push" if al else
+                "host (uniform switch), window summed on read" if w_ > 1 else "host (uniform switch)")
             # bounded waits that ran out (a decision or a merge): none is expected
             if d1.wait_timeouts != d0.wait_timeouts or d1.merge_timeouts != d0.merge_timeouts:
                 row["wait_timeouts"] = int(d1.wait_timeouts - d0.wait_timeouts)

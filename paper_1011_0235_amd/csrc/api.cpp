@@ -464,20 +464,17 @@ static bool decisions_uniform(const hist_stream_config_t &c) {
   }
 }
 
-// The host hands each chunk of a launch of m chunks its decision (the chunk then starts
-// without waiting; the device still publishes the same decisions) when the decisions are
-// uniform as above.  A window stream (W > 1) without change detection then does not walk its
-// window in the launch either (see hist_stream::window_stale), so its launches run on equal
-// byte shares like those of W = 1.  With change detection the window is walked in order: the
-// host hands the decisions out only when some chunk of the launch waits for a decision made
-// in it (m > lag + 1), with tiles handed out dynamically so that a workgroup that walks for a
-// while leaves no static share behind (W = 32, lag 31: 3.89 TB/s so, 3.79 on a static plan,
-// 3.65 with the device's decisions); when every decision comes from an earlier launch, its
-// chunks wait only on that launch and run on equal shares, which measured faster than known
-// decisions there (W = 32, lag 65: 4.96 TB/s against 3.87).
-static bool decisions_known(const hist_stream_config_t &c, uint32_t m) {
-  return decisions_uniform(c) && (c.alarm_pct == 0 || m > c.lag + 1);
-}
+// The host hands each chunk of a launch its decision (the chunk then starts without
+// waiting; the device still publishes the same decisions) when the decisions are uniform as
+// above.  Nothing in such a launch waits for the in-order walk of the window, so it runs on
+// equal byte shares like a stream with W = 1.  A window stream without change detection does
+// not walk at all (see hist_stream::window_stale); with change detection the walk follows
+// the counting launch in a one-workgroup launch of its own (walk_kernel).  Before this, such
+// pushes walked inside the counting launch: on dynamic tiles, so that a workgroup that walks
+// for a while leaves no static share behind (W = 32, lag 31, change detection at 4 points:
+// 2.87 TB/s), and pushes whose decisions all came from an earlier push waited on it on
+// equal shares (W = 32, lag 65 without change detection: 4.96 TB/s).
+static bool decisions_known(const hist_stream_config_t &c) { return decisions_uniform(c); }
 
 // Make `s` wait for the launch in slot i, unless that launch went to `s` itself (then it is
 // ordered before anything queued on `s` now).  Its event is recorded on its HIP stream now
@@ -819,11 +816,11 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
     stream_layout(st->cfg.S, st->cfg.rmax, mode, &P);
     stream_params(st, &P);
     P.chunk_base = st->pushed;
-    const bool known = decisions_known(st->cfg, m);
+    const bool known = decisions_known(st->cfg);
     const bool sequenced = st->cfg.W > 1 || st->cfg.alarm_pct != 0;
     const bool unwalked = known && sequenced && st->cfg.alarm_pct == 0;
-    const bool walks = sequenced && !unwalked;
-    const uint32_t fam = (known && !walks) ? kFamStreamKnown : kFamStream;
+    const bool walk_after = known && st->cfg.alarm_pct != 0;
+    const uint32_t fam = known ? kFamStreamKnown : kFamStream;
     // Chunks that wait for decisions spin on their CU.  Two launches of the stream may be in
     // flight, and the hardware dispatches both at once: if they could not all be resident
     // together, the later launch's waiting workgroups could hold the CUs that the earlier
@@ -838,7 +835,7 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
     // the largest tile; launches that may wait cut tiles small enough that the lag + 1 chunks
     // which may run at once still fill the grid
     uint64_t tile = (uint64_t)g_tune[fam].tile_kib * 1024;
-    if (!known || walks) {
+    if (!known) {
       uint64_t total = 0;
       for (uint32_t j = 0; j < m; ++j) total += h_sizes[first + j];
       const uint64_t per_chunk = std::max<uint64_t>(1, total / m);
@@ -886,6 +883,7 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
           if (nz[(size_t)(q - lo + 1)] > nz[(size_t)(a - lo)]) segs[j].known |= kAfterAhist;
           segs[j].known |= kUnwalked;
         }
+        if (walk_after) segs[j].known |= kWalkAfter;
       }
     }
     MultiPlan mp;
@@ -899,7 +897,7 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
     // its chunks wait only on launches that run on their own, never on each other, so equal
     // shares are safe too (with the residency cap of launches that wait, set above).
     const bool ahead = !known && m <= st->cfg.lag + 1;
-    const bool split = (known && !walks) || ahead;
+    const bool split = known || ahead;
     if (split) {
       TRY(plan_split(segs, (uint64_t)g_tune[fam].tile_kib * 1024, maxg, &mp));
     } else {
@@ -922,6 +920,7 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
     TRY(stream_launch_begin(st, s, serialize || join));
     st->since_join = join ? m : st->since_join + m;
     TRY(run_multi(d, P, mp, copies, s, nullptr, !split, true));
+    if (walk_after) TRY(dev_err(launch_walk(P, s)));
     stream_launch_end(st, s);
     if (unwalked) st->window_stale = true;
     for (uint32_t j = 0; j < m; ++j) st->recent[(st->pushed + j) % ring] = h_sizes[first + j];

@@ -93,6 +93,8 @@ struct SegDesc {
                          // when there is no history yet), else 0: wait for the device's decision.
                          // kUnwalked: a window stream's chunk whose launch does not walk the
                          // window in order; kAfterAhist then gives the decision after it.
+                         // kWalkAfter: a chunk whose launch leaves the in-order walk to a
+                         // walk_kernel launch that follows it.
 };
 
 constexpr int64_t kServerChunk = -2;
@@ -100,6 +102,7 @@ constexpr uint32_t kKnown = 1u << 31;
 constexpr uint32_t kKnownCold = 1u << 30;
 constexpr uint32_t kUnwalked = 1u << 29;
 constexpr uint32_t kAfterAhist = 1u << 28;
+constexpr uint32_t kWalkAfter = 1u << 27;
 
 // One tile of a multi-segment launch, written by the host: its bytes and its segment.
 // Tiles never span segments; their sizes may differ (smaller tiles near the end of a

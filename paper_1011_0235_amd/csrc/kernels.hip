@@ -828,14 +828,23 @@ __device__ __forceinline__ void publish_decision(const Params &P, Decision *d, u
 // 128-bit arithmetic of change detection and of the collision criterion leaves room for fewer.
 constexpr uint32_t kSeqBatch = 6;
 constexpr uint32_t kSeqBatchExtra = 3;
-static_assert(kSeqBatch <= 8 && kSeqBatchExtra <= 4, "per-chunk flags: bits 0-7 absent, 16-23 over theta, "
+constexpr uint32_t kWalkBatch = 8;   // walk_kernel: registers are no concern there, no collision sums
+static_assert(kSeqBatch <= 8 && kSeqBatchExtra <= 4 && kWalkBatch <= 8, "per-chunk flags: bits 0-7 absent, 16-23 over theta, "
                                                     "24-31 alarms; collision sums for 4 chunks");
 
 // Change detection for value t (Sec. III.B; the measure is our reading): its share of the
 // window departs from its share of the Accumulator by more than pct percentage points,
-// 100 * |mw * N_acc - acc * N_mw| > lim with lim = pct * N_mw * N_acc, in exact 128-bit
-// integers held as (hi, lo) 64-bit halves (never with an empty window or Accumulator; lim is
-// the same for every thread and computed once per chunk).
+// 100 * |mw * N_acc - acc * N_mw| > lim with lim = pct * N_mw * N_acc, exactly (never with an
+// empty window or Accumulator).  The integers go up to 2^128, held as (hi, lo) 64-bit halves;
+// their products take the GPU's quarter-rate 32-bit multiplies (about half a microsecond a
+// chunk for the sequencer).  The walk_kernel launch, which has registers to spare (the
+// counting kernel has not), first takes the test in double precision (share_departs_filtered).  Below 2^53
+// every operand converts exactly, each of the two products and their difference is rounded
+// once (relative 2^-53), and so is 100 x that; the limit is pct x a rounded product of two
+// exact values.  The double comparison is therefore off by at most about 2^-51 of
+// 100 (mw N_acc + acc N_mw) + lim.  It decides when it clears the limit by 2^-49 of that, either
+// way.  Within that band (ties included), and for operands of 2^53 or more, the exact 128-bit
+// test decides.
 struct U128 {
   uint64_t hi, lo;
 };
@@ -855,6 +864,19 @@ __device__ __forceinline__ bool share_departs(uint64_t mwv, uint64_t accv, uint6
   const U128 d = gt_128(x, y) ? sub_128(x, y) : sub_128(y, x);
   const U128 d100 = {d.hi * 100u + __umul64hi(d.lo, 100u), d.lo * 100u};
   return gt_128(d100, lim);
+}
+__device__ __forceinline__ bool share_departs_filtered(uint64_t mwv, uint64_t accv, uint64_t nmw, uint64_t nacc,
+                                                       uint32_t pct) {
+  if (nmw == 0 || nacc == 0) return false;
+  if (((mwv | accv | nmw | nacc) >> 53) == 0) {
+    const double a = (double)mwv * (double)nacc, b = (double)accv * (double)nmw;
+    const double d = 100.0 * __builtin_fabs(a - b);
+    const double l = (double)pct * ((double)nmw * (double)nacc);
+    const double e = 0x1p-49 * (100.0 * (a + b) + l);
+    if (d > l + e) return true;
+    if (d < l - e) return false;
+  }
+  return share_departs(mwv, accv, nmw, nacc, alarm_limit(pct, nmw, nacc));
 }
 
 // The alternative switching criterion (the paper leaves others to future work; our reading):
@@ -892,14 +914,20 @@ __device__ __forceinline__ uint64_t lane_u64(uint64_t v, uint32_t lane) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-template <uint32_t B, bool EXTRA>
-__device__ __forceinline__ void sequence_stream(const Params &P, Ctl &c, StreamDev *st) {
+template <uint32_t B, bool EXTRA, bool WALK = false>
+__device__ __forceinline__ void sequence_stream(const Params &P, Ctl &c, StreamDev *st, uint64_t stop = ~0ull) {
   const uint32_t t = threadIdx.x, lane = lane_id();
   const uint32_t W = P.W, R = P.R, nslot = P.nslot;
   const uint32_t apct = P.alarm_pct;
-  // EXTRA: the instantiation that can also run change detection and the collision criterion
+  // EXTRA: the instantiation that can also run change detection and the collision criterion.
+  // WALK: the walk_kernel launch of a stream whose decisions the host knows (uniform switch):
+  // the decision after chunk j is AHist iff the window holds a byte, whatever the criterion,
+  // so no collision sums are kept; the next batch's entries are loaded while this one is
+  // decided, and the alarm test is filtered in double precision.  The walk ends at chunk
+  // `stop` (the end of its launch's chunks) with no last look: the next launch's walk takes
+  // over from there.
   const bool alarm_on = EXTRA && apct != 0;
-  const bool coll_on = EXTRA && P.criterion != HIST_CRIT_MAXBIN;
+  const bool coll_on = EXTRA && !WALK && P.criterion != HIST_CRIT_MAXBIN;
   uint32_t cb = 0;   // collision limb sums: this batch's buffer (three, so they clear without a barrier)
   const uint64_t *ring = st->ring;
   const uint64_t *ring_n = st->ring_n;
@@ -955,18 +983,44 @@ __device__ __forceinline__ void sequence_stream(const Params &P, Ctl &c, StreamD
         if (q < P.trace_cap) *gmem(&alarm_trace[q]) = (uint8_t)hit;
       }
     };
+    // WALK: the next batch's entries, loaded while this one is decided (valid when `ahead`)
+    uint64_t ne[WALK ? B : 1], neo[WALK ? B : 1], nnv = 0, nnov = 0;
+    bool ahead = false;
     for (;;) {
       // one round trip: this thread's bins of chunks j + b and j + b - W, and in lane b the
       // sizes of those two chunks
-      uint64_t e[B], eo[B];
-#pragma unroll
-      for (uint32_t b = 0; b < B; ++b) {
-        e[b] = ld_agent(&ring[(size_t)wrap(sj, b) * 256u + t]);
-        eo[b] = ld_agent(&ring[(size_t)wrap(so, b) * 256u + t]);
-      }
       const uint32_t bl = lane < B ? lane : 0u;
-      const uint64_t nv = ld_agent(&ring_n[wrap(sj, bl)]);
-      const uint64_t nov = ld_agent(&ring_n[wrap(so, bl)]);
+      uint64_t e[B], eo[B], nv, nov;
+      if (WALK && ahead) {
+#pragma unroll
+        for (uint32_t b = 0; b < B; ++b) {
+          e[b] = ne[WALK ? b : 0];
+          eo[b] = neo[WALK ? b : 0];
+        }
+        nv = nnv;
+        nov = nnov;
+      } else {
+#pragma unroll
+        for (uint32_t b = 0; b < B; ++b) {
+          e[b] = ld_agent(&ring[(size_t)wrap(sj, b) * 256u + t]);
+          eo[b] = ld_agent(&ring[(size_t)wrap(so, b) * 256u + t]);
+        }
+        nv = ld_agent(&ring_n[wrap(sj, bl)]);
+        nov = ld_agent(&ring_n[wrap(so, bl)]);
+      }
+      if (WALK) {
+        // chunks j + B .. j + 2B - 1, as they are now: one that is not complete yet reads as
+        // absent, which ends this walk early (its last look then finds it)
+        const uint32_t sj2 = wrap(sj, B), so2 = wrap(so, B);
+#pragma unroll
+        for (uint32_t b = 0; b < B; ++b) {
+          ne[WALK ? b : 0] = ld_agent(&ring[(size_t)wrap(sj2, b) * 256u + t]);
+          neo[WALK ? b : 0] = ld_agent(&ring[(size_t)wrap(so2, b) * 256u + t]);
+        }
+        nnv = ld_agent(&ring_n[wrap(sj2, bl)]);
+        nnov = ld_agent(&ring_n[wrap(so2, bl)]);
+        ahead = true;
+      }
       uint32_t bad = 0, hot = 0;
       uint64_t m = mw, NN = N;
 #pragma unroll
@@ -1003,7 +1057,8 @@ __device__ __forceinline__ void sequence_stream(const Params &P, Ctl &c, StreamD
       if (coll_on && t == 0)
         for (uint32_t i = 0; i < 4 * 3; ++i) (&c.coll[cprev][0][0])[i] = 0;
       // chunks j .. j + cnt - 1 are there (all four wavefronts saw every entry)
-      const uint32_t cnt = (uint32_t)__builtin_ctz((fl & 0xFFu) | (1u << B));
+      uint32_t cnt = (uint32_t)__builtin_ctz((fl & 0xFFu) | (1u << B));
+      if (WALK) cnt = j >= stop ? 0u : (stop - j < cnt ? (uint32_t)(stop - j) : cnt);
       TL(c, 15, cnt);
       uint32_t alarm = 0;
       // A batch whose decisions are all the uniform table (the budget holds rmax sub-bins for
@@ -1040,13 +1095,16 @@ __device__ __forceinline__ void sequence_stream(const Params &P, Ctl &c, StreamD
         bool coll = false;
         if (coll_on)
           coll = collision_above(from_limbs(c.coll[cb][b][0], c.coll[cb][b][1], c.coll[cb][b][2]), N, P.kappa);
-        const uint32_t mode = switch_mode(P.criterion, ((fl >> (16 + b)) & 1u) != 0, coll);
+        const uint32_t mode = WALK ? (N > 0 ? (uint32_t)HIST_MODE_AHIST : (uint32_t)HIST_MODE_WAVEHIST)
+                                   : switch_mode(P.criterion, ((fl >> (16 + b)) & 1u) != 0, coll);
         const uint32_t d = dj + b >= nslot ? dj + b - nslot : dj + b;
         publish_decision(P, &slots[d], q, mode, kind_lg, word);
         if (alarm_on) {
           sacc += (uint32_t)e[b];
           NA += lane_u64(nv, b) & kSizeMask;
-          if (__ballot(share_departs(mw, sacc, N, NA, alarm_limit(apct, N, NA))) != 0) alarm |= 1u << b;
+          const bool dep = WALK ? share_departs_filtered(mw, sacc, N, NA, apct)
+                                : share_departs(mw, sacc, N, NA, alarm_limit(apct, N, NA));
+          if (__ballot(dep) != 0) alarm |= 1u << b;
         }
       }
       cb = cb == 2 ? 0u : cb + 1u;
@@ -1089,6 +1147,7 @@ __device__ __forceinline__ void sequence_stream(const Params &P, Ctl &c, StreamD
     __syncthreads();
     if (t == 0) st_agent(&st->seq_lock, 0u);
     TL(c, 14, 0);
+    if (WALK && j >= stop) return;
     order_global();
     // look once more: a chunk that arrived while the lock was held
     const uint64_t e = ld_agent(&ring[(size_t)sj * 256u + t]);
@@ -1109,10 +1168,12 @@ __device__ __forceinline__ uint64_t clock_mhz(uint64_t s0, uint64_t w0, uint64_t
 // and rule P (Sec. III.B, Sec. III.C).  With a window of one chunk (W = 1) the decision after
 // chunk k depends on h_k alone, so epilogues of different chunks run independently; with
 // W > 1, or with change detection (which needs the Accumulator in chunk order), the chunks
-// are sequenced (see sequence_stream) -- unless the host knew every decision of the launch
-// and no change detection runs (`known` carries kUnwalked): the decision after chunk k then
-// depends only on which chunks of the window hold bytes, which the host passes in, and the
-// window itself is rebuilt from the ring when it is next read or walked.
+// are sequenced (see sequence_stream) -- unless the host knew every decision of the launch.
+// Then no chunk of the launch waits for the walk.  Without change detection (`known` carries
+// kUnwalked) the decision after chunk k depends only on which chunks of the window hold
+// bytes, which the host passes in, and the window itself is rebuilt from the ring when it is
+// next read.  With change detection (kWalkAfter) the chunk only leaves its entry in the ring,
+// and a one-workgroup walk_kernel launch after the counting launch walks the chunks in order.
 __device__ __forceinline__ void stream_epilogue(const Params &P, Ctl &c, uint32_t sidx, int64_t k, uint32_t h,
                                                 uint64_t bytes, uint32_t known) {
   const uint32_t t = threadIdx.x;
@@ -1181,6 +1242,7 @@ __device__ __forceinline__ void stream_epilogue(const Params &P, Ctl &c, uint32_
     }
     return;
   }
+  if (known & kWalkAfter) return;   // the walk_kernel launch after this one takes it in order
   order_global();     // every entry is in before the CAS below (so a failing CAS means the
   __syncthreads();    // sequencer's last look will find them)
   if (P.alarm_pct || P.criterion != HIST_CRIT_MAXBIN)
@@ -1565,6 +1627,46 @@ __global__ void __launch_bounds__(kBlock) read_probe_kernel(gu32x4 *v, uint64_t 
   if (lane_id() == 0 && acc) atomicAdd(reinterpret_cast<unsigned long long *>(sum), (unsigned long long)acc);
 }
 
+// The in-order walk of a stream whose chunks left it to a later launch (kWalkAfter): one
+// sequencer attempt, as a chunk's finalizer would make, once every chunk of the launch before
+// it is in the ring.  A walk that finds the lock held leaves; the holder's last look then
+// finds these chunks (see sequence_stream).  Change detection is on for such streams, so the
+// walk takes the instantiation that can raise alarms, eight chunks per batch.
+__global__ void __launch_bounds__(kBlock) walk_kernel(const Params P) {
+  extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+  Ctl &c = *reinterpret_cast<Ctl *>(lds);
+#ifdef HISTMI_TIMELINE
+  if (threadIdx.x == 0) c.tl_n = 0;
+#endif
+  // Walk this launch's chunks only, once the walk before it is done: its own push's chunks
+  // are all in the ring, and the next push's walk takes the rest (a walk that took both
+  // would hold up the counting launch queued behind it on its HIP stream).  The walk of the
+  // push before comes first in whatever hardware queue this one shares with it, so the wait
+  // ends; it is bounded all the same, and if it gives up (counted as a decision wait) this
+  // walk falls back to walking whatever it finds, as a chunk's finalizer would.
+  StreamDev *st = P.st;
+  const uint64_t k0 = P.chunk_base;
+  uint64_t stop = k0 + P.nseg;
+  if (threadIdx.x == 0) {
+    uint32_t i = 0;
+    for (; i < P.wait_polls; ++i) {
+      if (__hip_atomic_load(&st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= k0 &&
+          __hip_atomic_load(&st->seq_lock, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)
+        break;
+      __builtin_amdgcn_s_sleep(8);
+    }
+    c.flag = i < P.wait_polls ? 1u : 0u;
+    if (!c.flag) {
+      atomicAdd(&P.diag[1], 1u);
+      __hip_atomic_fetch_add(&st->wait_timeouts, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  __syncthreads();
+  if (!c.flag) stop = ~0ull;
+  __syncthreads();
+  sequence_stream<kWalkBatch, true, true>(P, c, st, stop);
+}
+
 // A window stream's window after launches that did not walk it in order (their chunks left
 // their histograms and sizes in the ring, see stream_epilogue): MW is the sum of the last W
 // chunks' histograms and N their bytes (Sec. III.B), and the walk resumes at chunk n.  One
@@ -1603,6 +1705,11 @@ hipError_t launch_hist(const Params &P, const LaunchShape &sh, hipStream_t s, hi
 
 hipError_t launch_pattern_update(const uint64_t *h, uint32_t S, uint32_t rmax, hist_pattern_t *out, hipStream_t s) {
   hipLaunchKernelGGL(pattern_update_kernel, dim3(1), dim3(kBlock), 0, s, h, S, rmax, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_walk(const Params &P, hipStream_t s) {
+  hipLaunchKernelGGL(walk_kernel, dim3(1), dim3(kBlock), ctl_bytes(), s, P);
   return hipGetLastError();
 }
 

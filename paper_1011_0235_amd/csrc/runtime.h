@@ -18,6 +18,8 @@ namespace histmi {
 hipError_t launch_hist(const Params &P, const LaunchShape &sh, hipStream_t s, hipEvent_t done = nullptr);
 hipError_t launch_pattern_update(const uint64_t *h, uint32_t S, uint32_t rmax, hist_pattern_t *out, hipStream_t s);
 hipError_t launch_read_probe(const void *d_in, uint64_t nvec, uint64_t *d_sum, uint32_t grid, hipStream_t s);
+// the in-order walk of a stream launch's chunks (kWalkAfter), after that launch on `s`
+hipError_t launch_walk(const Params &P, hipStream_t s);
 // a window stream's window (MW, its bytes, the walk's position) rebuilt from its ring at chunk n
 hipError_t launch_window_rebuild(StreamDev *st, uint64_t n, hipStream_t s);
 hipError_t set_kernel_attrs(uint32_t max_dyn_lds);

@@ -104,7 +104,7 @@ def check(hm, chunks, W, alarm_pct, theta=45, S=960, rmax=8, lag=0, hists=None, 
 
 @pytest.mark.parametrize("W,alarm_pct,lag,S,rmax,theta", [
     (1, 20, 0, 960, 8, 45), (2, 10, 1, 8192, 32, 0), (3, 5, 0, 960, 8, 30), (4, 30, 3, 2048, 16, 45),
-    (7, 10, 2, 8192, 32, 45), (32, 5, 4, 300, 64, 20), (32, 3, 0, 960, 8, 45)])
+    (7, 10, 2, 8192, 32, 45), (32, 5, 4, 300, 64, 20), (32, 3, 0, 960, 8, 45), (1, 15, 2, 16384, 64, 0)])
 def test_alarms_match_oracle(hm, W, alarm_pct, lag, S, rmax, theta):
     chunks = mixed(700 + W * 3 + alarm_pct, 160, 80_000)
     ref = check(hm, chunks, W, alarm_pct, theta=theta, S=S, rmax=rmax, lag=lag)
