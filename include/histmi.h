@@ -201,7 +201,12 @@ typedef struct {
  * alarm_pct percentage points, i.e. 100 * |MW(v) * sum Acc - Acc(v) * sum MW| >
  * alarm_pct * sum MW * sum Acc (exact integers; never with an empty MW or Acc; exact while
  * the Accumulator holds fewer than 2^60 bytes).  A stream with alarms on is sequenced in
- * chunk order on the device (as every stream with W > 1 is).
+ * chunk order on the device (as every stream with W > 1 is).  When every decision is a
+ * function of the chunk sizes (a budget of rmax sub-bins for every value, and theta or kappa
+ * 0), the host hands each chunk its decision: a stream with alarms then walks its chunks in
+ * order in a one-workgroup launch queued after each push, and a window stream without
+ * alarms does not walk them at all (its window is summed from its ring of recent
+ * histograms when read).  The results are the same either way.
  *
  * Pushes of one stream must be issued from one host thread at a time, in chunk order, but
  * may go to different HIP streams: a chunk waits on the device for the decision it runs
@@ -452,8 +457,8 @@ typedef struct {
  * 3 = wavefront aggregation (these four for hist_u8 / hist_batch / the server, by kernel),
  * 4 = ordered stream pushes whose chunks wait for the device's decisions (tiles handed out
  * in chunk order), 5 = ordered stream pushes whose decisions the host knows in advance
- * (W = 1, no change detection, a budget of rmax sub-bins for every value and a switching
- * threshold of 0: nothing waits, and each workgroup takes one equal share of the bytes). */
+ * (a budget of rmax sub-bins for every value and a switching threshold of 0: nothing waits,
+ * and each workgroup takes one equal share of the bytes). */
 #define HIST_TUNE_STREAM 4u
 #define HIST_TUNE_STREAM_KNOWN 5u
 hist_status_t hist_tune_set(uint32_t family, const hist_tune_t *t);
