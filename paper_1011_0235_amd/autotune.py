@@ -186,8 +186,8 @@ def main():
     # launch shapes of stream pushes: workgroups per CU x tiles per workgroup (each measured
     # in three interleaved passes of 20 pushes, the median kept).  Two families: pushes whose
     # decisions the host knows (the tuned configuration at lag 0: nothing waits) and pushes
-    # whose chunks wait for the device's decisions (here a moving window of 32 chunks at the
-    # tuned lag: tiles handed out in chunk order).
+    # whose chunks wait for the device's decisions (the paper's threshold of 45 with the
+    # tuned budget at the tuned lag: tiles handed out in chunk order).
     c = cfgs[best]
 
     def shape_sweep(family, make, bpcs, tpws):
@@ -212,8 +212,8 @@ def main():
                 lambda: hm.Stream(W=1, theta_pct=c["theta_pct"], S=c["S"], rmax=c["rmax"], lag=0, trace_cap=0),
                 (1, 2, 3, 4), (1, 2))
     shape_sweep("stream",
-                lambda: hm.Stream(W=32, theta_pct=c["theta_pct"], S=c["S"], rmax=c["rmax"], lag=c["lag"], trace_cap=0),
-                (1, 2, 3, 4), (1, 2, 3, 4))
+                lambda: hm.Stream(W=1, theta_pct=45, S=c["S"], rmax=c["rmax"], lag=c["lag"], trace_cap=0),
+                (1, 2), (2, 4, 6, 8, 12, 16))   # launches that may wait take at most 2 per CU
     del arenas, a0
 
     # ---- Figure 5: degenerate + uniform mixture, d = 0..100 %
