@@ -55,6 +55,7 @@ struct Ctl {
   uint32_t tmp;
   uint64_t tag;            // decision tag of the current segment's stream chunk
   uint32_t sflag[2][kWaves];  // the sequencer's per-wavefront flags, by chunk parity
+  uint64_t ptag[8];        // the sequencer's decision tags of one batch, published together
   uint64_t alarms[3];      // the sequencer's change-detection count, first and last alarm
   uint64_t coll[3][4][3];  // collision criterion: limb sums of sum MW^2 [batch mod 3][chunk][limb]
   // multi-segment launches, double-buffered so that one barrier per step suffices:
@@ -1082,7 +1083,11 @@ __device__ __forceinline__ void sequence_stream(const Params &P, Ctl &c, StreamD
             st_agent(&slots[d].tag, make_tag(j + b + 1, mode, kind_lg));
           }
         }
-      } else
+      } else {
+      // the batch's decisions: a lookup pattern's words are stored as each is decided, and
+      // the tags all go out at the end, after one fence for the whole batch (a tag may be
+      // read only once its words are visible; a fence and a barrier per chunk cost more)
+      bool words = false;
 #pragma unroll
       for (uint32_t b = 0; b < B; ++b) {
         if (b >= cnt) break;
@@ -1098,13 +1103,31 @@ __device__ __forceinline__ void sequence_stream(const Params &P, Ctl &c, StreamD
         const uint32_t mode = WALK ? (N > 0 ? (uint32_t)HIST_MODE_AHIST : (uint32_t)HIST_MODE_WAVEHIST)
                                    : switch_mode(P.criterion, ((fl >> (16 + b)) & 1u) != 0, coll);
         const uint32_t d = dj + b >= nslot ? dj + b - nslot : dj + b;
-        publish_decision(P, &slots[d], q, mode, kind_lg, word);
+        if ((kind_lg >> 8) == KIND_LOOKUP) {
+          st_agent(&slots[d].words[t], word);
+          if (t == 0) {
+            st_agent(&slots[d].S, P.S);
+            st_agent(&slots[d].rmax, P.rmax);
+          }
+          words = true;
+        }
+        if (t == 0) c.ptag[b] = make_tag(q + 1, mode, kind_lg);
         if (alarm_on) {
           sacc += (uint32_t)e[b];
           NA += lane_u64(nv, b) & kSizeMask;
           const bool dep = WALK ? share_departs_filtered(mw, sacc, N, NA, apct)
                                 : share_departs(mw, sacc, N, NA, alarm_limit(apct, N, NA));
           if (__ballot(dep) != 0) alarm |= 1u << b;
+        }
+      }
+      if (words) {                 // (the same in every thread: the kind is the workgroup's)
+        order_global();            // this thread's words before any tag
+        __syncthreads();           // every thread's, before thread 0 stores the tags
+      }
+      if (t == 0)
+        for (uint32_t b = 0; b < cnt; ++b) {
+          const uint32_t d = dj + b >= nslot ? dj + b - nslot : dj + b;
+          st_agent(&slots[d].tag, c.ptag[b]);
         }
       }
       cb = cb == 2 ? 0u : cb + 1u;
