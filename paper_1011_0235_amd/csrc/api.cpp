@@ -898,9 +898,19 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
     // shares are safe too (with the residency cap of launches that wait, set above).
     const bool ahead = !known && m <= st->cfg.lag + 1;
     const bool split = known || ahead;
+    // At lag 0 every chunk waits for the one before it, so the chunks run one at a time: each
+    // is cut into one slice per workgroup, and workgroup w counts slice w of every chunk in
+    // order (plan_striped).  No tile counter sits on that chain, and a slice is loading while
+    // its workgroup waits for the decision.
+    bool striped = !split && st->cfg.lag == 0;
+    if (striped) {
+      const hist_status_t ps = plan_striped(segs, maxg, &mp);
+      if (ps == HIST_EOVERFLOW) striped = false;   // slices too large for a tile record
+      else TRY(ps);
+    }
     if (split) {
       TRY(plan_split(segs, (uint64_t)g_tune[fam].tile_kib * 1024, maxg, &mp));
-    } else {
+    } else if (!striped) {
       // Chunks 0 .. m - 2 - lag of this launch make the decisions of its later chunks.  Where
       // those decisions depend on the data, their tiles are cut small (a 64th of a chunk), so
       // that each of them is spread over many workgroups and done soon after its tiles are
@@ -919,7 +929,7 @@ hist_status_t hist_stream_push_many(hist_stream_t *st, const void *const *h_ptrs
     const bool join = known && st->since_join + m > kMaxChunksPerLaunch;
     TRY(stream_launch_begin(st, s, serialize || join));
     st->since_join = join ? m : st->since_join + m;
-    TRY(run_multi(d, P, mp, copies, s, nullptr, !split, true));
+    TRY(run_multi(d, P, mp, copies, s, nullptr, !split && !striped, true));
     if (walk_after) TRY(dev_err(launch_walk(P, s)));
     stream_launch_end(st, s);
     if (unwalked) st->window_stale = true;

@@ -75,6 +75,62 @@ hist_status_t plan_split(std::vector<SegDesc> &segs, uint64_t tile, uint32_t max
   return HIST_OK;
 }
 
+hist_status_t plan_striped(std::vector<SegDesc> &segs, uint32_t max_grid, MultiPlan *mp) {
+  constexpr uint64_t kQuantum = 16384;
+  const uint32_t n = (uint32_t)segs.size();
+  uint64_t most = 0;   // the most 16 KiB steps in one segment
+  for (uint32_t j = 0; j < n; ++j) {
+    if (segs[j].size > kMaxSegBytes) return HIST_EOVERFLOW;
+    if (segs[j].size && !segs[j].ptr) return HIST_EINVAL;
+    most = std::max<uint64_t>(most, ceil_div(segs[j].size, kQuantum));
+  }
+  const uint32_t G = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(max_grid, most));
+  // segment j is cut into slices of q_j bytes (whole steps), slice w going to workgroup w;
+  // an empty segment's one (empty) tile goes to workgroup 0
+  std::vector<uint64_t> q(n);
+  for (uint32_t j = 0; j < n; ++j) {
+    q[j] = std::max<uint64_t>(kQuantum, ceil_div(ceil_div(segs[j].size, G), kQuantum) * kQuantum);
+    if (q[j] > (1ull << 30)) return HIST_EOVERFLOW;   // a slice must fit a tile record
+    segs[j].tile0 = 0;   // tiles of a segment are not contiguous here (unused by the kernel)
+    segs[j].ntiles = segs[j].size ? (uint32_t)ceil_div(segs[j].size, q[j]) : 1u;
+  }
+  std::vector<TileRec> recs;
+  std::vector<uint32_t> bounds(G + 1, 0);
+  for (uint32_t w = 0; w < G; ++w) {
+    bounds[w] = (uint32_t)recs.size();
+    for (uint32_t j = 0; j < n; ++j) {
+      const uint64_t off = (uint64_t)w * q[j], sz = segs[j].size;
+      if (sz == 0 ? w == 0 : off < sz)
+        recs.push_back(TileRec{reinterpret_cast<uint64_t>(segs[j].ptr) + off,
+                               (uint32_t)(sz ? std::min<uint64_t>(q[j], sz - off) : 0u), j});
+      if (recs.size() >= 0x7FFFFFFFull) return HIST_EOVERFLOW;
+    }
+  }
+  bounds[G] = (uint32_t)recs.size();
+  const uint32_t ntiles = (uint32_t)recs.size();
+  mp->nseg = n;
+  mp->ntiles = ntiles;
+  mp->grid = G;
+  mp->seg_bytes = ((size_t)n * sizeof(SegDesc) + 15) & ~(size_t)15;
+  mp->rec_bytes = (size_t)ntiles * sizeof(TileRec);
+  const size_t bounds_bytes = (((size_t)G + 1) * 4 + 15) & ~(size_t)15;
+  mp->start_off = mp->seg_bytes + mp->rec_bytes + bounds_bytes;
+  mp->blob.assign(mp->start_off + (size_t)G * sizeof(WgStart), 0);
+  std::memcpy(mp->blob.data(), segs.data(), (size_t)n * sizeof(SegDesc));
+  std::memcpy(mp->blob.data() + mp->seg_bytes, recs.data(), mp->rec_bytes);
+  std::memcpy(mp->blob.data() + mp->seg_bytes + mp->rec_bytes, bounds.data(), ((size_t)G + 1) * 4);
+  WgStart *starts = reinterpret_cast<WgStart *>(mp->blob.data() + mp->start_off);
+  for (uint32_t w = 0; w < G; ++w) {
+    starts[w].tile = bounds[w];
+    starts[w].tile_end = bounds[w + 1];
+    if (bounds[w] < bounds[w + 1]) {
+      starts[w].first = recs[bounds[w]];
+      starts[w].seg = segs[recs[bounds[w]].seg];
+    }
+  }
+  return HIST_OK;
+}
+
 hist_status_t plan_multi(std::vector<SegDesc> &segs, uint64_t tile, uint32_t max_grid, MultiPlan *mp,
                          uint32_t n_small, uint64_t small_tile) {
   constexpr uint64_t kQuantum = 16384;

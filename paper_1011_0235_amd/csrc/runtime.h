@@ -156,6 +156,13 @@ hist_status_t plan_multi(std::vector<SegDesc> &segs, uint64_t tile, uint32_t max
 // one workgroup counts in 4-5 us, so a segment's start is charged 64 KiB on the axis the
 // shares are cut from.
 hist_status_t plan_split(std::vector<SegDesc> &segs, uint64_t tile, uint32_t max_grid, MultiPlan *mp);
+// Static launches whose chunks wait for decisions made in the same launch at lag 0: each
+// segment is cut into one slice per workgroup (whole 16 KiB steps), and workgroup w takes
+// slice w of every segment, in segment order.  Every chunk is then counted by the whole
+// grid at once, with no tile counter, and a workgroup's next slice is loading while it waits
+// for that chunk's decision.  Needs every workgroup of the launch resident (the half-CU rule
+// for launches that may wait).  Tiles of one segment are not contiguous; tile0 is unused.
+hist_status_t plan_striped(std::vector<SegDesc> &segs, uint32_t max_grid, MultiPlan *mp);
 // own: a dedicated scratch (already sized, descriptors already on the device) or nullptr;
 // either way one that only launches on `s` use.  done: as for launch_hist.
 hist_status_t run_multi(DevCtx *d, Params &P, const MultiPlan &mp, uint32_t copies, hipStream_t s, Scratch *own,

@@ -92,6 +92,49 @@ static bool multi_case(const std::vector<uint64_t> &sizes, uint32_t maxg, uint64
   return true;
 }
 
+// striped plans: workgroup w holds slice w of every segment, in segment order; each segment is
+// covered exactly once, by slices of whole 16 KiB steps but its last; start records match
+static bool striped_case(const std::vector<uint64_t> &sizes, uint32_t maxg) {
+  std::vector<SegDesc> segs = segments(sizes);
+  MultiPlan mp;
+  if (plan_striped(segs, maxg, &mp) != HIST_OK || mp.grid < 1 || mp.grid > std::max<uint32_t>(1, maxg)) return false;
+  const TileRec *r = reinterpret_cast<const TileRec *>(mp.blob.data() + mp.seg_bytes);
+  const uint32_t *b = reinterpret_cast<const uint32_t *>(mp.blob.data() + mp.seg_bytes + mp.rec_bytes);
+  const SegDesc *sd = reinterpret_cast<const SegDesc *>(mp.blob.data());
+  const WgStart *st = reinterpret_cast<const WgStart *>(mp.blob.data() + mp.start_off);
+  if (b[0] != 0 || b[mp.grid] != mp.ntiles) return false;
+  std::vector<uint64_t> got(segs.size(), 0);
+  std::vector<uint32_t> count(segs.size(), 0);
+  std::vector<std::vector<std::pair<uint64_t, uint64_t>>> parts(segs.size());
+  for (uint32_t w = 0; w < mp.grid; ++w) {
+    if (b[w] > b[w + 1] || st[w].tile != b[w] || st[w].tile_end != b[w + 1]) return false;
+    if (b[w] < b[w + 1] && (std::memcmp(&st[w].first, &r[b[w]], sizeof(TileRec)) != 0 ||
+                            std::memcmp(&st[w].seg, &sd[r[b[w]].seg], sizeof(SegDesc)) != 0))
+      return false;
+    for (uint32_t i = b[w]; i < b[w + 1]; ++i) {
+      if (i > b[w] && r[i].seg <= r[i - 1].seg) return false;   // segment order within a workgroup
+      const uint32_t j = r[i].seg;
+      const uint64_t off = r[i].addr - reinterpret_cast<uint64_t>(segs[j].ptr);
+      if (off + r[i].len > segs[j].size) return false;
+      if (off + r[i].len < segs[j].size && (r[i].len == 0 || r[i].len % 16384)) return false;
+      parts[j].push_back({off, r[i].len});
+      got[j] += r[i].len;
+      ++count[j];
+    }
+  }
+  for (size_t j = 0; j < segs.size(); ++j) {
+    if (got[j] != segs[j].size || count[j] != segs[j].ntiles || sd[j].ntiles != segs[j].ntiles || count[j] < 1)
+      return false;
+    std::sort(parts[j].begin(), parts[j].end());
+    uint64_t at = 0;
+    for (auto &pr : parts[j]) {
+      if (pr.first != at) return false;
+      at += pr.second;
+    }
+  }
+  return true;
+}
+
 // ---- forward progress of launches whose chunks wait for decisions (a model on the real plan)
 //
 // The kernel's rules, as the model takes them: a launch's tiles are handed out in order by
@@ -114,7 +157,7 @@ struct Sim {
 // launch before it); otherwise it mixes them at random.
 static bool simulate(const std::vector<uint64_t> &chunk_bytes, uint64_t tile, uint32_t grid_cap, uint32_t slots,
                      uint32_t lag, bool window, bool later_first, std::mt19937_64 &g, uint32_t n_small = 0,
-                     uint64_t small_tile = 0) {
+                     uint64_t small_tile = 0, bool striped = false) {
   const uint32_t m = (uint32_t)chunk_bytes.size();
   struct L {
     MultiPlan mp;
@@ -123,7 +166,9 @@ static bool simulate(const std::vector<uint64_t> &chunk_bytes, uint64_t tile, ui
   } ln[2];
   for (int l = 0; l < 2; ++l) {
     ln[l].segs = segments(chunk_bytes);
-    if (plan_multi(ln[l].segs, tile, grid_cap, &ln[l].mp, n_small, small_tile) != HIST_OK) return false;
+    if ((striped ? plan_striped(ln[l].segs, grid_cap, &ln[l].mp)
+                 : plan_multi(ln[l].segs, tile, grid_cap, &ln[l].mp, n_small, small_tile)) != HIST_OK)
+      return false;
     ln[l].left = ln[l].mp.grid;
   }
   const uint32_t nchunk = 2 * m;
@@ -142,7 +187,12 @@ static bool simulate(const std::vector<uint64_t> &chunk_bytes, uint64_t tile, ui
     int l;
     uint32_t tile;   // held tile, or ~0u before the first request
     int work;        // remaining work units of the held tile once it runs
+    uint32_t idx;    // striped: its index in its launch (its own range of tiles)
+    uint32_t pos;    // striped: the next tile of that range
   };
+  std::vector<const uint32_t *> bnd(2);
+  for (int l = 0; l < 2; ++l)
+    bnd[l] = reinterpret_cast<const uint32_t *>(ln[l].mp.blob.data() + ln[l].mp.seg_bytes + ln[l].mp.rec_bytes);
   std::vector<WG> res;   // resident workgroups
   uint32_t done_tiles = 0, total = ln[0].mp.ntiles + ln[1].mp.ntiles;
   std::vector<std::vector<uint32_t>> seg_of(2);
@@ -157,8 +207,8 @@ static bool simulate(const std::vector<uint64_t> &chunk_bytes, uint64_t tile, ui
     while (res.size() < slots && (ln[0].started < ln[0].mp.grid || ln[1].started < ln[1].mp.grid)) {
       int l = later_first ? 1 : (int)(g() & 1);
       if (ln[l].started == ln[l].mp.grid) l ^= 1;
-      ++ln[l].started;
-      res.push_back(WG{l, ~0u, 0});
+      const uint32_t idx = ln[l].started++;
+      res.push_back(WG{l, ~0u, 0, idx, striped ? bnd[l][idx] : 0u});
     }
     // some resident workgroup that can move makes its next move (tried in a random order)
     bool moved = false;
@@ -168,13 +218,14 @@ static bool simulate(const std::vector<uint64_t> &chunk_bytes, uint64_t tile, ui
     for (size_t i : order) {
       WG &w = res[i];
       L &x = ln[w.l];
-      if (w.tile == ~0u) {   // ask for a tile
-        if (x.next >= x.mp.ntiles) {
+      if (w.tile == ~0u) {   // ask for a tile (striped: take the next of its own range)
+        const bool out = striped ? w.pos >= bnd[w.l][w.idx + 1] : x.next >= x.mp.ntiles;
+        if (out) {
           res.erase(res.begin() + (long)i);   // out of tiles: leaves, freeing its slot
           moved = true;
           break;
         }
-        w.tile = x.next++;
+        w.tile = striped ? w.pos++ : x.next++;
         w.work = 1 + (int)(g() % 5);
         moved = true;
         break;
@@ -217,7 +268,7 @@ int main() {
     const uint64_t tile = 16384ull * (1 + g() % 128);
     const uint32_t n_small = (uint32_t)(g() % (s.size() + 1));
     if (split_case(s, maxg, tile) == 0 || !multi_case(s, maxg, tile) ||
-        !multi_case(s, maxg, tile, n_small, 16384ull * (1 + g() % 8))) {
+        !multi_case(s, maxg, tile, n_small, 16384ull * (1 + g() % 8)) || !striped_case(s, maxg)) {
       std::printf("invalid plan at case %d\n", it);
       bad = 1;
     }
@@ -248,6 +299,24 @@ int main() {
     std::printf("progress model: %d of 300 runs finished at half capacity; %d of 300 stalled at full\n", ok_half,
                 stalls_full);
     if (stalls_full == 0) bad = 1;   // the model must be able to show the hazard the rule avoids
+    // striped static launches (every workgroup a slice of every chunk, in chunk order) at lag
+    // 0 and 1: with each grid at most half of the slots, both launches always finish
+    int ok_striped = 0;
+    for (int it = 0; it < 300 && !bad; ++it) {
+      const uint32_t slots = 16 + (uint32_t)(gs() % 48), lag = (uint32_t)(gs() % 2);
+      const bool window = (gs() & 1) != 0, later_first = (gs() & 1) != 0;
+      if (simulate(chunks, 16384, slots / 2, slots, lag, window, later_first, gs, 0, 0, true)) ++ok_striped;
+      else {
+        std::printf("stall of a striped launch with half-capacity grids at case %d\n", it);
+        bad = 1;
+      }
+    }
+    std::printf("striped progress model: %d of 300 runs finished at half capacity\n", ok_striped);
+  }
+  if (!striped_case(std::vector<uint64_t>(66, 4u << 20), 512) || !striped_case({0, 5, 0}, 3) ||
+      !striped_case({1u << 20}, 1) || !striped_case(std::vector<uint64_t>(3, 0), 7)) {
+    std::printf("invalid striped plan\n");
+    bad = 1;
   }
   std::printf(bad ? "FAILED\n" : "all plans valid\n");
   return bad;
