@@ -244,7 +244,9 @@ typedef struct {
 } hist_stream_snapshot_t;
 
 /* Synchronous: waits for `stream` and for this stream's launches on any HIP stream, then
- * copies the state.  h_mode_trace (uint8[trace_len])
+ * copies the state.  A window stream whose pushes did not walk the window (see
+ * hist_stream_create) first has it summed from its ring by a one-workgroup launch on
+ * `stream`, which this call also waits for.  h_mode_trace (uint8[trace_len])
  * and h_pattern_trace (uint32[trace_len][256]) may be NULL; entry k holds the mode / pattern
  * words chunk k ran with (k < trace_cap).
  * Returns HIST_ETIMEDOUT, with everything still copied, when a bounded wait of one of the
