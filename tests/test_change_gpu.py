@@ -162,6 +162,50 @@ def test_full_size_stream_with_alarms(hm):
     st.close()
 
 
+@pytest.mark.parametrize("W,alarm_pct,lag", [(5, 10, 2), (1, 15, 0), (32, 4, 7)])
+def test_alarms_read_between_pushes(hm, W, alarm_pct, lag):
+    # With the uniform switch each push's chunks are walked in order by a launch of its own
+    # after the push, which stops at the push's last chunk; the next push's walk goes on from
+    # there.  Reads after pushes of one, a few and many chunks (on two HIP streams, runs of
+    # empty chunks among them) must each give the oracle's state after that many chunks:
+    # alarms and their trace, the window, the Accumulator.
+    chunks = attack_stream(13 + W, 120, 1 << 15, 40, 70, 0.35, 200)
+    for k in range(0, len(chunks), 17):
+        chunks[k] = np.zeros(0, dtype=np.uint8)
+    S, rmax = 8192, 32
+    ds = [dev(c) if c.size else None for c in chunks]
+    bufs = [(int(x.data_ptr()) if x is not None else 0, c.size) for x, c in zip(ds, chunks)]
+    outs = torch.full((len(chunks), 256), -1, dtype=torch.int32, device="cuda")
+    st = hm.Stream(W=W, theta_pct=0, S=S, rmax=rmax, lag=lag, trace_cap=len(chunks), alarm_pct=alarm_pct)
+    hs = [torch.cuda.Stream(), torch.cuda.Stream()]
+    torch.cuda.synchronize()
+    n = 0
+    for i, m in enumerate([1, 7, 30, 2, 45, 35]):
+        st.push_many(bufs[n:n + m], d_out=outs[n:n + m], stream=hs[i & 1])
+        n += m
+        if i % 2 == 1:
+            ref = O.stream_reference(chunks[:n], W=W, theta_pct=0, S=S, rmax=rmax, lag=lag, alarm_pct=alarm_pct)
+            snap, modes, _ = st.read(n, stream=hs[i & 1])
+            alarms = st.read_alarms(n, stream=hs[i & 1])
+            tag = (W, alarm_pct, lag, n)
+            assert int(snap.chunks) == n, tag
+            assert [int(x) for x in snap.acc] == ref["acc"], tag
+            assert [int(x) for x in snap.mw] == ref["mw"], tag
+            assert [int(m_) for m_ in modes] == ref["modes"], tag
+            assert [int(a) for a in alarms] == ref["alarms"], tag
+            hits = [k for k, a in enumerate(ref["alarms"]) if a]
+            assert int(snap.alarms) == len(hits), tag
+            assert int(snap.first_alarm) == (hits[0] + 1 if hits else 0), tag
+            assert int(snap.last_alarm) == (hits[-1] + 1 if hits else 0), tag
+    assert n == len(chunks)
+    got = outs.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+    assert np.array_equal(got, ref["hists"].astype(np.int64))
+    assert 0 < sum(ref["alarms"]) < len(chunks)
+    d = hm.diag()
+    assert d.invalid_patterns == 0 and d.wait_timeouts == 0 and d.merge_timeouts == 0
+    st.close()
+
+
 def test_read_alarms_needs_alarms_on(hm):
     st = hm.Stream(W=4, theta_pct=45, S=960, rmax=8, lag=0, trace_cap=8)
     with pytest.raises(hm.HistError):
