@@ -1083,6 +1083,47 @@ __device__ __forceinline__ void sequence_stream(const Params &P, Ctl &c, StreamD
             st_agent(&slots[d].tag, make_tag(j + b + 1, mode, kind_lg));
           }
         }
+      } else if (WALK) {
+        // The walk after a push (decisions from the host, alarms on): every running sum of
+        // the batch first (cheap adds), then the alarm tests, which do not depend on one
+        // another.  With one wavefront per SIMD, a test per step would wait out its own
+        // latency before the next could start.
+        uint64_t wm[B], wa[B], wn[B], wna[B];
+        {
+          uint64_t m = mw, a = sacc, n = N, na = NA;
+#pragma unroll
+          for (uint32_t b = 0; b < B; ++b) {
+            const bool old = j + b >= W;
+            const uint64_t nb = lane_u64(nv, b) & kSizeMask;
+            m += (uint64_t)(uint32_t)e[b] - (old ? (uint64_t)(uint32_t)eo[b] : 0u);
+            n += nb - (old ? (lane_u64(nov, b) & kSizeMask) : 0u);
+            a += (uint32_t)e[b];
+            na += nb;
+            wm[b] = m;
+            wa[b] = a;
+            wn[b] = n;
+            wna[b] = na;
+          }
+        }
+#pragma unroll
+        for (uint32_t b = 0; b < B; ++b) {
+          const bool dep = b < cnt && share_departs_filtered(wm[b], wa[b], wn[b], wna[b], apct);
+          if (__ballot(dep) != 0) alarm |= 1u << b;
+        }
+        const uint32_t kind_lg = ((uint32_t)KIND_UNIFORM << 8) | (uint32_t)__builtin_ctz(P.rmax);
+#pragma unroll
+        for (uint32_t b = 0; b < B; ++b)
+          if (b < cnt) {
+            mw = wm[b];
+            sacc = wa[b];
+            N = wn[b];
+            NA = wna[b];
+            if (t == 0) {
+              const uint32_t d = dj + b >= nslot ? dj + b - nslot : dj + b;
+              const uint32_t mode = wn[b] > 0 ? (uint32_t)HIST_MODE_AHIST : (uint32_t)HIST_MODE_WAVEHIST;
+              st_agent(&slots[d].tag, make_tag(j + b + 1, mode, kind_lg));
+            }
+          }
       } else {
       // the batch's decisions: a lookup pattern's words are stored as each is decided, and
       // the tags all go out at the end, after one fence for the whole batch (a tag may be
