@@ -544,6 +544,8 @@ def bench_served(hm, G, O, torch, dev, stream, theta, S, rmax, rates=(1000, 1000
                "served_GBps": round(nbytes / span / 1e9, 2),
                "p50_us": round(float(np.percentile(lat, 50)), 1), "p99_us": round(float(np.percentile(lat, 99)), 1),
                "batches": int(stats.batches), "max_concurrent_batches": int(stats.max_concurrent_batches),
+               "scheduler_max_launch_us": round(stats.max_launch_ns / 1e3, 1),
+               "scheduler_max_query_us": round(stats.max_query_ns / 1e3, 1),
                "parity_exact": ok}
         if paced:
             row["offered_GBps"] = round(sum(r.size for r in reqs) / duration / 1e9, 2)

@@ -374,12 +374,17 @@ typedef struct {
 typedef struct {
     uint64_t submitted, completed, canceled, batches, bytes_done;
     uint64_t max_inflight_bytes, max_inflight_requests, max_concurrent_batches;
+    uint64_t max_launch_ns;      /* longest host call that queued one micro-batch (HIP launch path) */
+    uint64_t max_query_ns;       /* longest host call that asked whether a micro-batch had finished */
 } hist_server_stats_t;
 
 /* Synchronous.  Starts the scheduler thread on the current device.  The scheduler spins on
  * one host core while micro-batches are in flight and for 2 ms after its last activity (a
  * timed sleep would round up to the OS timer slack and set the latency floor); idle beyond
- * that it blocks until the next submission. */
+ * that it blocks until the next submission.  Everything a micro-batch of up to
+ * min(max_batch, max_slots, 1024) requests needs is allocated here, per slot: device scratch
+ * and a pinned host buffer of descriptors that the kernel reads in place, so the scheduler's
+ * launches neither allocate nor copy (a larger batch grows its slot's scratch on first use). */
 hist_status_t hist_server_create(hist_server_t **sv, const hist_server_config_t *cfg);
 
 /* Thread-safe, non-blocking.  d_buf: n device bytes (any alignment) that stay unchanged until

@@ -100,7 +100,8 @@ class ServerResult(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("canceled", ctypes.c_uint64),
                 ("batches", ctypes.c_uint64), ("bytes_done", ctypes.c_uint64), ("max_inflight_bytes", ctypes.c_uint64),
-                ("max_inflight_requests", ctypes.c_uint64), ("max_concurrent_batches", ctypes.c_uint64)]
+                ("max_inflight_requests", ctypes.c_uint64), ("max_concurrent_batches", ctypes.c_uint64),
+                ("max_launch_ns", ctypes.c_uint64), ("max_query_ns", ctypes.c_uint64)]
 
 
 # (name, restype, argtypes) of every symbol include/histmi.h declares

@@ -180,6 +180,36 @@ hist_status_t upload_desc(Scratch *sc, const void *host, size_t bytes, hipStream
   return HIST_OK;
 }
 
+hist_status_t reserve_scratch(Scratch *sc, size_t nseg, uint32_t copies, size_t desc_bytes, hipStream_t s) {
+  TRY(alloc_scratch(sc, nseg, copies, 0, s));
+  const size_t cap = std::max<size_t>(desc_bytes, 1 << 16);   // upload_desc's smallest buffers
+  for (int k = 0; k < 2; ++k) {
+    if (!sc->ev[k]) TRY_HIP(hipEventCreateWithFlags(&sc->ev[k], hipEventDisableTiming));
+    if (sc->stage_cap[k] < cap) {
+      if (sc->ev[k]) TRY_HIP(hipEventSynchronize(sc->ev[k]));
+      if (sc->stage[k]) TRY_HIP(hipHostFree(sc->stage[k]));
+      sc->stage[k] = nullptr;
+      sc->stage_cap[k] = 0;
+      if (hipHostMalloc(reinterpret_cast<void **>(&sc->stage[k]), cap, hipHostMallocDefault) != hipSuccess)
+        return HIST_ENOMEM;
+      sc->stage_cap[k] = cap;
+    }
+  }
+  for (Scratch::Cached &e : sc->cache) {
+    if (e.cap >= cap) continue;
+    if (e.dev) {
+      TRY_HIP(hipStreamSynchronize(s));   // launches still reading the old buffer are done
+      TRY_HIP(hipFree(e.dev));
+    }
+    e.dev = nullptr;
+    e.cap = 0;
+    e.blob.clear();
+    if (hipMalloc(&e.dev, cap) != hipSuccess) return HIST_ENOMEM;
+    e.cap = cap;
+  }
+  return HIST_OK;
+}
+
 bool pattern_ok(const hist_pattern_t *p) {
   const uint32_t S = p->total_S, rmax = p->rmax;
   if (!is_pow2(rmax) || rmax > HIST_RMAX_MAX || S < 1 || S > HIST_S_MAX) return false;
@@ -320,15 +350,16 @@ hist_status_t run_single(DevCtx *d, Params &P, hipStream_t s, Scratch *own, hipE
 }
 
 hist_status_t run_multi(DevCtx *d, Params &P, const MultiPlan &mp, uint32_t copies, hipStream_t s, Scratch *own,
-                        bool dynamic, bool upload, hipEvent_t done) {
+                        bool dynamic, bool upload, hipEvent_t done, const uint8_t *in_place) {
   Scratch *sc = own;
   if (!sc) TRY(get_scratch(d, s, mp.nseg, copies, 0, &sc));
-  else TRY(alloc_scratch(sc, mp.nseg, copies, upload ? 0 : mp.blob.size(), s));
-  if (upload) TRY(upload_desc(sc, mp.blob.data(), mp.blob.size(), s));
-  P.segs = reinterpret_cast<const SegDesc *>(sc->desc);
-  P.recs = reinterpret_cast<const TileRec *>(sc->desc + mp.seg_bytes);
-  P.bounds = reinterpret_cast<const uint32_t *>(sc->desc + mp.seg_bytes + mp.rec_bytes);
-  P.starts = mp.start_off ? reinterpret_cast<const WgStart *>(sc->desc + mp.start_off) : nullptr;
+  else TRY(alloc_scratch(sc, mp.nseg, copies, (upload || in_place) ? 0 : mp.blob.size(), s));
+  if (upload && !in_place) TRY(upload_desc(sc, mp.blob.data(), mp.blob.size(), s));
+  const uint8_t *desc = in_place ? in_place : sc->desc;
+  P.segs = reinterpret_cast<const SegDesc *>(desc);
+  P.recs = reinterpret_cast<const TileRec *>(desc + mp.seg_bytes);
+  P.bounds = reinterpret_cast<const uint32_t *>(desc + mp.seg_bytes + mp.rec_bytes);
+  P.starts = mp.start_off ? reinterpret_cast<const WgStart *>(desc + mp.start_off) : nullptr;
   P.nseg = mp.nseg;
   P.single = 0;
   P.ntiles = mp.ntiles;

@@ -9,6 +9,17 @@
 namespace histmi {
 namespace rt {
 
+// Tiles: each ends at its segment's end (n), at `tile` bytes (at most bytes / tile in all), or
+// where a workgroup's share ends (each share end cuts at most once, since the cut moves past
+// it): n + G + bytes / tile.  The grid is at most max_grid.
+size_t plan_split_blob_max(uint64_t nseg, uint64_t bytes, uint64_t tile, uint32_t max_grid) {
+  tile = std::max<uint64_t>(16384, std::min<uint64_t>(tile, 1ull << 30));
+  const uint64_t G = std::max<uint32_t>(1, max_grid);
+  const uint64_t recs = std::max<uint64_t>(nseg, 1) + G + bytes / tile + 1;
+  return ((nseg * sizeof(SegDesc) + 15) & ~(uint64_t)15) + recs * sizeof(TileRec) + (((G + 1) * 4 + 15) & ~(uint64_t)15) +
+         G * sizeof(WgStart);
+}
+
 hist_status_t plan_split(std::vector<SegDesc> &segs, uint64_t tile, uint32_t max_grid, MultiPlan *mp) {
   constexpr uint64_t kQuantum = 16384, kSwitchBytes = 65536;
   const uint32_t n = (uint32_t)segs.size();

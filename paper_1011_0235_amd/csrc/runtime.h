@@ -118,6 +118,10 @@ hist_status_t get_dev(DevCtx **out);
 hist_status_t alloc_scratch(Scratch *sc, size_t nseg, uint32_t copies, size_t desc_bytes, hipStream_t s);
 hist_status_t get_scratch(DevCtx *d, hipStream_t s, size_t nseg, uint32_t copies, size_t desc_bytes, Scratch **out);
 hist_status_t upload_desc(Scratch *sc, const void *host, size_t bytes, hipStream_t s);
+// Allocate now everything that launches of up to nseg segments with up to `copies` partial
+// copies, and descriptor sets of up to desc_bytes uploaded through upload_desc, will use, so
+// that those launches make no allocation (whose device-wide waits would stall the caller).
+hist_status_t reserve_scratch(Scratch *sc, size_t nseg, uint32_t copies, size_t desc_bytes, hipStream_t s);
 
 bool pattern_ok(const hist_pattern_t *p);
 void init_params(Params *P);
@@ -156,6 +160,9 @@ hist_status_t plan_multi(std::vector<SegDesc> &segs, uint64_t tile, uint32_t max
 // one workgroup counts in 4-5 us, so a segment's start is charged 64 KiB on the axis the
 // shares are cut from.
 hist_status_t plan_split(std::vector<SegDesc> &segs, uint64_t tile, uint32_t max_grid, MultiPlan *mp);
+// An upper bound on plan_split's descriptor bytes for at most nseg segments holding at most
+// `bytes` bytes in all (what a caller reserves so that later launches allocate nothing).
+size_t plan_split_blob_max(uint64_t nseg, uint64_t bytes, uint64_t tile, uint32_t max_grid);
 // Static launches whose chunks wait for decisions made in the same launch at lag 0: each
 // segment is cut into one slice per workgroup (whole 16 KiB steps), and workgroup w takes
 // slice w of every segment, in segment order.  Every chunk is then counted by the whole
@@ -164,9 +171,11 @@ hist_status_t plan_split(std::vector<SegDesc> &segs, uint64_t tile, uint32_t max
 // for launches that may wait).  Tiles of one segment are not contiguous; tile0 is unused.
 hist_status_t plan_striped(std::vector<SegDesc> &segs, uint32_t max_grid, MultiPlan *mp);
 // own: a dedicated scratch (already sized, descriptors already on the device) or nullptr;
-// either way one that only launches on `s` use.  done: as for launch_hist.
+// either way one that only launches on `s` use.  done: as for launch_hist.  in_place: a
+// device-visible copy of mp.blob that the launch reads where it is (no upload), which the
+// caller keeps unchanged until the launch has finished; nullptr: the scratch's descriptors.
 hist_status_t run_multi(DevCtx *d, Params &P, const MultiPlan &mp, uint32_t copies, hipStream_t s, Scratch *own,
-                        bool dynamic, bool upload, hipEvent_t done = nullptr);
+                        bool dynamic, bool upload, hipEvent_t done = nullptr, const uint8_t *in_place = nullptr);
 
 // Device-resident stream states: allocation and release.
 struct StreamAlloc {

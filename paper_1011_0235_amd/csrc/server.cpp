@@ -64,6 +64,13 @@ struct Slot {
   uint32_t seq = 0;
   bool by_word = false;
   uint64_t t_check = 0;       // last time a wait on the word asked the HIP stream for errors
+  // a batch's descriptors, in pinned coherent host memory that its kernel reads in place
+  // (rewritten only once the slot's previous launch has finished, since a slot runs one
+  // launch at a time): no copy goes through the HIP runtime's copy path, whose first use of
+  // a kind can hold the launching thread for milliseconds
+  uint8_t *desc_host = nullptr;
+  const uint8_t *desc_dev = nullptr;
+  size_t desc_cap = 0;
   bool busy = false;
   int hs = 0;
   uint64_t bytes = 0;
@@ -73,7 +80,11 @@ struct Slot {
 constexpr size_t kQueueCap = 1u << 20;      // not-yet-admitted requests
 constexpr size_t kFinishedCap = 1u << 20;   // finished requests kept for poll / wait
 constexpr uint64_t kIdleSpinNs = 2000000;   // the scheduler spins this long after its last activity
-constexpr uint64_t kCheckNs = 100000;       // a launch not done yet: its HIP stream is asked for errors this often
+constexpr uint64_t kCheckNs = 100000;
+// each slot's scratch is reserved at creation for micro-batches of up to this many requests,
+// with descriptor sets of up to kReserveDescBytes (a larger batch grows it on first use)
+constexpr uint64_t kReserveSegs = 1024;
+constexpr size_t kReserveDescBytes = size_t(4) << 20;       // a launch not done yet: its HIP stream is asked for errors this often
 
 inline void cpu_relax() { __builtin_ia32_pause(); }
 
@@ -95,6 +106,8 @@ struct hist_server {
   uint64_t next_ticket = 1;
   std::atomic<uint64_t> submissions{0};     // lets the spinning scheduler notice work without the lock
   std::atomic<bool> stopping{false};
+  // longest host calls of the scheduler (written by it alone, read by hist_server_stats)
+  std::atomic<uint64_t> max_launch_ns{0}, max_query_ns{0};
   uint64_t inflight_bytes = 0, inflight_reqs = 0;
   uint32_t busy_slots = 0;
   bool stop = false;
@@ -104,6 +117,7 @@ struct hist_server {
   void run();
   bool launch(Slot &sl, std::vector<uint64_t> &batch);
   hipError_t query(Slot &sl);
+  hipError_t timed_query(Slot &sl);
   void finish(uint64_t tk, int32_t status, uint64_t t);
 };
 
@@ -121,6 +135,11 @@ void hist_server::finish(uint64_t tk, int32_t status, uint64_t t) {
     reqs.erase(finished.front());   // no-op if poll or wait already retired it
     finished.pop_front();
   }
+}
+
+// Partial copies per segment of a micro-batch of several requests.
+static uint32_t multi_copies() {
+  return std::min<uint32_t>(64, pow2ceil32(std::max<uint32_t>(1, g_tune[KIND_UNIFORM].copies)));
 }
 
 // Launch one micro-batch on slot `sl` (called without the lock; the requests are admitted).
@@ -159,9 +178,15 @@ bool hist_server::launch(Slot &sl, std::vector<uint64_t> &batch) {
   const uint32_t maxg = (uint32_t)d->cus * blocks_per_cu(fam, lds_bytes(P));
   MultiPlan mp;
   if (plan_split(segs, tile, maxg, &mp) != HIST_OK) return false;
-  const uint32_t copies = std::min<uint32_t>(64, pow2ceil32(std::max<uint32_t>(1, g_tune[fam].copies)));
-  // sl.ev completes with the launch (the slot's scratch only ever serves this HIP stream)
-  return run_multi(d, P, mp, copies, s, &sl.sc, false, true, sl.ev) == HIST_OK;
+  const uint32_t copies = multi_copies();
+  // sl.ev completes with the launch (the slot's scratch only ever serves this HIP stream);
+  // descriptors beyond the slot's host buffer (a batch larger than reserved) are uploaded
+  const uint8_t *in_place = nullptr;
+  if (mp.blob.size() <= sl.desc_cap) {
+    std::memcpy(sl.desc_host, mp.blob.data(), mp.blob.size());
+    in_place = sl.desc_dev;
+  }
+  return run_multi(d, P, mp, copies, s, &sl.sc, false, true, sl.ev, in_place) == HIST_OK;
 }
 
 // State of the slot's launch: hipSuccess once done, hipErrorNotReady while it runs, or the
@@ -181,6 +206,15 @@ hipError_t hist_server::query(Slot &sl) {
   return e == hipSuccess ? hipErrorUnknown : e;
 }
 
+// query() with its duration kept in max_query_ns (scheduler thread only).
+hipError_t hist_server::timed_query(Slot &sl) {
+  const uint64_t t0 = now_ns();
+  const hipError_t e = query(sl);
+  const uint64_t dt = now_ns() - t0;
+  if (dt > max_query_ns.load(std::memory_order_relaxed)) max_query_ns.store(dt, std::memory_order_relaxed);
+  return e;
+}
+
 void hist_server::run() {
   (void)hipSetDevice(dev);
   std::unique_lock<std::mutex> lk(mu);
@@ -189,7 +223,7 @@ void hist_server::run() {
     // 1. retire finished micro-batches
     for (Slot &sl : slots) {
       if (!sl.busy) continue;
-      const hipError_t e = query(sl);
+      const hipError_t e = timed_query(sl);
       if (e == hipErrorNotReady) continue;
       const uint64_t t = now_ns();
       for (uint64_t tk : sl.tickets) finish(tk, e == hipSuccess ? HIST_OK : HIST_EDEVICE, t);
@@ -226,6 +260,8 @@ void hist_server::run() {
       last_active = t;
       lk.unlock();
       const bool ok = launch(sl, batch);
+      const uint64_t dl = now_ns() - t;
+      if (dl > max_launch_ns.load(std::memory_order_relaxed)) max_launch_ns.store(dl, std::memory_order_relaxed);
       lk.lock();
       sl.tickets = batch;
       if (!ok) {
@@ -255,7 +291,7 @@ void hist_server::run() {
     for (uint32_t spins = 0;; ++spins) {
       bool done = false;
       for (Slot &sl : slots)
-        if (sl.busy && query(sl) != hipErrorNotReady) {
+        if (sl.busy && timed_query(sl) != hipErrorNotReady) {
           done = true;
           break;
         }
@@ -320,6 +356,49 @@ hist_status_t hist_server_create(hist_server_t **out, const hist_server_config_t
       return HIST_EDEVICE;
     }
   }
+  // Reserve every slot's scratch for the largest micro-batch the server launches, and a host
+  // buffer for its largest descriptor set, so that the scheduler's launches allocate and copy
+  // nothing: a buffer grown in the launch path costs a hipFree and a hipMalloc, which wait
+  // for the whole device and held up every slot's completion and admission for milliseconds.
+  {
+    Params P;
+    init_params(&P);
+    stream_layout(c.S, c.rmax, (hist_mode_t)c.mode, &P);
+    const uint32_t maxg = (uint32_t)d->cus * blocks_per_cu(KIND_UNIFORM, lds_bytes(P));
+    const uint64_t nseg = std::min<uint64_t>({(uint64_t)c.max_batch, (uint64_t)c.max_slots, kReserveSegs});
+    const uint32_t copies = std::max<uint32_t>(g_single_copies, multi_copies());
+    const uint64_t bytes = std::min<uint64_t>(c.hbm_budget_bytes, nseg * kMaxSegBytes);
+    const size_t desc = std::max<size_t>(
+        4096, std::min<size_t>(plan_split_blob_max(nseg, bytes, (uint64_t)g_tune[KIND_UNIFORM].tile_kib * 1024, maxg),
+                               kReserveDescBytes));
+    for (Slot &sl : sv->slots) {
+      const hist_status_t rs = reserve_scratch(&sl.sc, nseg, copies, 0, sv->hs[sl.hs]);
+      if (rs != HIST_OK) {
+        hist_server_destroy(sv);
+        return rs;
+      }
+      void *hp = nullptr, *dp = nullptr;
+      if (hipHostMalloc(&hp, desc, hipHostMallocCoherent) != hipSuccess) {
+        hist_server_destroy(sv);
+        return HIST_ENOMEM;
+      }
+      sl.desc_host = static_cast<uint8_t *>(hp);
+      if (hipHostGetDevicePointer(&dp, hp, 0) != hipSuccess) {
+        hist_server_destroy(sv);
+        return HIST_EDEVICE;
+      }
+      sl.desc_dev = static_cast<const uint8_t *>(dp);
+      sl.desc_cap = desc;
+    }
+    for (hipStream_t h : sv->hs)
+      if (hipStreamSynchronize(h) != hipSuccess) {
+        hist_server_destroy(sv);
+        return HIST_EDEVICE;
+      }
+  }
+  // every ticket the server can hold at once (queued, in flight, finished and not yet
+  // retired) fits without a rehash, which would hold the lock for milliseconds at 10^5 entries
+  sv->reqs.reserve(kQueueCap + kFinishedCap + c.max_slots + 1);
   sv->th = std::thread([sv] { sv->run(); });
   *out = sv;
   return HIST_OK;
@@ -416,6 +495,8 @@ hist_status_t hist_server_stats(hist_server_t *sv, hist_server_stats_t *st) {
   if (!sv || !st) return HIST_EINVAL;
   std::lock_guard<std::mutex> lk(sv->mu);
   *st = sv->stats;
+  st->max_launch_ns = sv->max_launch_ns.load(std::memory_order_relaxed);
+  st->max_query_ns = sv->max_query_ns.load(std::memory_order_relaxed);
   return HIST_OK;
 }
 
@@ -442,6 +523,7 @@ hist_status_t hist_server_destroy(hist_server_t *sv) {
     if (h) (void)hipStreamSynchronize(h);
   for (Slot &sl : sv->slots) {
     free_scratch(&sl.sc);
+    if (sl.desc_host) (void)hipHostFree(sl.desc_host);
     if (sl.ev) (void)hipEventDestroy(sl.ev);
   }
   for (hipStream_t h : sv->hs)

@@ -47,6 +47,9 @@ static double split_case(const std::vector<uint64_t> &sizes, uint32_t maxg, uint
   std::vector<SegDesc> segs = segments(sizes);
   MultiPlan mp;
   if (plan_split(segs, tile, maxg, &mp) != HIST_OK || !covered(segs, mp, tile)) return 0;
+  uint64_t total = 0;
+  for (uint64_t x : sizes) total += x;
+  if (mp.blob.size() > plan_split_blob_max(sizes.size(), total, tile, maxg)) return 0;
   const TileRec *r = reinterpret_cast<const TileRec *>(mp.blob.data() + mp.seg_bytes);
   const uint32_t *b = reinterpret_cast<const uint32_t *>(mp.blob.data() + mp.seg_bytes + mp.rec_bytes);
   if (mp.grid < 1 || mp.grid > maxg || b[0] != 0 || b[mp.grid] != mp.ntiles) return 0;

@@ -99,6 +99,8 @@ def test_budget_and_slots_bound_admission(hm):
     assert s.completed == 200
     assert s.max_inflight_bytes <= 3 << 20 and s.max_inflight_requests <= 5
     assert s.max_concurrent_batches >= 1
+    # the scheduler's longest launch and completion query were timed (and are plausible)
+    assert 0 < s.max_launch_ns < 10 ** 9 and 0 < s.max_query_ns < 10 ** 9
     host = pool.cpu().numpy()
     o = outs.cpu().numpy().astype(np.int64)
     for i in (0, 1, 57, 199):
