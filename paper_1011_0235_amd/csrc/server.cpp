@@ -259,8 +259,9 @@ void hist_server::run() {
       stats.max_concurrent_batches = std::max<uint64_t>(stats.max_concurrent_batches, busy_slots);
       last_active = t;
       lk.unlock();
+      const uint64_t tl = now_ns();
       const bool ok = launch(sl, batch);
-      const uint64_t dl = now_ns() - t;
+      const uint64_t dl = now_ns() - tl;
       if (dl > max_launch_ns.load(std::memory_order_relaxed)) max_launch_ns.store(dl, std::memory_order_relaxed);
       lk.lock();
       sl.tickets = batch;
