@@ -486,7 +486,8 @@ class PoolOracle:
 def bench_served(hm, G, O, torch, dev, stream, theta, S, rmax, rates=(1000, 10000, 50000), duration=2.0):
     """Open-loop Poisson arrivals (sizes log-uniform 4 KiB..64 MiB, 64 stream ids, slices of
     per-stream drifting pools) into the continuous-batching server with the tuned switch;
-    latency from scheduled arrival to host-observed completion.  Then every request of the
+    latency from scheduled arrival to host-observed completion, beside the plain kernel taking
+    the same arrivals one synchronous hist_u8 call at a time.  Then every request of the
     largest set submitted at once (offered load unbounded): the server's capacity.  Every
     request's histogram and every stream id's running histogram are checked against the
     oracle."""
@@ -553,6 +554,20 @@ def bench_served(hm, G, O, torch, dev, stream, theta, S, rmax, rates=(1000, 1000
             ms_fifo = timed(torch, stream, lambda: [hm.hist_u8(ptrs[i], outs[i], stream=stream, n=reqs[i].size)
                                                     for i in range(len(reqs))], 1)
             row["fifo_hist_u8_GBps"] = round(sum(r.size for r in reqs) / (ms_fifo * 1e-3) / 1e9, 1)
+            # the plain kernel as a server: one thread takes the same arrivals in order, calls
+            # hist_u8 for each at its arrival (or at once when behind) and synchronizes; latency
+            # from scheduled arrival to the synchronize's return, queueing included
+            lat_plain = np.empty(len(reqs))
+            t0 = time.perf_counter_ns()
+            for i, r in enumerate(reqs):
+                due = t0 + int(r.t_arrival * 1e9)
+                while time.perf_counter_ns() < due:
+                    pass
+                hm.hist_u8(ptrs[i], outs[i], stream=stream, n=r.size)
+                stream.synchronize()
+                lat_plain[i] = (time.perf_counter_ns() - due) / 1e3
+            row["plain_sync_p50_us"] = round(float(np.percentile(lat_plain, 50)), 1)
+            row["plain_sync_p99_us"] = round(float(np.percentile(lat_plain, 99)), 1)
             out["%d_per_s" % rate] = row
         else:
             row["offered"] = "all %d requests of the %d/s set at once" % (len(reqs), rate)
