@@ -360,6 +360,9 @@ typedef struct {
     uint32_t theta_pct;         /* critical degeneracy, percent */
     uint32_t S;                 /* sub-histogram budget for rule P (256..HIST_S_MAX) */
     uint32_t rmax;              /* most sub-bins per value (power of two <= HIST_RMAX_MAX) */
+    uint32_t idle_spin_us;      /* the scheduler spins this long after its last activity before it
+                                   blocks (0: 20000; at most 10^7).  A submission to a blocked
+                                   scheduler waits 10-25 us for its wake-up; spinning costs a core */
 } hist_server_config_t;
 
 typedef struct {
@@ -379,9 +382,9 @@ typedef struct {
 } hist_server_stats_t;
 
 /* Synchronous.  Starts the scheduler thread on the current device.  The scheduler spins on
- * one host core while micro-batches are in flight and for 2 ms after its last activity (a
- * timed sleep would round up to the OS timer slack and set the latency floor); idle beyond
- * that it blocks until the next submission.  Everything a micro-batch of up to
+ * one host core while micro-batches are in flight and for idle_spin_us after its last
+ * activity (a timed sleep would round up to the OS timer slack and set the latency floor);
+ * idle beyond that it blocks until the next submission.  Everything a micro-batch of up to
  * min(max_batch, max_slots, 1024) requests needs is allocated here, per slot: device scratch
  * and a pinned host buffer of descriptors that the kernel reads in place, so the scheduler's
  * launches neither allocate nor copy (a larger batch grows its slot's scratch on first use). */

@@ -89,7 +89,7 @@ class ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_uint32),
                 ("n_stream_ids", ctypes.c_uint32), ("n_hip_streams", ctypes.c_uint32),
                 ("max_batch", ctypes.c_uint32), ("mode", ctypes.c_uint32), ("theta_pct", ctypes.c_uint32),
-                ("S", ctypes.c_uint32), ("rmax", ctypes.c_uint32)]
+                ("S", ctypes.c_uint32), ("rmax", ctypes.c_uint32), ("idle_spin_us", ctypes.c_uint32)]
 
 
 class ServerResult(ctypes.Structure):
@@ -529,9 +529,9 @@ class Server:
 
     def __init__(self, hbm_budget_bytes: int = 1 << 30, max_slots: int = 256, n_stream_ids: int = 64,
                  n_hip_streams: int = 4, max_batch: int = 64, mode: int = MODE_AUTO, theta_pct: int = 45,
-                 S: int = 8192, rmax: int = 32):
+                 S: int = 8192, rmax: int = 32, idle_spin_us: int = 0):
         cfg = ServerConfig(int(hbm_budget_bytes), max_slots, n_stream_ids, n_hip_streams, max_batch, mode, theta_pct,
-                           S, rmax)
+                           S, rmax, idle_spin_us)
         self.cfg = cfg
         self._h = ctypes.c_void_p()
         _check(load().hist_server_create(ctypes.byref(self._h), ctypes.byref(cfg)), "hist_server_create")

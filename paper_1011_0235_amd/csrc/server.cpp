@@ -8,7 +8,7 @@
 // slot limit allow, launching each admitted group as one persistent multi-segment kernel.
 // Between rounds it spins (no timed sleep: a sleep of a few microseconds is rounded up to
 // the kernel's timer slack, tens of microseconds, which would set the latency floor) while
-// a batch is in flight and for kIdleSpinNs after the last activity; only then does it block
+// a batch is in flight and for idle_spin_ns after the last activity; only then does it block
 // until a submission wakes it.  Tickets are retired once poll or wait has returned their
 // final state, and finished tickets nobody asks about are dropped oldest first beyond
 // kFinishedCap, so the host memory a server holds stays bounded.
@@ -79,7 +79,7 @@ struct Slot {
 
 constexpr size_t kQueueCap = 1u << 20;      // not-yet-admitted requests
 constexpr size_t kFinishedCap = 1u << 20;   // finished requests kept for poll / wait
-constexpr uint64_t kIdleSpinNs = 2000000;   // the scheduler spins this long after its last activity
+constexpr uint64_t kIdleSpinNs = 20000000;  // default of how long the scheduler spins after its last activity
 constexpr uint64_t kCheckNs = 100000;
 // each slot's scratch is reserved at creation for micro-batches of up to this many requests,
 // with descriptor sets of up to kReserveDescBytes (a larger batch grows it on first use)
@@ -108,6 +108,7 @@ struct hist_server {
   std::atomic<bool> stopping{false};
   // longest host calls of the scheduler (written by it alone, read by hist_server_stats)
   std::atomic<uint64_t> max_launch_ns{0}, max_query_ns{0};
+  uint64_t idle_spin_ns = kIdleSpinNs;
   uint64_t inflight_bytes = 0, inflight_reqs = 0;
   uint32_t busy_slots = 0;
   bool stop = false;
@@ -282,7 +283,7 @@ void hist_server::run() {
     // here without the lock.
     const uint64_t seen = submissions.load(std::memory_order_acquire);
     const bool inflight = busy_slots > 0;
-    if (!inflight && pending.empty() && now_ns() - last_active > kIdleSpinNs) {
+    if (!inflight && pending.empty() && now_ns() - last_active > idle_spin_ns) {
       if (stop) break;
       cv_work.wait(lk, [this] { return stop || !pending.empty(); });
       last_active = now_ns();
@@ -297,7 +298,7 @@ void hist_server::run() {
           break;
         }
       if (done || submissions.load(std::memory_order_acquire) != seen || (stopping.load() && !inflight)) break;
-      if (!inflight && now_ns() - last_active > kIdleSpinNs) break;
+      if (!inflight && now_ns() - last_active > idle_spin_ns) break;
       for (int i = 0; i < 32; ++i) cpu_relax();
     }
     lk.lock();
@@ -314,12 +315,13 @@ hist_status_t hist_server_create(hist_server_t **out, const hist_server_config_t
   if (c.hbm_budget_bytes == 0 || c.max_slots < 1 || c.n_stream_ids < 1 || c.n_stream_ids > 65536 ||
       c.n_hip_streams < 1 || c.n_hip_streams > 16 || c.max_batch < 1 || c.max_batch > 65536 ||
       !mode_ok((hist_mode_t)c.mode) || c.theta_pct > 100 || c.S < 256 || c.S > HIST_S_MAX || !is_pow2(c.rmax) ||
-      c.rmax > HIST_RMAX_MAX)
+      c.rmax > HIST_RMAX_MAX || c.idle_spin_us > 10000000u)
     return HIST_EINVAL;
   DevCtx *d;
   TRY(get_dev(&d));
   hist_server *sv = new hist_server();
   sv->cfg = c;
+  if (c.idle_spin_us) sv->idle_spin_ns = (uint64_t)c.idle_spin_us * 1000u;
   sv->dev = d->dev;
   sv->d = d;
   std::memset(&sv->stats, 0, sizeof(sv->stats));

@@ -133,7 +133,8 @@ def test_stream_and_server_config_errors(hm):
     assert lib.hist_stream_read_alarms(None, None, 0, None) == hm.EINVAL
     for cfg in (hm._lib.ServerConfig(0, 4, 4, 1, 4, 0, 45, 960, 8), hm._lib.ServerConfig(1 << 20, 0, 4, 1, 4, 0, 45, 960, 8),
                 hm._lib.ServerConfig(1 << 20, 4, 4, 17, 4, 0, 45, 960, 8),
-                hm._lib.ServerConfig(1 << 20, 4, 4, 1, 4, 5, 45, 960, 8)):
+                hm._lib.ServerConfig(1 << 20, 4, 4, 1, 4, 5, 45, 960, 8),
+                hm._lib.ServerConfig(1 << 20, 4, 4, 1, 4, 0, 45, 960, 8, 10000001)):
         assert lib.hist_server_create(ctypes.byref(h), ctypes.byref(cfg)) == hm.EINVAL
     for cfg in (hm._lib.IngestConfig(0, 1 << 20), hm._lib.IngestConfig(257, 1 << 20), hm._lib.IngestConfig(4, 0),
                 hm._lib.IngestConfig(4, 1 << 33)):
