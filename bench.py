@@ -568,6 +568,7 @@ def bench_served(hm, G, O, torch, dev, stream, theta, S, rmax, rates=(1000, 1000
                 lat_plain[i] = (time.perf_counter_ns() - due) / 1e3
             row["plain_sync_p50_us"] = round(float(np.percentile(lat_plain, 50)), 1)
             row["plain_sync_p99_us"] = round(float(np.percentile(lat_plain, 99)), 1)
+            row["plain_parity_exact"] = bool(np.array_equal(outs.cpu().numpy().astype(np.int64), exp))
             out["%d_per_s" % rate] = row
         else:
             row["offered"] = "all %d requests of the %d/s set at once" % (len(reqs), rate)
