@@ -109,6 +109,35 @@ def test_budget_and_slots_bound_admission(hm):
     sv.close()
 
 
+def test_scheduler_wakes_after_blocking(hm):
+    # with a 1 us idle spin the scheduler blocks between these requests, so each one is
+    # admitted by a wake-up from submit; results and running histograms stay exact
+    import time
+    pool = torch.randint(0, 256, (4 << 20,), dtype=torch.uint8, device="cuda")
+    host = pool.cpu().numpy()
+    sv = hm.Server(hbm_budget_bytes=64 << 20, max_slots=8, n_stream_ids=2, n_hip_streams=2, max_batch=4,
+                   idle_spin_us=1)
+    outs = torch.zeros((12, 256), dtype=torch.int32, device="cuda")
+    sizes = [1, 4096, 1 << 20, 3 << 20, 17, 65536, 4 << 20, 12345, 0, 2 << 20, 999, 1 << 16]
+    want_acc = [np.zeros(256, dtype=np.int64) for _ in range(2)]
+    for i, n in enumerate(sizes):
+        time.sleep(0.003)           # well beyond the spin: the scheduler is blocked here
+        t = sv.submit(i % 2, pool, d_out=outs[i], n=n)
+        r = sv.wait(t)
+        assert r.status == hm.OK and r.bytes == n
+        want_acc[i % 2] += O.hist(host[:n]).astype(np.int64)
+    torch.cuda.synchronize()
+    got = outs.cpu().numpy().astype(np.int64)
+    for i, n in enumerate(sizes):
+        assert np.array_equal(got[i], O.hist(host[:n]).astype(np.int64)), n
+    for sid in range(2):
+        assert np.array_equal(sv.stream_acc(sid).astype(np.int64), want_acc[sid])
+    sv.close()
+    # the spin's upper bound is enforced
+    with pytest.raises(hm.HistError):
+        hm.Server(n_stream_ids=1, idle_spin_us=10 ** 7 + 1)
+
+
 def test_wait_poll_and_cancel(hm):
     pool = torch.randint(0, 256, (64 << 20,), dtype=torch.uint8, device="cuda")
     sv = hm.Server(hbm_budget_bytes=64 << 20, max_slots=1, n_stream_ids=1, n_hip_streams=1, max_batch=1)
