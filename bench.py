@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+SERVER_HIP_STREAMS = 4   # HIP streams the served bench's micro-batches are spread over
 MIB = 1 << 20
 N_ARENAS = 4
 
@@ -501,7 +502,7 @@ def bench_served(hm, G, O, torch, dev, stream, theta, S, rmax, rates=(1000, 1000
         outs = torch.zeros((len(reqs), 256), dtype=torch.int32, device=dev)
         ptrs = [int(pools[r.stream_id].data_ptr()) + r.offset for r in reqs]
         optr = int(outs.data_ptr())
-        sv = hm.Server(hbm_budget_bytes=1 << 30, max_slots=256, n_stream_ids=n_streams, n_hip_streams=4,
+        sv = hm.Server(hbm_budget_bytes=1 << 30, max_slots=256, n_stream_ids=n_streams, n_hip_streams=SERVER_HIP_STREAMS,
                        max_batch=64, mode=hm.MODE_AUTO, theta_pct=theta, S=S, rmax=rmax)
         subs = []      # (request index, ticket, scheduled arrival ns) of every accepted submission
         refused = 0
